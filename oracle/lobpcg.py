@@ -1,0 +1,200 @@
+"""Block LOBPCG oracle, FP64 (test infrastructure only).
+
+Follows the algorithm of Section 2.2 (steps 1-37) for B = I and no
+constraints Y (steps 2 and 10 are then empty), with soft locking as described
+in Section 2.3: only the active columns J get residuals, preconditioned
+residuals W_J and directions P_J, while all m columns of X take part in every
+Rayleigh-Ritz procedure.
+
+Readings of the paper taken here (each is listed with its reason in the
+design notes of the repository):
+* residual norm: rho_j = ||A x_j - lambda_j x_j||_2 / (||A|| ||x_j||_2), with
+  ||A|| the Gershgorin bound of the operator;
+* "for k = 0, ..., MaxIterations" is read as maxit passes of the loop;
+* a column leaves J when rho_j <= tol and stays out while other columns are
+  active; the loop ends only when every column has rho_j <= tol.  If J
+  empties while a soft-locked column has drifted back above tol (this
+  happens inside degenerate eigenvalue groups, where the condition that makes
+  locked vectors keep improving, Section 2.3, does not hold), those columns
+  are made active again;
+* Cholesky is made scale invariant by an explicit diagonal scaling (the
+  paper requires scale invariance, Section 2.2, and explicit column scaling
+  is the fix it names);
+* if the Cholesky factorisation of P_J^T P_J or the Rayleigh-Ritz problem with
+  P fails, that iteration proceeds without P (a restart); failure without P is
+  an error.
+"""
+import numpy as np
+import scipy.linalg
+
+OK, NOT_CONVERGED = 0, 1
+ERR_CHOL, ERR_RR, ERR_NONFINITE = -4, -5, -6
+
+
+class CholeskyFailure(Exception):
+    pass
+
+
+def chol_scaled(G):
+    """Scale-invariant Cholesky G = R^T R, R upper triangular (Section 2.2).
+
+    With d = sqrt(diag G): G = D Gh D, Gh = R_h^T R_h, and R = R_h D, so the
+    factor of a column-scaled Gram matrix is the column-scaled factor.
+    """
+    G = 0.5 * (G + G.T)
+    d = np.sqrt(np.diag(G)) if np.all(np.diag(G) > 0) else None
+    if d is None or not np.all(np.isfinite(d)):
+        raise CholeskyFailure("non-positive or non-finite diagonal")
+    Gh = G / np.outer(d, d)
+    try:
+        L = np.linalg.cholesky(Gh)
+    except np.linalg.LinAlgError as e:
+        raise CholeskyFailure(str(e))
+    return L.T * d[None, :]
+
+
+def right_solve_upper(V, R):
+    """V R^{-1} for upper-triangular R."""
+    return scipy.linalg.solve_triangular(R, V.T, trans="T", lower=False).T
+
+
+def orthonormalize(V, *others):
+    """Cholesky orthonormalisation: R = chol(V^T V); V R^-1 (and others R^-1)."""
+    R = chol_scaled(V.T @ V)
+    return (right_solve_upper(V, R),) + tuple(right_solve_upper(O, R) for O in others)
+
+
+def rayleigh_ritz(gramA, gramB, m):
+    """Step 24: gramA C = gramB C Theta; the m smallest, C gramB-orthonormal."""
+    theta, C = scipy.linalg.eigh(gramA, gramB)
+    return theta[:m], C[:, :m]
+
+
+class Result:
+    def __init__(self, **kw):
+        self.__dict__.update(kw)
+
+
+def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactivate=True):
+    """Smallest eigenpairs of A x = lambda x (Section 2.1.1, B = I).
+
+    apply_A, apply_T: functions on (N, k) blocks.  X0: (N, m) start block.
+    Returns Result(status, lam, X, hist, iters, resid) where hist[k] holds
+    rho_j of every column at iteration k and resid the explicit final rho_j.
+    """
+    X0 = np.asfortranarray(np.asarray(X0, dtype=np.float64))
+    N, m = X0.shape
+    if not np.all(np.isfinite(X0)):
+        return Result(status=ERR_NONFINITE, lam=None, X=None, hist=np.zeros((0, m)), iters=0, resid=None)
+    T = apply_T if apply_T is not None else (lambda V: V)
+
+    def rho_of(X, AX, lam):
+        Rr = AX - X * lam[None, :]
+        return np.linalg.norm(Rr, axis=0) / (normA * np.linalg.norm(X, axis=0)), Rr
+
+    # step 3: orthonormalise X, then AX = A X
+    try:
+        (X,) = orthonormalize(X0)
+    except CholeskyFailure:
+        return Result(status=ERR_CHOL, lam=None, X=None, hist=np.zeros((0, m)), iters=0, resid=None)
+    AX = apply_A(X)
+    # step 4: initial Ritz vectors from X^T A X
+    H = X.T @ AX
+    lam, Z = np.linalg.eigh(0.5 * (H + H.T))
+    X, AX = X @ Z, AX @ Z
+    # step 5
+    J = np.arange(m)
+    P = AP = None
+    hist, status, k = [], NOT_CONVERGED, 0
+    for k in range(maxit):                                     # step 6
+        rho, Rr = rho_of(X, AX, lam)                           # step 7 (all columns)
+        hist.append(rho)
+        if not np.all(np.isfinite(rho)):
+            status = ERR_NONFINITE
+            break
+        J = J[rho[J] > tol]                                    # step 8
+        if J.size == 0 and reactivate:
+            J = np.flatnonzero(rho > tol)
+        if callback is not None:
+            callback(k, lam, rho, J)
+        if J.size == 0:
+            status = OK
+            break
+        W = T(np.asfortranarray(Rr[:, J]))                     # step 9
+        try:                                                   # step 11
+            (W,) = orthonormalize(W)
+        except CholeskyFailure:
+            status = ERR_CHOL
+            break
+        AW = apply_A(W)                                        # step 12
+        use_p = False
+        if P is not None:                                      # steps 13-16
+            try:
+                PJ, APJ = orthonormalize(P[:, J], AP[:, J])
+                use_p = True
+            except CholeskyFailure:
+                use_p = False
+        C = None
+        for with_p in ([True, False] if use_p else [False]):
+            if with_p:                                         # steps 18-19
+                gramA = np.block([[np.diag(lam), X.T @ AW, X.T @ APJ],
+                                  [AW.T @ X, W.T @ AW, W.T @ APJ],
+                                  [APJ.T @ X, APJ.T @ W, PJ.T @ APJ]])
+                gramB = np.block([[np.eye(m), X.T @ W, X.T @ PJ],
+                                  [W.T @ X, np.eye(J.size), W.T @ PJ],
+                                  [PJ.T @ X, PJ.T @ W, np.eye(J.size)]])
+            else:                                              # steps 21-22
+                gramA = np.block([[np.diag(lam), X.T @ AW], [AW.T @ X, W.T @ AW]])
+                gramB = np.block([[np.eye(m), X.T @ W], [W.T @ X, np.eye(J.size)]])
+            # the lower blocks are the transposes of the upper ones
+            gramA = np.triu(gramA) + np.triu(gramA, 1).T
+            gramB = np.triu(gramB) + np.triu(gramB, 1).T
+            try:
+                theta, C = rayleigh_ritz(gramA, gramB, m)      # step 24
+                use_p = with_p
+                break
+            except np.linalg.LinAlgError:
+                C = None
+        if C is None:
+            status = ERR_RR
+            break
+        j = J.size
+        CX, CW = C[:m], C[m:m + j]
+        if use_p:                                              # steps 26-28
+            CP = C[m + j:]
+            P = W @ CW + PJ @ CP
+            AP = AW @ CW + APJ @ CP
+        else:                                                  # steps 30-32
+            P = W @ CW
+            AP = AW @ CW
+        X = X @ CX + P
+        AX = AX @ CX + AP
+        lam = theta
+    else:
+        k = maxit
+    iters = len(hist)
+    # explicit final residuals with a fresh A X
+    AXt = apply_A(X)
+    resid, _ = rho_of(X, AXt, lam)
+    return Result(status=status, lam=lam, X=X, hist=np.array(hist).reshape(-1, m), iters=iters,
+                  resid=resid, J=J)
+
+
+def laplace7_solver(dims, m, X0, tol, maxit, levels=None, nu_pre=2, nu_post=2, coarse_sweeps=20,
+                    omega=2.0 / 3.0, callback=None):
+    """LOBPCG on the 7-point Laplacian with optional V-cycle preconditioning."""
+    from . import grid, mg
+    A = lambda V: grid.laplace7(dims, V)
+    T = None
+    if levels:
+        T = mg.VCycle(dims, levels, nu_pre, nu_post, coarse_sweeps, omega)
+    return lobpcg(A, X0, tol, maxit, grid.gershgorin_laplace7(), apply_T=T, callback=callback)
+
+
+def varcoef_solver(dims, kx, ky, kz, m, X0, tol, maxit, levels=None, callback=None):
+    """LOBPCG on -div(k grad u), preconditioned by the constant-coefficient V-cycle."""
+    from . import grid, mg
+    A = lambda V: grid.varcoef7(dims, kx, ky, kz, V)
+    T = mg.VCycle(dims, levels) if levels else None
+    return lobpcg(A, X0, tol, maxit, grid.gershgorin_varcoef7(dims, kx, ky, kz), apply_T=T,
+                  callback=callback)
