@@ -1,0 +1,185 @@
+"""Benchmark: LOBPCG time-to-residual on the 256^3 Laplacian, mixed vs FP64.
+
+One "step" is one complete solve for the m=32 smallest eigenpairs of the
+7-point Dirichlet Laplacian on a 256^3 grid (16,777,216 unknowns) with the
+multigrid V(2,2) preconditioner (6 levels), from the seeded uniform[-1,1]
+start block, to an explicit FP64 residual ||Ax - lambda x|| / (||A|| ||x||)
+<= 1e-8 for every pair.  The headline value is the mixed-precision solve
+time (FP32 iterations, FP64 refinement); the plain FP64 solve is timed beside
+it.  The start block is resident in HBM before the timed region starts.
+
+Also reported:
+  roofline      the 7-point block stencil (the "SpMM" of the metric) on the
+                N x 32 FP32 block, timed with HIP events on the library's
+                stream: algorithmic bytes 2*N*m*4 per launch / average launch
+                time, against 8 TB/s
+  cpu_baseline  the FP64 CPU oracle on the host's cores: its setup plus one
+                LOBPCG iteration at the same size, extrapolated to the
+                iteration count of the FP64 GPU solve
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-residual 1e-8, 256^3 Laplacian m=32, FP64 vs mixed; SpMM HBM GB/s"
+HBM_PEAK_GBPS = 8000.0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--m", type=int, default=32)
+    ap.add_argument("--levels", type=int, default=6)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--maxit", type=int, default=300)
+    ap.add_argument("--spmm-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--profile-steps", action="store_true", help="one extra solve with per-step HIP-event timing")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see the design notes on how "
+              "the solver would shard); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_0705_2626_amd as L
+    import synth
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    n, m, levels, tol = args.n, args.m, args.levels, args.tol
+    dims = (n, n, n)
+    N = n ** 3
+    X0 = torch.from_numpy(synth.x0_uniform(N, m, seed=2)).to(dev)
+    A, T = L.Op(*dims), L.Precond(levels)
+    from oracle import closed_form  # closed form of the spectrum, used only to report accuracy
+    exact, _ = closed_form.smallest(*dims, m)
+
+    def run(prec, K, W):
+        ctx = L.lobpcg_setup(A, T, m, prec, device=dev)
+        res = None
+        for _ in range(W):
+            res = L.lobpcg_solve(ctx, X0, tol, args.maxit)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        results = []
+        for _ in range(K):
+            results.append(L.lobpcg_solve(ctx, X0, tol, args.maxit, hist=False))
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / K
+        stats = L.lobpcg_get_stats(ctx)
+        steps = None
+        if args.profile_steps:
+            L.lobpcg_set_option(ctx, L.OPT_PROFILE, 1)
+            L.lobpcg_solve(ctx, X0, tol, args.maxit, hist=False)
+            steps = L.lobpcg_get_stats(ctx)["step_ms"]
+        for r in results:
+            assert r.status == L.OK, L.status_string(r.status)
+        r = results[-1]
+        acc = {"max_rel_err_closed_form": float(np.max(np.abs(r.lam / exact - 1))),
+               "max_resid": float(r.resid.max()), "iters": r.iters,
+               "iters_fp32": stats["iters_fp32"], "iters_fp64": stats["iters_fp64"]}
+        del ctx
+        torch.cuda.empty_cache()
+        return dt, acc, steps, r
+
+    t_mixed, acc_mixed, steps_mixed, r_mixed = run(L.MIXED, args.steps, args.warmup)
+    fp64 = None
+    if not args.no_fp64:
+        t64, acc64, steps64, r64 = run(L.FP64, args.steps, args.warmup)
+        fp64 = {"value": t64, "unit": "s", "ms_per_step": 1e3 * t64, **acc64}
+        if steps64:
+            fp64["steps_ms"] = steps64
+        lam_agree = float(np.max(np.abs(r_mixed.lam / r64.lam - 1)))
+    else:
+        lam_agree = None
+
+    # ---- stencil SpMM on the N x m FP32 block, HIP events on the library's stream
+    ctx = L.lobpcg_setup(A, L.Precond(None), m, L.MIXED, device=dev)
+    U = X0.float()
+    V = torch.empty_like(U)
+    lib = L.lib()
+    import ctypes
+    opc = A.c()
+    for _ in range(3):
+        lib.lobpcg_apply_A(ctx.h, ctypes.byref(opc), L.F32, ctypes.c_void_p(U.data_ptr()),
+                           ctypes.c_void_p(V.data_ptr()), m)
+    st = ctx.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(args.spmm_reps):
+        s = lib.lobpcg_apply_A(ctx.h, ctypes.byref(opc), L.F32, ctypes.c_void_p(U.data_ptr()),
+                               ctypes.c_void_p(V.data_ptr()), m)
+        assert s == 0
+    e1.record(st)
+    e1.synchronize()
+    spmm_ms = e0.elapsed_time(e1) / args.spmm_reps
+    spmm_bytes = 2.0 * N * m * 4
+    spmm_gbps = spmm_bytes / (spmm_ms * 1e-3) / 1e9
+    del ctx, U, V
+    torch.cuda.empty_cache()
+
+    out = {
+        "metric": METRIC, "value": t_mixed, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * t_mixed, "higher_is_better": False, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "7-point Dirichlet Laplacian %d^3 (N=%d), m=%d smallest eigenpairs, "
+                               "GMG V(2,2) %d levels, tol %g after FP64 refinement, X0 uniform[-1,1] seed 2"
+                               % (n, N, m, levels, tol),
+                   "n": n, "N": N, "m": m, "levels": levels, "tol": tol},
+        "mixed": {"value": t_mixed, "unit": "s", **acc_mixed},
+        "fp64": fp64,
+        "speedup_mixed_vs_fp64": (fp64["value"] / t_mixed) if fp64 else None,
+        "mixed_vs_fp64_max_rel_lambda_diff": lam_agree,
+        "spmm": {"GBps": spmm_gbps, "dtype": "f32", "block": [N, m], "ms": spmm_ms},
+        "roofline": {"bound": "hbm", "achieved": spmm_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": spmm_gbps / HBM_PEAK_GBPS, "traffic": None, "kernel": "stencil7 f32 N x 32"},
+    }
+    if steps_mixed:
+        out["mixed"]["steps_ms"] = steps_mixed
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(dims, m, levels, X0.cpu().numpy(),
+                                           fp64["iters"] if fp64 else acc_mixed["iters"])
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(dims, m, levels, X0, iters):
+    """The FP64 oracle at the benchmark size: setup (steps 3-4) plus one loop
+    iteration, timed, and extrapolated to `iters` iterations."""
+    from oracle import lobpcg as olob
+
+    marks = []
+    t0 = time.perf_counter()
+
+    def cb(k, lam, rho, J):
+        marks.append(time.perf_counter())
+
+    olob.laplace7_solver(dims, m, X0, 1e-300, 1, levels=levels, callback=cb)
+    t_end = time.perf_counter()
+    # the callback fires after the first residual: before it lie steps 3-4,
+    # after it one loop iteration and the final explicit residual
+    t_setup = marks[0] - t0
+    t_iter = t_end - marks[0]
+    est = t_setup + iters * t_iter
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": est, "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": "FP64 oracle at the same size (n=%d, m=%d): setup + 1 iteration (with the final explicit "
+                      "residual) timed (%.1f s + %.1f s), extrapolated to %d iterations" % (dims[0], m, t_setup, t_iter, iters)}
+
+
+if __name__ == "__main__":
+    main()

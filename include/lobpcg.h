@@ -1,0 +1,210 @@
+/*
+ * lobpcg.h -- C ABI of liblobpcg.so, block LOBPCG for the 7-point 3-D
+ * Laplacian (and -div(k grad u)) on one AMD MI355X (gfx950).
+ *
+ * Method: Knyazev, Argentati, Lashuk, Ovtchinnikov, "Block Locally Optimal
+ * Preconditioned Eigenvalue Xolvers (BLOPEX) in hypre and PETSc".  The solver
+ * computes the m smallest eigenpairs of A x = lambda B x (Section 2.1.1) with
+ * the algorithm of Section 2.2 and soft locking (Section 2.3).  A, B and the
+ * preconditioner T are matrix-free (Section 2.2 and Appendix A): here they are
+ * described by small descriptors and applied by the library's own kernels.
+ *
+ * Conventions shared by every entry point
+ *  - Grid point (x, y, z) of an nx x ny x nz grid is p = x + nx*(y + ny*z).
+ *  - A block of k grid vectors is an N x k array stored point-major: element
+ *    (p, j) at offset p*k + j (a C-contiguous (N, k) tensor).  Device blocks
+ *    must be 16-byte aligned.
+ *  - "d_" pointers are device memory, "h_" pointers host memory.  The caller
+ *    owns all memory; the library never allocates or frees device memory
+ *    (it carves the caller's workspace) and only allocates small host and
+ *    pinned-host buffers inside its context.
+ *  - All kernels run on the stream given to lobpcg_setup.  Every entry point
+ *    that returns host results synchronises that stream before returning.
+ *  - Errors are returned as a status code (below); nothing is thrown across
+ *    the ABI.  On an error the outputs are unspecified unless stated.
+ *  - Calls on one context must not overlap (a context is not thread-safe).
+ */
+#ifndef LOBPCG_H
+#define LOBPCG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status codes */
+enum {
+    LOBPCG_OK = 0,              /* converged: every residual norm <= tol            */
+    LOBPCG_NOT_CONVERGED = 1,   /* maxit reached; outputs hold the last iterate     */
+    LOBPCG_ERR_ARG = -1,        /* bad dimension, pointer, tolerance or mismatch    */
+    LOBPCG_ERR_UNSUPPORTED = -2,/* B other than the identity                        */
+    LOBPCG_ERR_WORKSPACE = -3,  /* workspace too small or misaligned               */
+    LOBPCG_ERR_CHOL = -4,       /* Cholesky of X0^T X0 or W^T W failed (steps 3, 11)*/
+    LOBPCG_ERR_RR = -5,         /* Rayleigh-Ritz failed even without P (step 24)    */
+    LOBPCG_ERR_NONFINITE = -6,  /* NaN or Inf in the input or the iteration         */
+    LOBPCG_ERR_HIP = -7         /* a HIP runtime call failed                        */
+};
+
+/* ---------------------------------------------------------------- descriptors */
+enum { LOBPCG_OP_LAPLACE7 = 0, LOBPCG_OP_VARCOEF7 = 1 };
+enum { LOBPCG_PC_NONE = 0, LOBPCG_PC_GMG_V = 1 };
+enum { LOBPCG_FP64 = 0, LOBPCG_MIXED = 1 };     /* solver precision           */
+enum { LOBPCG_F64 = 0, LOBPCG_F32 = 1 };        /* element type of one block  */
+
+/* Operator A (or B).  LAPLACE7: the 7-point finite-difference Laplacian with
+ * homogeneous Dirichlet boundary, diagonal 6 and off-diagonals -1 (Section 4).
+ * VARCOEF7: -div(k grad u) with one coefficient per cell face,
+ *   (A u)_p = sum over the six faces f of p of k_f (u_p - u_q),
+ * q the neighbour across f (u_q = 0 beyond the boundary).  Face arrays are
+ * device FP64, C order: kx (nz, ny, nx+1), ky (nz, ny+1, nx), kz (nz+1, ny, nx);
+ * face i along an axis lies between grid indices i-1 and i. */
+typedef struct lobpcg_op {
+    int nx, ny, nz;
+    int kind;
+    const double *kx, *ky, *kz;     /* VARCOEF7 only, else NULL */
+} lobpcg_op;
+
+/* Preconditioner T (Section 2.1.1 requires it linear, symmetric, positive
+ * definite).  GMG_V: a geometric-multigrid V(nu_pre, nu_post) cycle on the
+ * constant-coefficient 7-point operator: level l has floor(n/2^l) points per
+ * axis (coarse node I on fine node 2I+1), level operator 4^-l L7, weighted
+ * Jacobi smoothing with weight omega, full-weighting restriction P^T/8,
+ * trilinear prolongation P, and coarse_sweeps Jacobi sweeps from zero on the
+ * coarsest level.  nu_pre must equal nu_post (symmetry). */
+typedef struct lobpcg_precond {
+    int kind;
+    int levels;
+    int nu_pre, nu_post, coarse_sweeps;
+    double omega;
+} lobpcg_precond;
+
+typedef struct lobpcg_ctx lobpcg_ctx;   /* opaque */
+
+/* ---------------------------------------------------------------- solver */
+
+/* Device workspace needed by lobpcg_setup for this problem, in bytes.
+ * B must be NULL (B = I).  m: block size, 1 <= m and 3m <= N.  Pure host
+ * code: callable without a GPU. */
+int lobpcg_workspace_bytes(const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T,
+                           int m, int precision, size_t *bytes);
+
+/* Create a context.  d_workspace: caller-owned device memory of at least
+ * lobpcg_workspace_bytes bytes, 256-byte aligned, kept alive until
+ * lobpcg_destroy.  stream: a hipStream_t (NULL = the default stream). */
+int lobpcg_setup(lobpcg_ctx **ctx, const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T,
+                 int m, int precision, void *d_workspace, size_t ws_bytes, void *stream);
+
+/* Solve for the m smallest eigenpairs (Section 2.2, steps 1-37, B = I, no
+ * constraints).  A must have the dimensions and kind given to setup (its
+ * face arrays may differ between calls); T must equal setup's.
+ *   d_X0         N x m FP64 start block (linearly independent columns)
+ *   tol          stop when every rho_j = ||A x_j - lambda_j x_j|| / (||A|| ||x_j||)
+ *                is <= tol; ||A|| is the operator's infinity norm
+ *   maxit        number of passes through the main loop
+ *   h_lambda     [m] out: Ritz values, ascending
+ *   d_X          N x m FP64 out: Ritz vectors, orthonormal
+ *   h_hist       [maxit x m] out or NULL: rho_j of every column per iteration
+ *   h_iters      out: iterations performed (rows of h_hist written)
+ *   h_final_resid [m] out or NULL: rho_j recomputed with an explicit A X
+ * precision MIXED: FP32 iterations until the residuals stop falling or reach
+ * the switch tolerance, then FP64 iterations (FP32 preconditioner) to tol. */
+int lobpcg_solve(lobpcg_ctx *ctx, const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T,
+                 const double *d_X0, int m, double tol, int maxit, double *h_lambda, double *d_X,
+                 double *h_hist, int *h_iters, double *h_final_resid);
+
+/* Hellmann-Feynman eigenvalue adjoint for VARCOEF7: for
+ * lambda_i = (x_i, A x_i) / (x_i, x_i) and A = sum_f k_f (e_p - e_q)(e_p - e_q)^T,
+ * d lambda_i / d k_f = (x_i[p] - x_i[q])^2 / (x_i, x_i).  Writes the
+ * vector-Jacobian product g_f = sum_i h_gbar[i] d lambda_i / d k_f into the
+ * three device FP64 face arrays (shapes as in lobpcg_op).  d_X: N x m FP64. */
+int lobpcg_eig_grad_k(lobpcg_ctx *ctx, const double *d_X, const double *h_gbar, int m,
+                      double *d_gkx, double *d_gky, double *d_gkz);
+
+void lobpcg_destroy(lobpcg_ctx *ctx);
+const char *lobpcg_status_string(int status);
+
+/* ---------------------------------------------------------------- options and statistics */
+enum {
+    LOBPCG_OPT_SWITCH_TOL = 0,      /* MIXED: FP32 phase ends at max rho <= this (default 1e-5) */
+    LOBPCG_OPT_STALL_WINDOW = 1,    /* MIXED: ... or when max rho fell by less than      */
+    LOBPCG_OPT_STALL_FACTOR = 2,    /*        STALL_FACTOR over STALL_WINDOW iterations  */
+    LOBPCG_OPT_PROFILE = 3,         /* 1: time each step class with HIP events          */
+    LOBPCG_OPT_REACTIVATE = 4       /* 1 (default): see lobpcg_solve's stopping rule    */
+};
+int lobpcg_set_option(lobpcg_ctx *ctx, int key, double value);
+
+enum {
+    LOBPCG_STEP_RESIDUAL = 0,   /* step 7 and the norms of step 8          */
+    LOBPCG_STEP_PRECOND = 1,    /* step 9                                  */
+    LOBPCG_STEP_ORTHO = 2,      /* steps 3, 11, 14-15 (Gram, Cholesky, apply)*/
+    LOBPCG_STEP_APPLY_A = 3,    /* step 12 and explicit A X                */
+    LOBPCG_STEP_GRAM = 4,       /* steps 17-23                             */
+    LOBPCG_STEP_RR = 5,         /* step 24 (host FP64)                     */
+    LOBPCG_STEP_UPDATE = 6,     /* steps 25-33                             */
+    LOBPCG_STEP_OTHER = 7,      /* precision casts, phase switch, copies   */
+    LOBPCG_NSTEP = 8
+};
+typedef struct lobpcg_stats {
+    int iters_total, iters_fp32, iters_fp64;
+    int restarts;               /* iterations run without P after a failure */
+    int status;
+    double solve_ms;            /* host wall time of the last lobpcg_solve  */
+    double step_ms[LOBPCG_NSTEP];   /* summed HIP-event times (OPT_PROFILE)  */
+    int step_calls[LOBPCG_NSTEP];
+} lobpcg_stats;
+int lobpcg_get_stats(const lobpcg_ctx *ctx, lobpcg_stats *stats);
+
+/* ---------------------------------------------------------------- the steps one by one
+ * The solver's building blocks, exposed for testing and timing.  They use
+ * the context's workspace as scratch (so they may overwrite solver state)
+ * and its dimensions: N = nx*ny*nz of setup's operator, k <= m unless said.
+ * dtype selects FP64 or FP32 elements; FP32 requires a MIXED context. */
+
+/* d_out = A d_in for an N x k block (the block product of step 12). */
+int lobpcg_apply_A(lobpcg_ctx *ctx, const lobpcg_op *A, int dtype, const void *d_in, void *d_out, int k);
+
+/* d_out = T d_in for an N x k block (step 9); T is setup's preconditioner. */
+int lobpcg_apply_T(lobpcg_ctx *ctx, int dtype, const void *d_in, void *d_out, int k);
+
+/* Gram products of steps 17-23 for S = [S_0 .. S_{n-1}] and AS = [AS_0 ..],
+ * n <= 3 blocks of widths w_i (sum K <= 3m), all N x w_i of type dtype:
+ * h_SS = S^T S and h_SAS = S^T AS, K x K row-major FP64 on the host, upper
+ * triangle (entries (a, b), a <= b) computed, the strict lower triangle
+ * mirrored from it.  Accumulation is FP64 across row chunks. */
+int lobpcg_gram(lobpcg_ctx *ctx, int dtype, int n, const void *const *d_S, const void *const *d_AS,
+                const int *w, double *h_SS, double *h_SAS);
+
+/* Multivector combination used by steps 3-4, 11, 14-15 and 25-33:
+ * d_out (N x kout) = sum_i in_i[:, cols_i] C_i (+ d_add if not NULL), with
+ * n <= 3 inputs of widths ld_i, column selections cols_i[0..k_i-1] (NULL =
+ * all ld_i columns, k_i = ld_i) and h_C the stacked (sum k_i) x kout
+ * row-major FP64 coefficients.  d_out must not alias an input. */
+int lobpcg_combine(lobpcg_ctx *ctx, int dtype, int n, const void *const *d_in, const int *ld,
+                   const int *const *cols, const int *k, const double *h_C, int kout,
+                   const void *d_add, void *d_out);
+
+/* Step 7 and the norms of step 8: for the m columns of d_X, d_AX (N x m)
+ * and Ritz values h_lambda, writes W_J = AX_J - X_J Lambda_J packed as
+ * N x nJ (column jj = column h_J[jj]) and h_rho[j] = ||AX_j - lambda_j X_j|| /
+ * (norm_A ||X_j||) for all j. */
+int lobpcg_residual(lobpcg_ctx *ctx, int dtype, const void *d_X, const void *d_AX, int m,
+                    const double *h_lambda, const int *h_J, int nJ, double norm_A, void *d_W,
+                    double *h_rho);
+
+/* Host FP64 dense kernels (no GPU needed). */
+/* Scale-invariant Cholesky G = R^T R (Section 2.2: the factorisation must be
+ * invariant under column scaling): R = Rh D, D = diag(G)^(1/2), Rh^T Rh =
+ * D^-1 G D^-1.  G, R: n x n row-major; R upper triangular.  Returns
+ * LOBPCG_ERR_CHOL if G is not numerically positive definite. */
+int lobpcg_dense_chol(int n, const double *G, double *R);
+/* Step 24: the m smallest eigenpairs of gramA C = gramB C Theta (n x n,
+ * row-major, symmetric, gramB positive definite), ascending, with
+ * C^T gramB C = I.  C: n x m row-major.  LOBPCG_ERR_RR if gramB is not
+ * positive definite or the eigensolver fails. */
+int lobpcg_dense_rr(int n, int m, const double *gramA, const double *gramB, double *theta, double *C);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LOBPCG_H */

@@ -133,3 +133,21 @@ def gershgorin_varcoef7(dims, kx, ky, kz):
     off[1:] += kz[1:-1]
     off[:-1] += kz[1:-1]
     return float((diag + off).max())
+
+
+def laplace7_rows(dims, U, points):
+    """(A U)[p, :] for the listed grid points only (for sampled checks of
+    blocks too large to apply the whole operator to).  U: (N, k), any order."""
+    nx, ny, nz = dims
+    U = np.asarray(U)
+    out = np.empty((len(points), U.shape[1]))
+    for r, p in enumerate(points):
+        p = int(p)
+        x, y, z = p % nx, (p // nx) % ny, p // (nx * ny)
+        s = 6.0 * U[p].astype(np.float64)
+        for dx, dy, dz in ((-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)):
+            a, b, c = x + dx, y + dy, z + dz
+            if 0 <= a < nx and 0 <= b < ny and 0 <= c < nz:
+                s = s - U[a + nx * (b + ny * c)].astype(np.float64)
+        out[r] = s
+    return out

@@ -1,0 +1,240 @@
+// Block stencil products on point-major N x k blocks (gfx950).
+//
+// A u for the 7-point Laplacian (Section 4) and for -div(k grad u), applied to
+// all k columns of a block at once (the block product A*W of step 12).  The
+// same kernel, with a different epilogue, gives the multigrid smoother and
+// residual (weighted Jacobi on the level operator s*L7, s = 4^-l).
+//
+// Mapping: one thread owns V consecutive columns of one (x, y) grid column and
+// marches in z, so the z-1 / z / z+1 values stay in registers and every
+// element is fetched from HBM once; the four in-plane neighbours are the
+// centre values of the adjacent threads of the same or a nearby workgroup,
+// fetched through L1/L2.  Workgroups are remapped so that each XCD owns a
+// contiguous range of (x, y) tiles.
+#include "common.h"
+#include "kernels.h"
+
+namespace lobpcg {
+
+enum { EPI_APPLY = 0, EPI_JACOBI = 1, EPI_RESID = 2 };
+
+template <typename T, int V>
+__device__ __forceinline__ vec<T, V> lap(const vec<T, V> &c, const vec<T, V> &zm, const vec<T, V> &zp,
+                                         const vec<T, V> &xm, const vec<T, V> &xp, const vec<T, V> &ym,
+                                         const vec<T, V> &yp)
+{
+    vec<T, V> r;
+#pragma unroll
+    for (int i = 0; i < V; i++)
+        r.v[i] = T(6) * c.v[i] - zm.v[i] - zp.v[i] - xm.v[i] - xp.v[i] - ym.v[i] - yp.v[i];
+    return r;
+}
+
+// EPI_APPLY : out = s * L7 u
+// EPI_JACOBI: out = u + c1 * (b - s * L7 u)
+// EPI_RESID : out = b - s * L7 u
+template <typename T, int V, int EPI>
+__global__ void __launch_bounds__(256) stencil7_kernel(int nx, int ny, int nz, int L, int zchunk,
+                                                       const T *__restrict__ u, T *__restrict__ out,
+                                                       const T *__restrict__ b, T s, T c1)
+{
+    const unsigned nbx = gridDim.x;
+    const unsigned bx = xcd_remap(blockIdx.x, nbx);
+    const i64 plane = (i64)nx * ny * L;   // threads per z-plane
+    const i64 t = (i64)bx * blockDim.x + threadIdx.x;
+    if (t >= plane) return;
+    const int c = (int)(t % L);
+    const i64 pxy = t / L;
+    const int x = (int)(pxy % nx);
+    const int y = (int)(pxy / nx);
+    const int z0 = blockIdx.y * zchunk;
+    const int z1 = min(nz, z0 + zchunk);
+    const i64 sx = (i64)L * V, sy = (i64)nx * L * V, sz = (i64)nx * ny * L * V;   // element strides
+    const i64 base = (pxy * L + c) * V;
+    const vec<T, V> zero = vzero<T, V>();
+    vec<T, V> prev = z0 > 0 ? vload<T, V>(u + base + (z0 - 1) * sz) : zero;
+    vec<T, V> cur = vload<T, V>(u + base + z0 * sz);
+    for (int z = z0; z < z1; z++) {
+        const i64 i = base + z * sz;
+        vec<T, V> next = (z + 1 < nz) ? vload<T, V>(u + i + sz) : zero;
+        vec<T, V> xm = x > 0 ? vload<T, V>(u + i - sx) : zero;
+        vec<T, V> xp = x + 1 < nx ? vload<T, V>(u + i + sx) : zero;
+        vec<T, V> ym = y > 0 ? vload<T, V>(u + i - sy) : zero;
+        vec<T, V> yp = y + 1 < ny ? vload<T, V>(u + i + sy) : zero;
+        vec<T, V> au = lap<T, V>(cur, prev, next, xm, xp, ym, yp);
+        vec<T, V> o;
+        if (EPI == EPI_APPLY) {
+#pragma unroll
+            for (int q = 0; q < V; q++) o.v[q] = s * au.v[q];
+        } else {
+            vec<T, V> bb = vload<T, V>(b + i);
+#pragma unroll
+            for (int q = 0; q < V; q++) {
+                T r = bb.v[q] - s * au.v[q];
+                o.v[q] = (EPI == EPI_JACOBI) ? cur.v[q] + c1 * r : r;
+            }
+        }
+        vstore<T, V>(out + i, o);
+        prev = cur;
+        cur = next;
+    }
+}
+
+// Variable-coefficient operator: (A u)_p = sum_f k_f (u_p - u_q), face arrays
+// kx (nz, ny, nx+1), ky (nz, ny+1, nx), kz (nz+1, ny, nx).
+template <typename T, int V>
+__global__ void __launch_bounds__(256) varcoef7_kernel(int nx, int ny, int nz, int L, int zchunk,
+                                                       const double *__restrict__ kx,
+                                                       const double *__restrict__ ky,
+                                                       const double *__restrict__ kz,
+                                                       const T *__restrict__ u, T *__restrict__ out)
+{
+    const unsigned bx = xcd_remap(blockIdx.x, gridDim.x);
+    const i64 plane = (i64)nx * ny * L;
+    const i64 t = (i64)bx * blockDim.x + threadIdx.x;
+    if (t >= plane) return;
+    const int c = (int)(t % L);
+    const i64 pxy = t / L;
+    const int x = (int)(pxy % nx);
+    const int y = (int)(pxy / nx);
+    const int z0 = blockIdx.y * zchunk;
+    const int z1 = min(nz, z0 + zchunk);
+    const i64 sx = (i64)L * V, sy = (i64)nx * L * V, sz = (i64)nx * ny * L * V;
+    const i64 base = (pxy * L + c) * V;
+    const vec<T, V> zero = vzero<T, V>();
+    vec<T, V> prev = z0 > 0 ? vload<T, V>(u + base + (z0 - 1) * sz) : zero;
+    vec<T, V> cur = vload<T, V>(u + base + z0 * sz);
+    for (int z = z0; z < z1; z++) {
+        const i64 i = base + z * sz;
+        vec<T, V> next = (z + 1 < nz) ? vload<T, V>(u + i + sz) : zero;
+        vec<T, V> xm = x > 0 ? vload<T, V>(u + i - sx) : zero;
+        vec<T, V> xp = x + 1 < nx ? vload<T, V>(u + i + sx) : zero;
+        vec<T, V> ym = y > 0 ? vload<T, V>(u + i - sy) : zero;
+        vec<T, V> yp = y + 1 < ny ? vload<T, V>(u + i + sy) : zero;
+        const i64 fxi = ((i64)z * ny + y) * (nx + 1) + x;
+        const i64 fyi = ((i64)z * (ny + 1) + y) * nx + x;
+        const i64 fzi = ((i64)z * ny + y) * nx + x;
+        const T kxm = (T)kx[fxi], kxp = (T)kx[fxi + 1];
+        const T kym = (T)ky[fyi], kyp = (T)ky[fyi + nx];
+        const T kzm = (T)kz[fzi], kzp = (T)kz[fzi + (i64)nx * ny];
+        vec<T, V> o;
+#pragma unroll
+        for (int q = 0; q < V; q++) {
+            T up = cur.v[q];
+            o.v[q] = kxm * (up - xm.v[q]) + kxp * (up - xp.v[q]) + kym * (up - ym.v[q]) +
+                     kyp * (up - yp.v[q]) + kzm * (up - prev.v[q]) + kzp * (up - next.v[q]);
+        }
+        vstore<T, V>(out + i, o);
+        prev = cur;
+        cur = next;
+    }
+}
+
+// Launch geometry: 256 threads over the (x, y, column-chunk) plane, z split
+// into chunks only when the plane alone gives too few workgroups.
+static void geometry(int nx, int ny, int nz, int L, dim3 &grid, int &zchunk)
+{
+    const i64 plane = (i64)nx * ny * L;
+    const unsigned pb = (unsigned)((plane + 255) / 256);
+    int zc = (int)((2048 + pb - 1) / pb);
+    if (zc < 1) zc = 1;
+    if (zc > nz) zc = nz;
+    zchunk = (nz + zc - 1) / zc;
+    grid = dim3(pb, (nz + zchunk - 1) / zchunk, 1);
+}
+
+template <typename T>
+static int pick_vec(int k)
+{
+    const int maxv = 16 / (int)sizeof(T);
+    for (int v = maxv; v > 1; v >>= 1)
+        if (k % v == 0) return v;
+    return 1;
+}
+
+template <typename T, int V, int EPI>
+static hipError_t run_stencil(const Grid3 &g, int k, const void *u, void *out, const void *b, double s, double c1,
+                              hipStream_t st)
+{
+    const int L = k / V;
+    dim3 grid;
+    int zchunk;
+    geometry(g.nx, g.ny, g.nz, L, grid, zchunk);
+    hipLaunchKernelGGL((stencil7_kernel<T, V, EPI>), grid, dim3(256), 0, st, g.nx, g.ny, g.nz, L, zchunk,
+                       (const T *)u, (T *)out, (const T *)b, (T)s, (T)c1);
+    return hipGetLastError();
+}
+
+template <typename T, int EPI>
+static hipError_t dispatch_vec(const Grid3 &g, int k, const void *u, void *out, const void *b, double s,
+                               double c1, hipStream_t st)
+{
+    switch (pick_vec<T>(k)) {
+    case 4: return run_stencil<T, 4, EPI>(g, k, u, out, b, s, c1, st);
+    case 2: return run_stencil<T, 2, EPI>(g, k, u, out, b, s, c1, st);
+    default: return run_stencil<T, 1, EPI>(g, k, u, out, b, s, c1, st);
+    }
+}
+
+template <typename T>
+static hipError_t dispatch_epi(int epi, const Grid3 &g, int k, const void *u, void *out, const void *b,
+                               double s, double c1, hipStream_t st)
+{
+    switch (epi) {
+    case EPI_APPLY: return dispatch_vec<T, EPI_APPLY>(g, k, u, out, b, s, c1, st);
+    case EPI_JACOBI: return dispatch_vec<T, EPI_JACOBI>(g, k, u, out, b, s, c1, st);
+    default: return dispatch_vec<T, EPI_RESID>(g, k, u, out, b, s, c1, st);
+    }
+}
+
+hipError_t launch_laplace7(int dtype, const Grid3 &g, int k, const void *u, void *out, double s, hipStream_t st)
+{
+    if (dtype == DT_F32) return dispatch_epi<float>(EPI_APPLY, g, k, u, out, nullptr, s, 0.0, st);
+    return dispatch_epi<double>(EPI_APPLY, g, k, u, out, nullptr, s, 0.0, st);
+}
+
+hipError_t launch_jacobi(int dtype, const Grid3 &g, int k, const void *x, const void *b, void *out, double s,
+                         double omega, hipStream_t st)
+{
+    const double c1 = omega / (6.0 * s);
+    if (dtype == DT_F32) return dispatch_epi<float>(EPI_JACOBI, g, k, x, out, b, s, c1, st);
+    return dispatch_epi<double>(EPI_JACOBI, g, k, x, out, b, s, c1, st);
+}
+
+hipError_t launch_resid7(int dtype, const Grid3 &g, int k, const void *x, const void *b, void *out, double s,
+                         hipStream_t st)
+{
+    if (dtype == DT_F32) return dispatch_epi<float>(EPI_RESID, g, k, x, out, b, s, 0.0, st);
+    return dispatch_epi<double>(EPI_RESID, g, k, x, out, b, s, 0.0, st);
+}
+
+template <typename T, int V>
+static hipError_t run_varcoef(const Grid3 &g, int k, const double *kx, const double *ky, const double *kz,
+                              const void *u, void *out, hipStream_t st)
+{
+    const int L = k / V;
+    dim3 grid;
+    int zchunk;
+    geometry(g.nx, g.ny, g.nz, L, grid, zchunk);
+    hipLaunchKernelGGL((varcoef7_kernel<T, V>), grid, dim3(256), 0, st, g.nx, g.ny, g.nz, L, zchunk, kx, ky, kz,
+                       (const T *)u, (T *)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_varcoef7(int dtype, const Grid3 &g, int k, const double *kx, const double *ky,
+                           const double *kz, const void *u, void *out, hipStream_t st)
+{
+    if (dtype == DT_F32) {
+        switch (pick_vec<float>(k)) {
+        case 4: return run_varcoef<float, 4>(g, k, kx, ky, kz, u, out, st);
+        case 2: return run_varcoef<float, 2>(g, k, kx, ky, kz, u, out, st);
+        default: return run_varcoef<float, 1>(g, k, kx, ky, kz, u, out, st);
+        }
+    }
+    switch (pick_vec<double>(k)) {
+    case 2: return run_varcoef<double, 2>(g, k, kx, ky, kz, u, out, st);
+    default: return run_varcoef<double, 1>(g, k, kx, ky, kz, u, out, st);
+    }
+}
+
+}  // namespace lobpcg

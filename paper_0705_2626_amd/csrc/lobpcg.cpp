@@ -1,0 +1,1086 @@
+// liblobpcg.so: block LOBPCG (Section 2.2, steps 1-37, B = I, no constraints)
+// with soft locking (Section 2.3) on one MI355X.  The host drives the
+// iteration; every N-sized operation runs in the library's HIP kernels and
+// only the small (<= 3m x 3m) FP64 matrices come back to the host for the
+// Cholesky factorisations and the Rayleigh-Ritz eigenproblem, as in the
+// paper's implementation (which calls LAPACK for them, Section 3).
+#include "../../include/lobpcg.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "dense.h"
+#include "kernels.h"
+
+using namespace lobpcg;
+
+namespace {
+
+const size_t ALIGN = 256;
+// The Gram kernel keeps 3m-column row chunks and the combine kernel its
+// (3m x m) coefficients in LDS; this bounds m.
+const int LOBPCG_MAX_M = 32;
+const int COEF_SLOTS = 16;
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+size_t esize(int dt) { return dt == DT_F32 ? 4 : 8; }
+
+// The eleven N x m blocks of one precision (steps 1-33 store 6m vectors for
+// B = I; the extra ones are ping-pong and packed-active copies).
+struct Blocks {
+    void *X[2], *AX[2];   // current / next Ritz vectors and A X
+    void *W, *AW;         // preconditioned residuals (packed |J| columns) and A W
+    void *P, *AP;         // directions of all m columns, as produced by steps 27/31
+    void *PJ, *APJ;       // orthonormalised active directions (packed)
+    void *T0;             // multigrid fine-level scratch
+};
+
+struct Layout {
+    size_t blocks64, blocks32;          // offsets (or SIZE_MAX if absent)
+    std::vector<size_t> mg;             // per level l >= 1: x, b, t (3 entries each)
+    size_t lambda, jpos, cols, coef, gram_out, gram_part, res_part, res_out, wvec;
+    size_t total;
+    int mg_dtype;
+    std::vector<Grid3> levels;
+};
+
+bool op_ok(const lobpcg_op *A)
+{
+    if (!A) return false;
+    if (A->nx < 1 || A->ny < 1 || A->nz < 1) return false;
+    if (A->kind == LOBPCG_OP_LAPLACE7) return true;
+    if (A->kind == LOBPCG_OP_VARCOEF7) return A->kx && A->ky && A->kz;
+    return false;
+}
+
+int check_common(const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T, int m, int precision)
+{
+    if (!op_ok(A)) return LOBPCG_ERR_ARG;
+    if (B) return LOBPCG_ERR_UNSUPPORTED;
+    if (precision != LOBPCG_FP64 && precision != LOBPCG_MIXED) return LOBPCG_ERR_ARG;
+    const long long N = (long long)A->nx * A->ny * A->nz;
+    if (m < 1 || m > LOBPCG_MAX_M || 3LL * m > N) return LOBPCG_ERR_ARG;
+    if (T) {
+        if (T->kind == LOBPCG_PC_GMG_V) {
+            if (T->levels < 1 || T->levels > 30 || T->nu_pre < 0 || T->nu_post != T->nu_pre ||
+                T->coarse_sweeps < 1 || !(T->omega > 0.0 && T->omega < 2.0))
+                return LOBPCG_ERR_ARG;
+            int nx = A->nx, ny = A->ny, nz = A->nz;
+            for (int l = 1; l < T->levels; l++) {
+                nx /= 2, ny /= 2, nz /= 2;
+                if (nx < 1 || ny < 1 || nz < 1) return LOBPCG_ERR_ARG;
+            }
+        } else if (T->kind != LOBPCG_PC_NONE) {
+            return LOBPCG_ERR_ARG;
+        }
+    }
+    return LOBPCG_OK;
+}
+
+bool has_mg(const lobpcg_precond *T) { return T && T->kind == LOBPCG_PC_GMG_V; }
+
+Layout make_layout(const lobpcg_op *A, const lobpcg_precond *T, int m, int precision)
+{
+    Layout L;
+    const long long N = (long long)A->nx * A->ny * A->nz;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = align_up(off);
+        off = o + bytes;
+        return o;
+    };
+    L.blocks64 = take(11 * (size_t)N * m * 8);
+    L.blocks32 = precision == LOBPCG_MIXED ? take(11 * (size_t)N * m * 4) : (size_t)-1;
+    L.mg_dtype = precision == LOBPCG_MIXED ? DT_F32 : DT_F64;
+    L.levels.push_back(Grid3{A->nx, A->ny, A->nz});
+    if (has_mg(T)) {
+        for (int l = 1; l < T->levels; l++) {
+            Grid3 g = L.levels.back();
+            L.levels.push_back(Grid3{g.nx / 2, g.ny / 2, g.nz / 2});
+            for (int j = 0; j < 3; j++) L.mg.push_back(take((size_t)L.levels.back().n() * m * esize(L.mg_dtype)));
+        }
+    }
+    const int K = 3 * m, Kp = gram_kpad(K);
+    L.lambda = take(sizeof(double) * m);
+    L.jpos = take(sizeof(int) * m);
+    L.cols = take(sizeof(int) * COEF_SLOTS * m);
+    L.coef = take((size_t)COEF_SLOTS * K * m * 8);
+    L.gram_out = take((size_t)2 * Kp * Kp * 8);
+    L.gram_part = take(gram_partials_bytes(DT_F64, N, K));
+    L.res_part = take((size_t)residual_blocks(N, m) * 2 * m * 8);
+    L.res_out = take((size_t)2 * m * 8);
+    L.wvec = take(sizeof(double) * m);
+    L.total = align_up(off);
+    return L;
+}
+
+double laplace7_norm(const Grid3 &g)
+{
+    // infinity norm: diagonal 6 plus one per axis neighbour that exists
+    return 6.0 + std::min(2, g.nx - 1) + std::min(2, g.ny - 1) + std::min(2, g.nz - 1);
+}
+
+}  // namespace
+
+struct lobpcg_ctx {
+    Grid3 g;
+    long long N;
+    int m, precision;
+    lobpcg_op A;
+    lobpcg_precond T;
+    bool mg;
+    hipStream_t st;
+    char *ws;
+    Layout L;
+    Blocks b64, b32;
+    std::vector<void *> mgx, mgb, mgt;
+    // small device areas
+    double *d_lambda, *d_gram_out, *d_gram_part, *d_res_part, *d_res_out, *d_w;
+    int *d_jpos, *d_cols;
+    char *d_coef;
+    // pinned host staging
+    char *h_pin;
+    size_t h_coef_off, h_cols_off, h_gram_off, h_res_off, h_small_off, h_pin_bytes;
+    int coef_slot;
+    // options
+    double switch_tol;
+    int stall_window;
+    double stall_factor;
+    bool profile, reactivate;
+    lobpcg_stats stats;
+    // profiling: pending (step, start, end) event pairs
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<int> ev_step;
+    int ev_used;
+};
+
+namespace {
+
+#define HIPCHK(x)                                        \
+    do {                                                 \
+        if ((x) != hipSuccess) return LOBPCG_ERR_HIP;    \
+    } while (0)
+
+Blocks carve_blocks(char *base, long long N, int m, int dt)
+{
+    Blocks b;
+    const size_t bs = (size_t)N * m * esize(dt);
+    void **slots[11] = {&b.X[0], &b.X[1], &b.AX[0], &b.AX[1], &b.W, &b.AW, &b.P, &b.AP, &b.PJ, &b.APJ, &b.T0};
+    for (int i = 0; i < 11; i++) *slots[i] = base + i * bs;
+    return b;
+}
+
+// ---- profiling
+void prof_begin(lobpcg_ctx *c, int step)
+{
+    if (!c->profile) return;
+    if (c->ev_used + 2 > (int)c->ev_pool.size()) return;
+    (void)hipEventRecord(c->ev_pool[c->ev_used], c->st);
+    c->ev_step[c->ev_used / 2] = step;
+    c->ev_used += 1;
+}
+void prof_end(lobpcg_ctx *c)
+{
+    if (!c->profile) return;
+    if (c->ev_used % 2 == 0) return;
+    (void)hipEventRecord(c->ev_pool[c->ev_used], c->st);
+    c->ev_used += 1;
+}
+// called right after a stream synchronisation
+void prof_collect(lobpcg_ctx *c)
+{
+    if (!c->profile) return;
+    for (int i = 0; i + 1 < c->ev_used; i += 2) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ev_pool[i], c->ev_pool[i + 1]) == hipSuccess) {
+            c->stats.step_ms[c->ev_step[i / 2]] += ms;
+            c->stats.step_calls[c->ev_step[i / 2]] += 1;
+        }
+    }
+    c->ev_used = 0;
+}
+
+int sync(lobpcg_ctx *c)
+{
+    HIPCHK(hipStreamSynchronize(c->st));
+    prof_collect(c);
+    c->coef_slot = 0;
+    return LOBPCG_OK;
+}
+
+// Upload small host data through a pinned ring slot; valid until the next sync.
+int upload_coef(lobpcg_ctx *c, int dt, const double *C, int rows, int cols, const void **dptr)
+{
+    if (c->coef_slot >= COEF_SLOTS) {
+        int s = sync(c);
+        if (s) return s;
+    }
+    const size_t slot_bytes = (size_t)3 * c->m * c->m * 8;
+    char *h = c->h_pin + c->h_coef_off + c->coef_slot * slot_bytes;
+    char *d = c->d_coef + c->coef_slot * slot_bytes;
+    const size_t n = (size_t)rows * cols;
+    if (dt == DT_F32) {
+        float *hf = (float *)h;
+        for (size_t i = 0; i < n; i++) hf[i] = (float)C[i];
+    } else {
+        memcpy(h, C, n * 8);
+    }
+    HIPCHK(hipMemcpyAsync(d, h, n * esize(dt), hipMemcpyHostToDevice, c->st));
+    *dptr = d;
+    c->coef_slot++;
+    return LOBPCG_OK;
+}
+
+int upload_cols(lobpcg_ctx *c, const std::vector<int> &cols, const int **dptr)
+{
+    // same ring index as the coefficients, separate area
+    if (c->coef_slot >= COEF_SLOTS) {
+        int s = sync(c);
+        if (s) return s;
+    }
+    int *h = (int *)(c->h_pin + c->h_cols_off) + c->coef_slot * c->m;
+    int *d = c->d_cols + c->coef_slot * c->m;
+    std::copy(cols.begin(), cols.end(), h);
+    HIPCHK(hipMemcpyAsync(d, h, cols.size() * sizeof(int), hipMemcpyHostToDevice, c->st));
+    *dptr = d;
+    c->coef_slot++;
+    return LOBPCG_OK;
+}
+
+// ---- kernel-level building blocks (asynchronous unless they return host data)
+
+int apply_A(lobpcg_ctx *c, const lobpcg_op *A, int dt, const void *in, void *out, int k)
+{
+    prof_begin(c, LOBPCG_STEP_APPLY_A);
+    hipError_t e;
+    if (A->kind == LOBPCG_OP_VARCOEF7)
+        e = launch_varcoef7(dt, c->g, k, A->kx, A->ky, A->kz, in, out, c->st);
+    else
+        e = launch_laplace7(dt, c->g, k, in, out, 1.0, c->st);
+    prof_end(c);
+    return e == hipSuccess ? LOBPCG_OK : LOBPCG_ERR_HIP;
+}
+
+// Gram products; returns K x K host matrices (row-major), upper triangle
+// mirrored.  SAS may be null when AS is not given.
+int gram(lobpcg_ctx *c, int dt, int n, const void *const *S, const void *const *AS, const int *w,
+         std::vector<double> &SS, std::vector<double> *SAS, int step)
+{
+    GramArgs a;
+    int K = 0;
+    for (int i = 0; i < 3; i++) {
+        a.S[i] = i < n ? S[i] : nullptr;
+        a.AS[i] = (i < n && AS) ? AS[i] : nullptr;
+        a.w[i] = i < n ? w[i] : 0;
+        if (i < n) K += w[i];
+    }
+    a.nblk = n;
+    a.N = c->N;
+    a.partials = c->d_gram_part;
+    a.out = c->d_gram_out;
+    const int Kp = gram_kpad(K);
+    prof_begin(c, step);
+    if (launch_gram(dt, a, c->st) != hipSuccess) return LOBPCG_ERR_HIP;
+    prof_end(c);
+    const size_t bytes = (size_t)(AS ? 2 : 1) * Kp * Kp * 8;
+    double *h = (double *)(c->h_pin + c->h_gram_off);
+    HIPCHK(hipMemcpyAsync(h, c->d_gram_out, bytes, hipMemcpyDeviceToHost, c->st));
+    int s = sync(c);
+    if (s) return s;
+    auto unpack = [&](const double *src, std::vector<double> &dst) {
+        dst.assign((size_t)K * K, 0.0);
+        for (int i = 0; i < K; i++)
+            for (int j = i; j < K; j++) dst[(size_t)i * K + j] = dst[(size_t)j * K + i] = src[(size_t)i * Kp + j];
+    };
+    unpack(h, SS);
+    if (AS && SAS) unpack(h + (size_t)Kp * Kp, *SAS);
+    return LOBPCG_OK;
+}
+
+// out = sum_i in_i[:, cols_i] C_i (+ add); optional out2 (see CombineArgs).
+int combine(lobpcg_ctx *c, int dt, int n, const void *const *in, const int *ld, const int *const *cols,
+            const int *k, const double *C, int kout, const void *add, void *out, void *out2, int step)
+{
+    CombineArgs a;
+    int ks = 0;
+    for (int i = 0; i < 3; i++) {
+        a.in[i] = i < n ? in[i] : nullptr;
+        a.ld[i] = i < n ? ld[i] : 0;
+        a.k[i] = i < n ? k[i] : 0;
+        a.cols[i] = i < n && cols ? cols[i] : nullptr;
+        if (i < n) ks += k[i];
+    }
+    a.nin = n;
+    a.kout = kout;
+    a.add = add;
+    a.out = out;
+    a.out2 = out2;
+    a.N = c->N;
+    int s = upload_coef(c, dt, C, ks, kout, &a.C);
+    if (s) return s;
+    prof_begin(c, step);
+    hipError_t e = launch_combine(dt, a, c->st);
+    prof_end(c);
+    return e == hipSuccess ? LOBPCG_OK : LOBPCG_ERR_HIP;
+}
+
+// Residual of step 7 over the m columns of (X, AX) with Ritz values lam;
+// writes W for the columns listed in J (packed) when W is not null and
+// returns the sums sum r_j^2, sum x_j^2 (both length m) on the host.
+int residual(lobpcg_ctx *c, int dt, const void *X, const void *AX, const std::vector<double> &lam,
+             const std::vector<int> &J, void *W, std::vector<double> &rr, std::vector<double> &xx)
+{
+    const int m = c->m;
+    double *hs = (double *)(c->h_pin + c->h_small_off);
+    int *hj = (int *)(hs + m);
+    for (int j = 0; j < m; j++) hs[j] = lam[j], hj[j] = -1;
+    for (size_t i = 0; i < J.size(); i++) hj[J[i]] = (int)i;
+    HIPCHK(hipMemcpyAsync(c->d_lambda, hs, m * 8, hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->d_jpos, hj, m * sizeof(int), hipMemcpyHostToDevice, c->st));
+    ResidualArgs a;
+    a.X = X;
+    a.AX = AX;
+    a.lambda = c->d_lambda;
+    a.jpos = c->d_jpos;
+    a.W = W;
+    a.m = m;
+    a.nJ = (int)J.size();
+    a.N = c->N;
+    a.partials = c->d_res_part;
+    a.out = c->d_res_out;
+    prof_begin(c, LOBPCG_STEP_RESIDUAL);
+    if (launch_residual(dt, a, c->st) != hipSuccess) return LOBPCG_ERR_HIP;
+    prof_end(c);
+    double *h = (double *)(c->h_pin + c->h_res_off);
+    HIPCHK(hipMemcpyAsync(h, c->d_res_out, 2 * m * 8, hipMemcpyDeviceToHost, c->st));
+    int s = sync(c);
+    if (s) return s;
+    rr.assign(h, h + m);
+    xx.assign(h + m, h + 2 * m);
+    return LOBPCG_OK;
+}
+
+// V-cycle on N x k blocks of the multigrid precision.  b: right-hand side at
+// level l; xa, xb: two buffers of that level; returns the buffer holding T b.
+void *vcycle(lobpcg_ctx *c, int l, const void *b, void *xa, void *xb, int k, hipError_t &err)
+{
+    const int dt = c->L.mg_dtype;
+    const Grid3 &g = c->L.levels[l];
+    const double s = std::pow(4.0, -l), om = c->T.omega;
+    const int Lv = (int)c->L.levels.size();
+    auto chk = [&](hipError_t e) {
+        if (e != hipSuccess && err == hipSuccess) err = e;
+    };
+    if (l == Lv - 1) {
+        if (coarse_solve_fits(dt, g)) {
+            chk(launch_coarse_solve(dt, g, k, c->T.coarse_sweeps, s, om, b, xa, c->st));
+            return xa;
+        }
+        chk(launch_scale(dt, g.n() * k, b, xa, om / (6.0 * s), c->st));
+        void *cur = xa, *oth = xb;
+        for (int i = 1; i < c->T.coarse_sweeps; i++) {
+            chk(launch_jacobi(dt, g, k, cur, b, oth, s, om, c->st));
+            std::swap(cur, oth);
+        }
+        return cur;
+    }
+    void *cur = xa, *oth = xb;
+    chk(launch_scale(dt, g.n() * k, b, cur, c->T.nu_pre > 0 ? om / (6.0 * s) : 0.0, c->st));
+    for (int i = 1; i < c->T.nu_pre; i++) {
+        chk(launch_jacobi(dt, g, k, cur, b, oth, s, om, c->st));
+        std::swap(cur, oth);
+    }
+    chk(launch_resid7(dt, g, k, cur, b, oth, s, c->st));
+    const Grid3 &gc = c->L.levels[l + 1];
+    void *bc = c->mgb[l + 1], *xc = c->mgx[l + 1], *tc = c->mgt[l + 1];
+    chk(launch_restrict(dt, g, gc, k, oth, bc, c->st));
+    void *e = vcycle(c, l + 1, bc, xc, tc, k, err);
+    chk(launch_prolong_add(dt, g, gc, k, e, cur, c->st));
+    for (int i = 0; i < c->T.nu_post; i++) {
+        chk(launch_jacobi(dt, g, k, cur, b, oth, s, om, c->st));
+        std::swap(cur, oth);
+    }
+    return cur;
+}
+
+// T applied to the N x k block `in` (precision dt); result in one of the two
+// fine-level buffers fa / fb of precision dt, returned.  In the FP64 phase of
+// the mixed solver the FP32 multigrid runs on a down-cast copy.
+int apply_T(lobpcg_ctx *c, int dt, const void *in, void *fa, void *fb, int k, void **result)
+{
+    prof_begin(c, LOBPCG_STEP_PRECOND);
+    hipError_t err = hipSuccess;
+    const int mdt = c->L.mg_dtype;
+    if (dt == mdt) {
+        *result = vcycle(c, 0, in, fa, fb, k, err);
+    } else {
+        // mixed solver, FP64 phase: b32 buffers are free; T in FP32
+        const long long n = c->N * k;
+        void *bin = c->b32.W, *xa = c->b32.AW, *xb = c->b32.T0;
+        if (launch_cast(dt, mdt, n, in, bin, c->st) != hipSuccess) err = hipErrorUnknown;
+        void *r = vcycle(c, 0, bin, xa, xb, k, err);
+        if (launch_cast(mdt, dt, n, r, fa, c->st) != hipSuccess) err = hipErrorUnknown;
+        *result = fa;
+    }
+    prof_end(c);
+    return err == hipSuccess ? LOBPCG_OK : LOBPCG_ERR_HIP;
+}
+
+// Cholesky orthonormalisation of a K x K Gram submatrix: returns R^-1.
+bool chol_inv(int n, const std::vector<double> &G, std::vector<double> &Ri)
+{
+    std::vector<double> R((size_t)n * n);
+    if (!chol_scaled(n, G.data(), R.data())) return false;
+    Ri.resize((size_t)n * n);
+    return triu_inverse(n, R.data(), Ri.data());
+}
+
+bool all_finite(const std::vector<double> &v)
+{
+    for (double x : v)
+        if (!std::isfinite(x)) return false;
+    return true;
+}
+
+double op_norm(lobpcg_ctx *c, const lobpcg_op *A)
+{
+    if (A->kind == LOBPCG_OP_LAPLACE7) return laplace7_norm(c->g);
+    // infinity norm of -div(k grad u): diagonal = sum of the six face
+    // coefficients, off-diagonal = the interior faces once more
+    const int nx = c->g.nx, ny = c->g.ny, nz = c->g.nz;
+    std::vector<double> kx((size_t)nz * ny * (nx + 1)), ky((size_t)nz * (ny + 1) * nx), kz((size_t)(nz + 1) * ny * nx);
+    if (hipMemcpyAsync(kx.data(), A->kx, kx.size() * 8, hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+        hipMemcpyAsync(ky.data(), A->ky, ky.size() * 8, hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+        hipMemcpyAsync(kz.data(), A->kz, kz.size() * 8, hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+        hipStreamSynchronize(c->st) != hipSuccess)
+        return -1.0;
+    double best = 0.0;
+    for (int z = 0; z < nz; z++)
+        for (int y = 0; y < ny; y++)
+            for (int x = 0; x < nx; x++) {
+                const double a = kx[((size_t)z * ny + y) * (nx + 1) + x], b = kx[((size_t)z * ny + y) * (nx + 1) + x + 1];
+                const double cc = ky[((size_t)z * (ny + 1) + y) * nx + x], d = ky[((size_t)z * (ny + 1) + y + 1) * nx + x];
+                const double e = kz[((size_t)z * ny + y) * nx + x], f = kz[((size_t)(z + 1) * ny + y) * nx + x];
+                double row = a + b + cc + d + e + f;
+                row += (x > 0 ? a : 0) + (x + 1 < nx ? b : 0) + (y > 0 ? cc : 0) + (y + 1 < ny ? d : 0) +
+                       (z > 0 ? e : 0) + (z + 1 < nz ? f : 0);
+                best = std::max(best, row);
+            }
+    return best;
+}
+
+// ---- one LOBPCG phase (steps 6-33) in precision dt on blocks B.
+struct PhaseState {
+    int cur;                  // which X/AX buffer is current
+    std::vector<double> lam;  // Ritz values
+    std::vector<int> J;       // active set
+    bool hasP;
+};
+
+enum { PH_CONVERGED, PH_MAXIT, PH_SWITCH };
+
+int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &ps, double tol, double normA,
+              int maxit, int &iters, double *h_hist, bool explicit_gram, bool allow_switch, int &outcome)
+{
+    const int m = c->m;
+    std::vector<double> rr, xx, rho(m), SS, SAS, PP;
+    std::vector<double> hist_max;
+    outcome = PH_MAXIT;
+    while (iters < maxit) {
+        // step 7 for the current active set (W_J written packed), norms for all m
+        int s = residual(c, dt, B.X[ps.cur], B.AX[ps.cur], ps.lam, ps.J, B.W, rr, xx);
+        if (s) return s;
+        double rmax = 0.0;
+        for (int j = 0; j < m; j++) {
+            rho[j] = std::sqrt(rr[j]) / (normA * std::sqrt(xx[j]));
+            if (!std::isfinite(rho[j])) return LOBPCG_ERR_NONFINITE;
+            rmax = std::max(rmax, rho[j]);
+        }
+        if (h_hist) std::copy(rho.begin(), rho.end(), h_hist + (size_t)iters * m);
+        iters++;
+        if (dt == DT_F32) c->stats.iters_fp32++;
+        else c->stats.iters_fp64++;
+        // step 8: drop converged columns; end only when every residual is small
+        std::vector<int> Jn;
+        for (int j : ps.J)
+            if (rho[j] > tol) Jn.push_back(j);
+        if (Jn.empty() && c->reactivate)
+            for (int j = 0; j < m; j++)
+                if (rho[j] > tol) Jn.push_back(j);
+        if (Jn.empty()) {
+            outcome = PH_CONVERGED;
+            return LOBPCG_OK;
+        }
+        if (allow_switch) {
+            hist_max.push_back(rmax);
+            const int wdw = c->stall_window;
+            if ((int)hist_max.size() > wdw && rmax > c->stall_factor * hist_max[hist_max.size() - 1 - wdw]) {
+                outcome = PH_SWITCH;
+                return LOBPCG_OK;
+            }
+        }
+        if (Jn != ps.J) {
+            // W was written for the previous active set: write it again for Jn
+            ps.J = Jn;
+            s = residual(c, dt, B.X[ps.cur], B.AX[ps.cur], ps.lam, ps.J, B.W, rr, xx);
+            if (s) return s;
+        }
+        const int nJ = (int)ps.J.size();
+        // step 9: W_J = T W_J
+        void *Wt = B.W;
+        if (c->mg) {
+            s = apply_T(c, dt, B.W, B.AW, B.T0, nJ, &Wt);
+            if (s) return s;
+        }
+        // step 11: W_J = W_J R^-1 with R = chol(W_J^T W_J); the result goes to
+        // whichever of W / T0 does not hold the input
+        {
+            const void *Sb[1] = {Wt};
+            int w1[1] = {nJ};
+            s = gram(c, dt, 1, Sb, nullptr, w1, SS, nullptr, LOBPCG_STEP_ORTHO);
+            if (s) return s;
+            std::vector<double> Ri;
+            if (!all_finite(SS)) return LOBPCG_ERR_NONFINITE;
+            if (!chol_inv(nJ, SS, Ri)) {
+                if (allow_switch) {
+                    outcome = PH_SWITCH;
+                    return LOBPCG_OK;
+                }
+                return LOBPCG_ERR_CHOL;
+            }
+            void *dst = (Wt == B.W) ? B.T0 : B.W;
+            const void *in1[1] = {Wt};
+            int ld1[1] = {nJ}, k1[1] = {nJ};
+            s = combine(c, dt, 1, in1, ld1, nullptr, k1, Ri.data(), nJ, nullptr, dst, nullptr, LOBPCG_STEP_ORTHO);
+            if (s) return s;
+            if (dst == B.T0) std::swap(B.W, B.T0);
+        }
+        // step 12: AW_J = A W_J
+        s = apply_A(c, A, dt, B.W, B.AW, nJ);
+        if (s) return s;
+        // steps 13-16: orthonormalise P_J, AP_J
+        bool useP = false;
+        if (ps.hasP) {
+            const void *Sb[1] = {B.P};
+            int w1[1] = {m};
+            s = gram(c, dt, 1, Sb, nullptr, w1, PP, nullptr, LOBPCG_STEP_ORTHO);
+            if (s) return s;
+            std::vector<double> G((size_t)nJ * nJ), Ri;
+            for (int i = 0; i < nJ; i++)
+                for (int j = 0; j < nJ; j++) G[(size_t)i * nJ + j] = PP[(size_t)ps.J[i] * m + ps.J[j]];
+            if (all_finite(G) && chol_inv(nJ, G, Ri)) {
+                const int *dcols;
+                s = upload_cols(c, ps.J, &dcols);
+                if (s) return s;
+                const void *in1[1] = {B.P};
+                int ld1[1] = {m}, k1[1] = {nJ};
+                const int *cl[1] = {dcols};
+                s = combine(c, dt, 1, in1, ld1, cl, k1, Ri.data(), nJ, nullptr, B.PJ, nullptr, LOBPCG_STEP_ORTHO);
+                if (s) return s;
+                const void *in2[1] = {B.AP};
+                s = combine(c, dt, 1, in2, ld1, cl, k1, Ri.data(), nJ, nullptr, B.APJ, nullptr, LOBPCG_STEP_ORTHO);
+                if (s) return s;
+                useP = true;
+            } else {
+                c->stats.restarts++;
+            }
+        }
+        // steps 17-23: Gram matrices of the trial basis [X, W_J, P_J]
+        const int nb = useP ? 3 : 2;
+        const void *Sb[3] = {B.X[ps.cur], B.W, B.PJ};
+        const void *ASb[3] = {B.AX[ps.cur], B.AW, B.APJ};
+        int wb[3] = {m, nJ, nJ};
+        s = gram(c, dt, nb, Sb, ASb, wb, SS, &SAS, LOBPCG_STEP_GRAM);
+        if (s) return s;
+        if (!all_finite(SS) || !all_finite(SAS)) return LOBPCG_ERR_NONFINITE;
+        const int K = m + (nb - 1) * nJ;
+        std::vector<double> gA(SAS), gB(SS);
+        if (!explicit_gram) {
+            // the paper's form: Lambda and identities on the block diagonal
+            auto blk = [&](int i0, int n0, std::vector<double> &M, bool lam) {
+                for (int i = 0; i < n0; i++)
+                    for (int j = 0; j < n0; j++)
+                        M[(size_t)(i0 + i) * K + i0 + j] = (i == j) ? (lam ? ps.lam[i] : 1.0) : 0.0;
+            };
+            blk(0, m, gA, true);
+            blk(0, m, gB, false);
+            blk(m, nJ, gB, false);
+            if (useP) blk(m + nJ, nJ, gB, false);
+        }
+        // step 24 (on failure with P, retry on the leading [X, W_J] part)
+        std::vector<double> theta(m), C;
+        int Kused = K;
+        bool ok = false;
+        for (int attempt = 0; attempt < 2 && !ok; attempt++) {
+            if (attempt == 1) {
+                if (!useP) break;
+                useP = false;
+                c->stats.restarts++;
+                Kused = m + nJ;
+            }
+            std::vector<double> a2((size_t)Kused * Kused), b2((size_t)Kused * Kused);
+            for (int i = 0; i < Kused; i++)
+                for (int j = 0; j < Kused; j++) {
+                    a2[(size_t)i * Kused + j] = gA[(size_t)i * K + j];
+                    b2[(size_t)i * Kused + j] = gB[(size_t)i * K + j];
+                }
+            C.assign((size_t)Kused * m, 0.0);
+            auto t0 = std::chrono::steady_clock::now();
+            ok = rayleigh_ritz(Kused, m, a2.data(), b2.data(), theta.data(), C.data());
+            auto t1 = std::chrono::steady_clock::now();
+            c->stats.step_ms[LOBPCG_STEP_RR] += std::chrono::duration<double, std::milli>(t1 - t0).count();
+            c->stats.step_calls[LOBPCG_STEP_RR] += 1;
+        }
+        if (!ok) {
+            if (allow_switch) {
+                outcome = PH_SWITCH;
+                return LOBPCG_OK;
+            }
+            return LOBPCG_ERR_RR;
+        }
+        // steps 25-33: P = W_J C_W + P_J C_P, X = X C_X + P (and the A-side)
+        const int nu = useP ? 3 : 2;
+        const void *inX[3] = {B.X[ps.cur], B.W, B.PJ};
+        const void *inA[3] = {B.AX[ps.cur], B.AW, B.APJ};
+        int ld[3] = {m, nJ, nJ}, kk[3] = {m, nJ, nJ};
+        s = combine(c, dt, nu, inX, ld, nullptr, kk, C.data(), m, nullptr, B.P, B.X[1 - ps.cur], LOBPCG_STEP_UPDATE);
+        if (s) return s;
+        s = combine(c, dt, nu, inA, ld, nullptr, kk, C.data(), m, nullptr, B.AP, B.AX[1 - ps.cur],
+                    LOBPCG_STEP_UPDATE);
+        if (s) return s;
+        ps.cur = 1 - ps.cur;
+        ps.lam = theta;
+        ps.hasP = true;
+    }
+    return LOBPCG_OK;
+}
+
+// Steps 3-4 (and the FP64 restart of the mixed solver): orthonormalise X if
+// asked, A X, Rayleigh-Ritz on span(X).  On entry X is in B.X[ps.cur].
+int init_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &ps, bool ortho, bool explicit_gram)
+{
+    const int m = c->m;
+    std::vector<double> SS, SAS;
+    int s;
+    if (ortho) {
+        const void *Sb[1] = {B.X[ps.cur]};
+        int w1[1] = {m};
+        s = gram(c, dt, 1, Sb, nullptr, w1, SS, nullptr, LOBPCG_STEP_ORTHO);
+        if (s) return s;
+        if (!all_finite(SS)) return LOBPCG_ERR_NONFINITE;
+        std::vector<double> Ri;
+        if (!chol_inv(m, SS, Ri)) return LOBPCG_ERR_CHOL;
+        const void *in1[1] = {B.X[ps.cur]};
+        int ld1[1] = {m}, k1[1] = {m};
+        s = combine(c, dt, 1, in1, ld1, nullptr, k1, Ri.data(), m, nullptr, B.X[1 - ps.cur], nullptr,
+                    LOBPCG_STEP_ORTHO);
+        if (s) return s;
+        ps.cur = 1 - ps.cur;
+    }
+    s = apply_A(c, A, dt, B.X[ps.cur], B.AX[ps.cur], m);
+    if (s) return s;
+    const void *Sb[1] = {B.X[ps.cur]}, *ASb[1] = {B.AX[ps.cur]};
+    int w1[1] = {m};
+    s = gram(c, dt, 1, Sb, ASb, w1, SS, &SAS, LOBPCG_STEP_GRAM);
+    if (s) return s;
+    if (!all_finite(SS) || !all_finite(SAS)) return LOBPCG_ERR_NONFINITE;
+    if (!explicit_gram) {
+        std::fill(SS.begin(), SS.end(), 0.0);
+        for (int i = 0; i < m; i++) SS[(size_t)i * m + i] = 1.0;
+    }
+    std::vector<double> theta(m), Z((size_t)m * m);
+    if (!rayleigh_ritz(m, m, SAS.data(), SS.data(), theta.data(), Z.data())) return LOBPCG_ERR_RR;
+    const void *in1[1] = {B.X[ps.cur]}, *in2[1] = {B.AX[ps.cur]};
+    int ld1[1] = {m}, k1[1] = {m};
+    s = combine(c, dt, 1, in1, ld1, nullptr, k1, Z.data(), m, nullptr, B.X[1 - ps.cur], nullptr, LOBPCG_STEP_OTHER);
+    if (s) return s;
+    s = combine(c, dt, 1, in2, ld1, nullptr, k1, Z.data(), m, nullptr, B.AX[1 - ps.cur], nullptr, LOBPCG_STEP_OTHER);
+    if (s) return s;
+    ps.cur = 1 - ps.cur;
+    ps.lam = theta;
+    ps.J.clear();
+    for (int j = 0; j < m; j++) ps.J.push_back(j);
+    ps.hasP = false;
+    return LOBPCG_OK;
+}
+
+}  // namespace
+
+// ============================================================================ ABI
+
+extern "C" {
+
+const char *lobpcg_status_string(int s)
+{
+    switch (s) {
+    case LOBPCG_OK: return "converged";
+    case LOBPCG_NOT_CONVERGED: return "not converged within maxit";
+    case LOBPCG_ERR_ARG: return "invalid argument";
+    case LOBPCG_ERR_UNSUPPORTED: return "unsupported (B must be the identity)";
+    case LOBPCG_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case LOBPCG_ERR_CHOL: return "Cholesky factorisation failed";
+    case LOBPCG_ERR_RR: return "Rayleigh-Ritz failed";
+    case LOBPCG_ERR_NONFINITE: return "non-finite values";
+    case LOBPCG_ERR_HIP: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+int lobpcg_workspace_bytes(const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T, int m, int precision,
+                           size_t *bytes)
+{
+    if (!bytes) return LOBPCG_ERR_ARG;
+    int s = check_common(A, B, T, m, precision);
+    if (s) return s;
+    *bytes = make_layout(A, T, m, precision).total;
+    return LOBPCG_OK;
+}
+
+int lobpcg_setup(lobpcg_ctx **out, const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T, int m,
+                 int precision, void *d_workspace, size_t ws_bytes, void *stream)
+{
+    if (!out) return LOBPCG_ERR_ARG;
+    *out = nullptr;
+    int s = check_common(A, B, T, m, precision);
+    if (s) return s;
+    Layout L = make_layout(A, T, m, precision);
+    if (!d_workspace || ws_bytes < L.total || ((uintptr_t)d_workspace % ALIGN)) return LOBPCG_ERR_WORKSPACE;
+    lobpcg_ctx *c = new lobpcg_ctx();
+    c->g = Grid3{A->nx, A->ny, A->nz};
+    c->N = c->g.n();
+    c->m = m;
+    c->precision = precision;
+    c->A = *A;
+    c->mg = has_mg(T);
+    if (T) c->T = *T;
+    else memset(&c->T, 0, sizeof(c->T));
+    c->st = (hipStream_t)stream;
+    c->ws = (char *)d_workspace;
+    c->L = L;
+    c->b64 = carve_blocks(c->ws + L.blocks64, c->N, m, DT_F64);
+    if (precision == LOBPCG_MIXED) c->b32 = carve_blocks(c->ws + L.blocks32, c->N, m, DT_F32);
+    else memset(&c->b32, 0, sizeof(c->b32));
+    c->mgx.assign(L.levels.size(), nullptr);
+    c->mgb.assign(L.levels.size(), nullptr);
+    c->mgt.assign(L.levels.size(), nullptr);
+    for (size_t l = 1; l < L.levels.size(); l++) {
+        c->mgx[l] = c->ws + L.mg[3 * (l - 1)];
+        c->mgb[l] = c->ws + L.mg[3 * (l - 1) + 1];
+        c->mgt[l] = c->ws + L.mg[3 * (l - 1) + 2];
+    }
+    c->d_lambda = (double *)(c->ws + L.lambda);
+    c->d_jpos = (int *)(c->ws + L.jpos);
+    c->d_cols = (int *)(c->ws + L.cols);
+    c->d_coef = c->ws + L.coef;
+    c->d_gram_out = (double *)(c->ws + L.gram_out);
+    c->d_gram_part = (double *)(c->ws + L.gram_part);
+    c->d_res_part = (double *)(c->ws + L.res_part);
+    c->d_res_out = (double *)(c->ws + L.res_out);
+    c->d_w = (double *)(c->ws + L.wvec);
+    // pinned host staging
+    const int Kp = gram_kpad(3 * m);
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        size_t o = align_up(off);
+        off = o + b;
+        return o;
+    };
+    c->h_coef_off = take((size_t)COEF_SLOTS * 3 * m * m * 8);
+    c->h_cols_off = take((size_t)COEF_SLOTS * m * sizeof(int));
+    c->h_gram_off = take((size_t)2 * Kp * Kp * 8);
+    c->h_res_off = take((size_t)2 * m * 8);
+    c->h_small_off = take((size_t)m * 8 + (size_t)m * sizeof(int));
+    c->h_pin_bytes = align_up(off);
+    if (hipHostMalloc((void **)&c->h_pin, c->h_pin_bytes, hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return LOBPCG_ERR_HIP;
+    }
+    c->coef_slot = 0;
+    c->switch_tol = 1e-5;
+    c->stall_window = 5;
+    c->stall_factor = 0.7;
+    c->profile = false;
+    c->reactivate = true;
+    memset(&c->stats, 0, sizeof(c->stats));
+    c->ev_used = 0;
+    *out = c;
+    return LOBPCG_OK;
+}
+
+void lobpcg_destroy(lobpcg_ctx *c)
+{
+    if (!c) return;
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->h_pin) (void)hipHostFree(c->h_pin);
+    delete c;
+}
+
+int lobpcg_set_option(lobpcg_ctx *c, int key, double v)
+{
+    if (!c) return LOBPCG_ERR_ARG;
+    switch (key) {
+    case LOBPCG_OPT_SWITCH_TOL:
+        if (!(v > 0)) return LOBPCG_ERR_ARG;
+        c->switch_tol = v;
+        return LOBPCG_OK;
+    case LOBPCG_OPT_STALL_WINDOW:
+        if (v < 1) return LOBPCG_ERR_ARG;
+        c->stall_window = (int)v;
+        return LOBPCG_OK;
+    case LOBPCG_OPT_STALL_FACTOR:
+        if (!(v > 0 && v <= 1)) return LOBPCG_ERR_ARG;
+        c->stall_factor = v;
+        return LOBPCG_OK;
+    case LOBPCG_OPT_PROFILE:
+        c->profile = v != 0;
+        if (c->profile && c->ev_pool.empty()) {
+            c->ev_pool.resize(512);
+            c->ev_step.assign(256, 0);
+            for (auto &e : c->ev_pool)
+                if (hipEventCreate(&e) != hipSuccess) return LOBPCG_ERR_HIP;
+        }
+        return LOBPCG_OK;
+    case LOBPCG_OPT_REACTIVATE: c->reactivate = v != 0; return LOBPCG_OK;
+    default: return LOBPCG_ERR_ARG;
+    }
+}
+
+int lobpcg_get_stats(const lobpcg_ctx *c, lobpcg_stats *st)
+{
+    if (!c || !st) return LOBPCG_ERR_ARG;
+    *st = c->stats;
+    return LOBPCG_OK;
+}
+
+static int same_op(const lobpcg_ctx *c, const lobpcg_op *A)
+{
+    return op_ok(A) && A->nx == c->g.nx && A->ny == c->g.ny && A->nz == c->g.nz && A->kind == c->A.kind;
+}
+
+static int same_precond(const lobpcg_ctx *c, const lobpcg_precond *T)
+{
+    if (!c->mg) return !T || T->kind == LOBPCG_PC_NONE;
+    return T && T->kind == c->T.kind && T->levels == c->T.levels && T->nu_pre == c->T.nu_pre &&
+           T->nu_post == c->T.nu_post && T->coarse_sweeps == c->T.coarse_sweeps && T->omega == c->T.omega;
+}
+
+int lobpcg_solve(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T, const double *d_X0,
+                 int m, double tol, int maxit, double *h_lambda, double *d_X, double *h_hist, int *h_iters,
+                 double *h_final_resid)
+{
+    if (!c) return LOBPCG_ERR_ARG;
+    if (B) return LOBPCG_ERR_UNSUPPORTED;
+    if (!same_op(c, A) || !same_precond(c, T) || m != c->m || !d_X0 || !d_X || !h_lambda || !h_iters ||
+        !(tol > 0) || maxit < 0)
+        return LOBPCG_ERR_ARG;
+    auto t0 = std::chrono::steady_clock::now();
+    memset(&c->stats, 0, sizeof(c->stats));
+    c->ev_used = 0;
+    c->coef_slot = 0;
+    *h_iters = 0;
+    const double normA = op_norm(c, A);
+    if (!(normA > 0)) return LOBPCG_ERR_HIP;
+    const size_t nm = (size_t)c->N * m;
+    int iters = 0, s = LOBPCG_OK, outcome = PH_MAXIT;
+    PhaseState ps;
+    ps.cur = 0;
+    if (c->precision == LOBPCG_MIXED) {
+        // FP32 phase
+        prof_begin(c, LOBPCG_STEP_OTHER);
+        if (launch_cast(DT_F64, DT_F32, nm, d_X0, c->b32.X[0], c->st) != hipSuccess) return LOBPCG_ERR_HIP;
+        prof_end(c);
+        s = init_phase(c, A, DT_F32, c->b32, ps, true, true);
+        if (s == LOBPCG_OK) {
+            s = run_phase(c, A, DT_F32, c->b32, ps, std::max(tol, c->switch_tol), normA, maxit, iters, h_hist,
+                          true, true, outcome);
+        }
+        if (s == LOBPCG_OK) {
+            // FP64 phase: up-cast X, explicit A X, Rayleigh-Ritz on span(X), P reset
+            prof_begin(c, LOBPCG_STEP_OTHER);
+            if (launch_cast(DT_F32, DT_F64, nm, c->b32.X[ps.cur], c->b64.X[0], c->st) != hipSuccess)
+                return LOBPCG_ERR_HIP;
+            prof_end(c);
+            ps.cur = 0;
+            s = init_phase(c, A, DT_F64, c->b64, ps, false, true);
+            if (s == LOBPCG_OK)
+                s = run_phase(c, A, DT_F64, c->b64, ps, tol, normA, maxit, iters, h_hist, false, false, outcome);
+        }
+    } else {
+        HIPCHK(hipMemcpyAsync(c->b64.X[0], d_X0, nm * 8, hipMemcpyDeviceToDevice, c->st));
+        s = init_phase(c, A, DT_F64, c->b64, ps, true, false);
+        if (s == LOBPCG_OK)
+            s = run_phase(c, A, DT_F64, c->b64, ps, tol, normA, maxit, iters, h_hist, false, false, outcome);
+    }
+    *h_iters = iters;
+    c->stats.iters_total = iters;
+    if (s != LOBPCG_OK) {
+        c->stats.status = s;
+        return s;
+    }
+    // outputs: X, Lambda, explicit residuals with a fresh A X
+    HIPCHK(hipMemcpyAsync(d_X, c->b64.X[ps.cur], nm * 8, hipMemcpyDeviceToDevice, c->st));
+    for (int j = 0; j < m; j++) h_lambda[j] = ps.lam[j];
+    if (h_final_resid) {
+        s = apply_A(c, A, DT_F64, c->b64.X[ps.cur], c->b64.AW, m);
+        if (s) return s;
+        std::vector<double> rr, xx;
+        std::vector<int> none;
+        s = residual(c, DT_F64, c->b64.X[ps.cur], c->b64.AW, ps.lam, none, nullptr, rr, xx);
+        if (s) return s;
+        for (int j = 0; j < m; j++) h_final_resid[j] = std::sqrt(rr[j]) / (normA * std::sqrt(xx[j]));
+    }
+    s = sync(c);
+    if (s) return s;
+    c->stats.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    c->stats.status = outcome == PH_CONVERGED ? LOBPCG_OK : LOBPCG_NOT_CONVERGED;
+    return c->stats.status;
+}
+
+int lobpcg_eig_grad_k(lobpcg_ctx *c, const double *d_X, const double *h_gbar, int m, double *gkx, double *gky,
+                      double *gkz)
+{
+    if (!c || !d_X || !h_gbar || !gkx || !gky || !gkz || m < 1 || m > c->m) return LOBPCG_ERR_ARG;
+    // column norms (x_i, x_i) through the residual kernel with AX = X and
+    // lambda = 0; it works on blocks of the context's width, so a narrower X
+    // is first copied into zero-padded scratch
+    std::vector<double> zero(c->m, 0.0), rr, xx;
+    std::vector<int> none;
+    const void *Xs = d_X;
+    if (m != c->m) {
+        void *t = c->b64.T0;
+        HIPCHK(hipMemsetAsync(t, 0, (size_t)c->N * c->m * 8, c->st));
+        HIPCHK(hipMemcpy2DAsync(t, (size_t)c->m * 8, d_X, (size_t)m * 8, (size_t)m * 8, (size_t)c->N,
+                                hipMemcpyDeviceToDevice, c->st));
+        Xs = t;
+    }
+    int s = residual(c, DT_F64, Xs, Xs, zero, none, nullptr, rr, xx);
+    if (s) return s;
+    std::vector<double> w(c->m, 0.0);
+    for (int i = 0; i < m; i++) {
+        if (!(xx[i] > 0)) return LOBPCG_ERR_ARG;
+        w[i] = h_gbar[i] / xx[i];
+    }
+    double *hs = (double *)(c->h_pin + c->h_small_off);
+    std::copy(w.begin(), w.end(), hs);
+    HIPCHK(hipMemcpyAsync(c->d_w, hs, c->m * 8, hipMemcpyHostToDevice, c->st));
+    if (launch_eig_grad(c->g, c->m, (const double *)Xs, c->d_w, gkx, gky, gkz, c->st) != hipSuccess)
+        return LOBPCG_ERR_HIP;
+    return sync(c);
+}
+
+// ---------------------------------------------------------------- the steps one by one
+
+static int dtype_ok(const lobpcg_ctx *c, int dt)
+{
+    return dt == LOBPCG_F64 || (dt == LOBPCG_F32 && c->precision == LOBPCG_MIXED);
+}
+
+int lobpcg_apply_A(lobpcg_ctx *c, const lobpcg_op *A, int dt, const void *in, void *out, int k)
+{
+    if (!c || !same_op(c, A) || !dtype_ok(c, dt) || !in || !out || k < 1 || k > 3 * c->m) return LOBPCG_ERR_ARG;
+    int s = apply_A(c, A, dt == LOBPCG_F32 ? DT_F32 : DT_F64, in, out, k);
+    if (s) return s;
+    return sync(c);
+}
+
+int lobpcg_apply_T(lobpcg_ctx *c, int dt, const void *in, void *out, int k)
+{
+    if (!c || !dtype_ok(c, dt) || !in || !out || k < 1 || k > c->m) return LOBPCG_ERR_ARG;
+    const int d = dt == LOBPCG_F32 ? DT_F32 : DT_F64;
+    const size_t bytes = (size_t)c->N * k * esize(d);
+    if (!c->mg) {
+        HIPCHK(hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, c->st));
+        return sync(c);
+    }
+    Blocks &B = d == DT_F32 ? c->b32 : c->b64;
+    void *r = nullptr;
+    int s = apply_T(c, d, in, B.AW, B.T0, k, &r);
+    if (s) return s;
+    HIPCHK(hipMemcpyAsync(out, r, bytes, hipMemcpyDeviceToDevice, c->st));
+    return sync(c);
+}
+
+int lobpcg_gram(lobpcg_ctx *c, int dt, int n, const void *const *S, const void *const *AS, const int *w, double *h_SS,
+                double *h_SAS)
+{
+    if (!c || !dtype_ok(c, dt) || n < 1 || n > 3 || !S || !w || !h_SS) return LOBPCG_ERR_ARG;
+    int K = 0;
+    for (int i = 0; i < n; i++) {
+        if (!S[i] || w[i] < 1 || (AS && !AS[i])) return LOBPCG_ERR_ARG;
+        K += w[i];
+    }
+    if (K > 3 * c->m || (AS && !h_SAS)) return LOBPCG_ERR_ARG;
+    std::vector<double> SS, SAS;
+    int s = gram(c, dt == LOBPCG_F32 ? DT_F32 : DT_F64, n, S, AS, w, SS, AS ? &SAS : nullptr, LOBPCG_STEP_GRAM);
+    if (s) return s;
+    std::copy(SS.begin(), SS.end(), h_SS);
+    if (AS) std::copy(SAS.begin(), SAS.end(), h_SAS);
+    return LOBPCG_OK;
+}
+
+int lobpcg_combine(lobpcg_ctx *c, int dt, int n, const void *const *in, const int *ld, const int *const *cols,
+                   const int *k, const double *h_C, int kout, const void *d_add, void *d_out)
+{
+    if (!c || !dtype_ok(c, dt) || n < 1 || n > 3 || !in || !ld || !k || !h_C || !d_out || kout < 1 || kout > c->m)
+        return LOBPCG_ERR_ARG;
+    int ks = 0;
+    std::vector<const int *> dcols(3, nullptr);
+    for (int i = 0; i < n; i++) {
+        if (!in[i] || ld[i] < 1 || k[i] < 1 || in[i] == d_out) return LOBPCG_ERR_ARG;
+        if (cols && cols[i]) {
+            std::vector<int> cv(cols[i], cols[i] + k[i]);
+            for (int x : cv)
+                if (x < 0 || x >= ld[i]) return LOBPCG_ERR_ARG;
+            if ((int)cv.size() > c->m) return LOBPCG_ERR_ARG;
+            int s = upload_cols(c, cv, &dcols[i]);
+            if (s) return s;
+        } else if (k[i] != ld[i]) {
+            return LOBPCG_ERR_ARG;
+        }
+        ks += k[i];
+    }
+    if (ks > 3 * c->m) return LOBPCG_ERR_ARG;
+    int s = combine(c, dt == LOBPCG_F32 ? DT_F32 : DT_F64, n, in, ld, dcols.data(), k, h_C, kout, d_add, d_out,
+                    nullptr, LOBPCG_STEP_UPDATE);
+    if (s) return s;
+    return sync(c);
+}
+
+int lobpcg_residual(lobpcg_ctx *c, int dt, const void *X, const void *AX, int m, const double *h_lambda,
+                    const int *h_J, int nJ, double norm_A, void *d_W, double *h_rho)
+{
+    if (!c || !dtype_ok(c, dt) || !X || !AX || m != c->m || !h_lambda || nJ < 0 || nJ > m || (nJ > 0 && !h_J) ||
+        !(norm_A > 0) || !h_rho || (nJ > 0 && !d_W))
+        return LOBPCG_ERR_ARG;
+    std::vector<double> lam(h_lambda, h_lambda + m), rr, xx;
+    std::vector<int> J(h_J, h_J + nJ);
+    std::vector<int> seen(m, 0);
+    for (int j : J) {
+        if (j < 0 || j >= m || seen[j]) return LOBPCG_ERR_ARG;
+        seen[j] = 1;
+    }
+    int s = residual(c, dt == LOBPCG_F32 ? DT_F32 : DT_F64, X, AX, lam, J, nJ ? d_W : nullptr, rr, xx);
+    if (s) return s;
+    for (int j = 0; j < m; j++) h_rho[j] = std::sqrt(rr[j]) / (norm_A * std::sqrt(xx[j]));
+    return LOBPCG_OK;
+}
+
+int lobpcg_dense_chol(int n, const double *G, double *R)
+{
+    if (n < 1 || !G || !R) return LOBPCG_ERR_ARG;
+    return chol_scaled(n, G, R) ? LOBPCG_OK : LOBPCG_ERR_CHOL;
+}
+
+int lobpcg_dense_rr(int n, int m, const double *gramA, const double *gramB, double *theta, double *C)
+{
+    if (n < 1 || m < 1 || m > n || !gramA || !gramB || !theta || !C) return LOBPCG_ERR_ARG;
+    return rayleigh_ritz(n, m, gramA, gramB, theta, C) ? LOBPCG_OK : LOBPCG_ERR_RR;
+}
+
+}  // extern "C"

@@ -1,0 +1,248 @@
+"""Kernel parity on the GPU: every step's kernel, called through the C ABI,
+against the FP64 CPU oracle on the same seeded inputs.
+
+Sizes span several workgroups, ragged grid tails (dimensions that are not
+multiples of anything) and ragged column counts (1, 3, 5, 7 ...).  FP64
+results must agree to rounding (about 1e-14 relative to the data); FP32
+kernels are compared with the oracle applied to the same FP32 values, to a
+bound of a few FP32 units in the last place times the number of terms.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import grid, mg
+
+L = pytest.importorskip("paper_0705_2626_amd")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+EPS32 = 2.0 ** -24
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
+
+
+def host(t):
+    return t.double().cpu().numpy()
+
+
+_ctx_cache = {}
+
+
+def ctx_for(dims, m, levels=None, prec=L.FP64):
+    key = (dims, m, levels, prec)
+    if key not in _ctx_cache:
+        _ctx_cache[key] = L.lobpcg_setup(L.Op(*dims), L.Precond(levels), m, prec)
+    return _ctx_cache[key]
+
+
+# ---------------------------------------------------------------- stencils (step 12)
+
+@pytest.mark.parametrize("dims", [(16, 16, 16), (13, 11, 9), (40, 7, 5), (3, 50, 2)])
+@pytest.mark.parametrize("k", [1, 3, 4, 8, 32, 33])
+def test_laplace7_fp64(dims, k):
+    N = int(np.prod(dims))
+    ctx = ctx_for(dims, 32 if 96 <= N else max(1, N // 3))
+    if k > 3 * ctx.m:
+        pytest.skip("block wider than the context allows")
+    U = synth.random_block(N, k, seed=k)
+    out = host(L.lobpcg_apply_A(ctx, dev(U)))
+    ref = grid.laplace7(dims, U)
+    np.testing.assert_allclose(out, ref, rtol=0, atol=1e-14 * 12)
+
+
+@pytest.mark.parametrize("dims,k", [((16, 16, 16), 32), ((13, 11, 9), 5), ((40, 7, 5), 8), ((9, 9, 9), 2)])
+def test_laplace7_fp32(dims, k):
+    N = int(np.prod(dims))
+    ctx = ctx_for(dims, min(32, N // 3), prec=L.MIXED)
+    U = synth.random_block(N, k, seed=5).astype(np.float32)
+    out = host(L.lobpcg_apply_A(ctx, dev(U, torch.float32)))
+    ref = grid.laplace7(dims, U.astype(np.float64))
+    np.testing.assert_allclose(out, ref, rtol=0, atol=16 * EPS32 * 12)
+
+
+@pytest.mark.parametrize("dims,k", [((12, 10, 8), 8), ((9, 7, 11), 3), ((16, 16, 16), 1)])
+def test_varcoef7_fp64(dims, k):
+    N = int(np.prod(dims))
+    kx, ky, kz = synth.gaussian_field_faces(*dims, sigma=0.5, corr=4.0, seed=7)
+    A = L.Op(*dims, dev(kx), dev(ky), dev(kz))
+    ctx = L.lobpcg_setup(A, L.Precond(None), 8, L.FP64)
+    U = synth.random_block(N, k, seed=9)
+    out = host(L.lobpcg_apply_A(ctx, dev(U), A=A))
+    ref = grid.varcoef7(dims, kx, ky, kz, U)
+    np.testing.assert_allclose(out, ref, rtol=0, atol=1e-14 * np.abs(ref).max())
+
+
+def test_laplace7_full_size_sampled_fp32():
+    """The n=256, m=32 FP32 block of the mixed-precision benchmark: sampled rows,
+    including the grid's corners, edges and its last point."""
+    dims, k = (256, 256, 256), 32
+    nx, ny, nz = dims
+    N = nx * ny * nz
+    ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(None), k, L.MIXED)
+    g = torch.Generator(device=DEV).manual_seed(3)
+    U = torch.rand((N, k), generator=g, device=DEV, dtype=torch.float32) * 2 - 1
+    out = L.lobpcg_apply_A(ctx, U)
+    pts = np.concatenate([[0, nx - 1, nx * (ny - 1), N - 1, N // 2], synth.sample_faces(N, 300, 4)])
+    # the sampled points and their six neighbours, copied to the host
+    need = set()
+    for p in pts:
+        x, y, z = p % nx, (p // nx) % ny, p // (nx * ny)
+        need.add(int(p))
+        for dx, dy, dz in ((-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)):
+            a, b, c = x + dx, y + dy, z + dz
+            if 0 <= a < nx and 0 <= b < ny and 0 <= c < nz:
+                need.add(int(a + nx * (b + ny * c)))
+    idx = np.array(sorted(need))
+    sparse = np.zeros((N, k))
+    sparse[idx] = U[torch.from_numpy(idx).to(DEV)].cpu().numpy().astype(np.float64)
+    ref = grid.laplace7_rows(dims, sparse, pts)
+    got = out[torch.from_numpy(pts).to(DEV)].double().cpu().numpy()
+    del ctx, U, out
+    np.testing.assert_allclose(got, ref, rtol=0, atol=16 * EPS32 * 12)
+
+
+# ---------------------------------------------------------------- multigrid (step 9)
+
+@pytest.mark.parametrize("dims,levels,k", [((16, 16, 16), 3, 4), ((15, 13, 12), 3, 1), ((24, 20, 16), 4, 7),
+                                           ((32, 32, 32), 3, 8), ((9, 9, 9), 1, 2)])
+def test_vcycle_fp64(dims, levels, k):
+    N = int(np.prod(dims))
+    ctx = ctx_for(dims, 8, levels)
+    B = synth.random_block(N, k, seed=13)
+    out = host(L.lobpcg_apply_T(ctx, dev(B)))
+    ref = mg.VCycle(dims, levels)(B)
+    np.testing.assert_allclose(out, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("dims,levels,k", [((16, 16, 16), 3, 4), ((24, 20, 16), 4, 6), ((33, 17, 9), 2, 3)])
+def test_vcycle_fp32(dims, levels, k):
+    N = int(np.prod(dims))
+    ctx = ctx_for(dims, 8, levels, L.MIXED)
+    B = synth.random_block(N, k, seed=14).astype(np.float32)
+    out = host(L.lobpcg_apply_T(ctx, dev(B, torch.float32)))
+    ref = mg.VCycle(dims, levels)(B.astype(np.float64))
+    np.testing.assert_allclose(out, ref, rtol=0, atol=2e-5 * np.abs(ref).max())
+
+
+def test_vcycle_large_coarsest_grid_uses_global_sweeps():
+    """A coarsest level too big for one workgroup's LDS (20^3 > 2048 points)."""
+    dims, levels, k = (40, 40, 40), 2, 3
+    ctx = ctx_for(dims, 4, levels)
+    B = synth.random_block(64000, k, seed=15)
+    out = host(L.lobpcg_apply_T(ctx, dev(B)))
+    ref = mg.VCycle(dims, levels)(B)
+    np.testing.assert_allclose(out, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+# ---------------------------------------------------------------- Gram products (steps 17-23, 3, 11, 14)
+
+@pytest.mark.parametrize("N,widths", [(4096, (8, 3, 3)), (33 * 17 * 9, (32, 32, 32)), (1000, (4,)),
+                                      (70001, (16, 16)), (5003, (5, 7, 2)), (200000, (32, 17, 17))])
+def test_gram_fp64(N, widths):
+    dims = (N, 1, 1)
+    ctx = ctx_for(dims, 32)
+    S = [synth.random_block(N, w, seed=20 + i) for i, w in enumerate(widths)]
+    AS = [synth.random_block(N, w, seed=40 + i) for i, w in enumerate(widths)]
+    SS, SAS = L.lobpcg_gram(ctx, [dev(s) for s in S], [dev(a) for a in AS])
+    Sf, ASf = np.hstack(S), np.hstack(AS)
+    refB, refA = Sf.T @ Sf, Sf.T @ ASf
+    iu = np.triu_indices(Sf.shape[1])
+    np.testing.assert_allclose(SS[iu], refB[iu], rtol=0, atol=1e-13 * N)
+    np.testing.assert_allclose(SAS[iu], refA[iu], rtol=0, atol=1e-13 * N)
+    np.testing.assert_allclose(SS, SS.T)      # lower triangle mirrored
+
+
+@pytest.mark.parametrize("N,widths", [(4096, (8, 3, 3)), (70001, (32, 32, 32)), (5003, (5, 7, 2))])
+def test_gram_fp32(N, widths):
+    ctx = ctx_for((N, 1, 1), 32, None, L.MIXED)
+    S = [synth.random_block(N, w, seed=60 + i).astype(np.float32) for i, w in enumerate(widths)]
+    AS = [synth.random_block(N, w, seed=80 + i).astype(np.float32) for i, w in enumerate(widths)]
+    SS, SAS = L.lobpcg_gram(ctx, [dev(s, torch.float32) for s in S], [dev(a, torch.float32) for a in AS])
+    Sf, ASf = np.hstack(S).astype(np.float64), np.hstack(AS).astype(np.float64)
+    iu = np.triu_indices(Sf.shape[1])
+    # FP32 partial sums over 32-row chunks: error <= 32 eps32 sum |s||a|
+    bound = 32 * EPS32 * (np.abs(Sf).T @ np.abs(ASf))
+    assert np.all(np.abs(SAS - Sf.T @ ASf)[iu] <= bound[iu] + 1e-30)
+    boundB = 32 * EPS32 * (np.abs(Sf).T @ np.abs(Sf))
+    assert np.all(np.abs(SS - Sf.T @ Sf)[iu] <= boundB[iu] + 1e-30)
+
+
+def test_gram_single_block_without_AS():
+    N = 12345
+    ctx = ctx_for((N, 1, 1), 8)
+    S = synth.random_block(N, 8, seed=3)
+    SS, SAS = L.lobpcg_gram(ctx, [dev(S)])
+    assert SAS is None
+    np.testing.assert_allclose(SS, S.T @ S, rtol=0, atol=1e-13 * N)
+
+
+def test_gram_is_deterministic():
+    N = 300001
+    ctx = ctx_for((N, 1, 1), 16)
+    S = dev(synth.random_block(N, 16, seed=4))
+    a = L.lobpcg_gram(ctx, [S, S], [S, S])
+    b = L.lobpcg_gram(ctx, [S, S], [S, S])
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+# ---------------------------------------------------------------- combinations (steps 3-4, 11, 14-15, 27-32)
+
+@pytest.mark.parametrize("N,ks,kout,use_cols", [(5000, (8,), 8, False), (4099, (8, 3, 3), 8, False),
+                                                (70001, (32, 32, 32), 32, False), (1234, (6, 5), 4, True),
+                                                (9999, (7,), 7, True)])
+@pytest.mark.parametrize("prec", [L.FP64, L.MIXED])
+def test_combine(N, ks, kout, use_cols, prec):
+    ctx = ctx_for((N, 1, 1), 32, None, L.MIXED)
+    dtype = torch.float64 if prec == L.FP64 else torch.float32
+    rng = np.random.default_rng(N + kout)
+    ld = [k + (3 if use_cols else 0) for k in ks]
+    ins = [synth.random_block(N, l, seed=i + 100).astype(np.float32 if prec == L.MIXED else np.float64)
+           for i, l in enumerate(ld)]
+    cols = [np.sort(rng.choice(l, size=k, replace=False)) for l, k in zip(ld, ks)] if use_cols else None
+    C = rng.standard_normal((sum(ks), kout))
+    add = synth.random_block(N, kout, seed=99).astype(ins[0].dtype)
+    out = host(L.lobpcg_combine(ctx, [dev(x, dtype) for x in ins], C, kout, cols=cols, add=dev(add, dtype)))
+    sel = [x.astype(np.float64)[:, c] if cols else x.astype(np.float64) for x, c in zip(ins, cols or [None] * len(ins))]
+    ref = np.hstack(sel) @ (C.astype(np.float32).astype(np.float64) if prec == L.MIXED else C) + add
+    tol = 1e-14 if prec == L.FP64 else 4 * sum(ks) * EPS32
+    np.testing.assert_allclose(out, ref, rtol=0, atol=tol * (np.abs(np.hstack(sel)) @ np.abs(C)).max())
+
+
+# ---------------------------------------------------------------- residual and norms (steps 7-8)
+
+@pytest.mark.parametrize("N,m,J", [(4096, 4, [0, 1, 2, 3]), (70001, 32, list(range(0, 32, 3))), (999, 7, [6]),
+                                   (5000, 8, [])])
+@pytest.mark.parametrize("prec", [L.FP64, L.MIXED])
+def test_residual(N, m, J, prec):
+    ctx = ctx_for((N, 1, 1), m, None, L.MIXED)
+    npdt = np.float64 if prec == L.FP64 else np.float32
+    dtype = torch.float64 if prec == L.FP64 else torch.float32
+    X = synth.random_block(N, m, seed=1).astype(npdt)
+    AX = synth.random_block(N, m, seed=2).astype(npdt)
+    lam = np.linspace(0.1, 2.0, m)
+    W, rho = L.lobpcg_residual(ctx, dev(X, dtype), dev(AX, dtype), lam, J, 12.0)
+    R = AX.astype(np.float64) - X.astype(np.float64) * lam[None, :]
+    ref_rho = np.linalg.norm(R, axis=0) / (12.0 * np.linalg.norm(X.astype(np.float64), axis=0))
+    np.testing.assert_allclose(rho, ref_rho, rtol=1e-12)
+    if J:
+        np.testing.assert_allclose(host(W), R[:, J], rtol=0, atol=(1e-15 if prec == L.FP64 else 1e-7) * 3)
+
+
+# ---------------------------------------------------------------- eigenvalue adjoint
+
+@pytest.mark.parametrize("dims,m", [((12, 10, 8), 4), ((7, 9, 5), 3), ((32, 32, 32), 8)])
+def test_eig_grad_faces(dims, m):
+    N = int(np.prod(dims))
+    kx, ky, kz = synth.gaussian_field_faces(*dims, seed=3)
+    A = L.Op(*dims, dev(kx), dev(ky), dev(kz))
+    ctx = L.lobpcg_setup(A, L.Precond(None), m, L.FP64)
+    X = synth.random_block(N, m, seed=5)
+    gbar = np.linspace(-1, 2, m)
+    got = [host(t) for t in L.lobpcg_eig_grad_k(ctx, dev(X), gbar)]
+    ref = grid.eig_grad_faces(dims, X, gbar)
+    for a, b in zip(got, ref):
+        np.testing.assert_allclose(a, b, rtol=1e-13, atol=1e-13 * np.abs(b).max())

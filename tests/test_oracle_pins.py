@@ -429,3 +429,10 @@ def test_adjoint_scale_invariance():
     g2 = grid.eig_grad_faces(dims, V2[:, :2], np.ones(2))
     for a, b in zip(g1, g2):
         np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-13)
+
+
+def test_laplace7_rows_matches_full_operator():
+    dims = (7, 5, 6)
+    U = synth.random_block(210, 3, seed=21)
+    pts = np.array([0, 1, 6, 34, 35, 100, 209])
+    np.testing.assert_allclose(grid.laplace7_rows(dims, U, pts), grid.laplace7(dims, U)[pts], rtol=0, atol=1e-14)
