@@ -1,8 +1,5 @@
 // Multivector kernels of LOBPCG on point-major N x k blocks (gfx950):
-//  - combine: out = sum_i in_i[:, cols_i] C_i, the "X*C" products of steps
-//    3-4 (X R^-1, X Z), 11 and 14-15 (W R^-1, P_J R^-1) and the Ritz-vector
-//    update of steps 27-28 / 31-32, fused so that P and X (or AP and AX) come
-//    out of one pass over [X, W_J, P_J];
+//  - gather: packing a subset of a block's columns (the active set shrinks);
 //  - residual: W_J = AX_J - X_J Lambda_J (step 7) with the column norms that
 //    decide the active set (step 8), accumulated in FP64 in a fixed order;
 //  - casts between FP32 and FP64 blocks;
@@ -11,81 +8,6 @@
 #include "kernels.h"
 
 namespace lobpcg {
-
-template <typename T>
-struct CombineDev {
-    const T *in[3];
-    int ld[3], k[3];
-    const int *cols[3];
-    int nin, kout, ksum;
-    const T *C;
-    const T *add;
-    T *out, *out2;
-    i64 N;
-};
-
-// One thread owns V consecutive output columns of one grid point.  The
-// coefficients (and column maps) live in LDS; the input rows are read once per
-// point by the kout/V threads that share it (L1 broadcast).
-template <typename T, int V, bool OUT2>
-__global__ void __launch_bounds__(256) combine_kernel(CombineDev<T> a)
-{
-    extern __shared__ unsigned char smem[];
-    T *Cs = reinterpret_cast<T *>(smem);
-    int *cmap = reinterpret_cast<int *>(Cs + a.ksum * a.kout);
-    for (int i = threadIdx.x; i < a.ksum * a.kout; i += blockDim.x) Cs[i] = a.C[i];
-    {
-        int off = 0;
-        for (int b = 0; b < a.nin; b++) {
-            for (int r = threadIdx.x; r < a.k[b]; r += blockDim.x) cmap[off + r] = a.cols[b] ? a.cols[b][r] : r;
-            off += a.k[b];
-        }
-    }
-    __syncthreads();
-    const int L = a.kout / V;
-    const i64 total = a.N * L;
-    for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (i64)gridDim.x * blockDim.x) {
-        const int c = (int)(t % L);
-        const i64 p = t / L;
-        T acc[V], acc0[V];
-        if (a.add) {
-            vec<T, V> ad = vload<T, V>(a.add + p * a.kout + c * V);
-#pragma unroll
-            for (int q = 0; q < V; q++) acc[q] = ad.v[q];
-        } else {
-#pragma unroll
-            for (int q = 0; q < V; q++) acc[q] = T(0);
-        }
-#pragma unroll
-        for (int q = 0; q < V; q++) acc0[q] = T(0);
-        int roff = 0;
-        for (int b = 0; b < a.nin; b++) {
-            const T *row = a.in[b] + p * a.ld[b];
-            const int kb = a.k[b];
-            for (int r = 0; r < kb; r++) {
-                const T xv = row[cmap[roff + r]];
-                const T *cr = Cs + (roff + r) * a.kout + c * V;
-                if (OUT2 && b == 0) {
-#pragma unroll
-                    for (int q = 0; q < V; q++) acc0[q] += xv * cr[q];
-                } else {
-#pragma unroll
-                    for (int q = 0; q < V; q++) acc[q] += xv * cr[q];
-                }
-            }
-            roff += kb;
-        }
-        vec<T, V> o;
-#pragma unroll
-        for (int q = 0; q < V; q++) o.v[q] = acc[q];
-        vstore<T, V>(a.out + p * a.kout + c * V, o);
-        if (OUT2) {
-#pragma unroll
-            for (int q = 0; q < V; q++) o.v[q] = acc0[q] + acc[q];
-            vstore<T, V>(a.out2 + p * a.kout + c * V, o);
-        }
-    }
-}
 
 template <typename T>
 static int pick_vec(int k)
@@ -103,46 +25,32 @@ static unsigned stride_blocks(i64 total, unsigned cap = 8192)
     return (unsigned)(nb < cap ? nb : cap);
 }
 
-template <typename T, int V>
-static hipError_t run_combine(const CombineArgs &ha, hipStream_t st)
+// ---------------------------------------------------------------- column gather
+
+template <typename T>
+__global__ void __launch_bounds__(256) gather_cols_kernel(i64 N, const T *__restrict__ in, int ld,
+                                                          const int *__restrict__ map, int nout, T *__restrict__ out)
 {
-    CombineDev<T> a;
-    a.ksum = 0;
-    for (int i = 0; i < 3; i++) {
-        a.in[i] = (const T *)ha.in[i];
-        a.ld[i] = ha.ld[i];
-        a.k[i] = ha.k[i];
-        a.cols[i] = ha.cols[i];
-        if (i < ha.nin) a.ksum += ha.k[i];
+    const i64 total = N * nout;
+    for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (i64)gridDim.x * blockDim.x) {
+        const i64 p = t / nout;
+        const int j = (int)(t - p * nout);
+        out[t] = in[p * ld + map[j]];
     }
-    a.nin = ha.nin;
-    a.kout = ha.kout;
-    a.C = (const T *)ha.C;
-    a.add = (const T *)ha.add;
-    a.out = (T *)ha.out;
-    a.out2 = (T *)ha.out2;
-    a.N = ha.N;
-    const size_t shm = (size_t)a.ksum * a.kout * sizeof(T) + (size_t)a.ksum * sizeof(int) + 16;
-    const i64 total = a.N * (a.kout / V);
-    if (ha.out2)
-        hipLaunchKernelGGL((combine_kernel<T, V, true>), dim3(stride_blocks(total)), dim3(256), shm, st, a);
-    else
-        hipLaunchKernelGGL((combine_kernel<T, V, false>), dim3(stride_blocks(total)), dim3(256), shm, st, a);
-    return hipGetLastError();
 }
 
-hipError_t launch_combine(int dtype, const CombineArgs &a, hipStream_t st)
+hipError_t launch_gather_cols(int dtype, long long N, const void *in, int ld, const int *map, int nout, void *out,
+                              hipStream_t st)
 {
-    if (a.N == 0 || a.kout == 0) return hipSuccess;
-    if (dtype == DT_F32) {
-        switch (pick_vec<float>(a.kout)) {
-        case 4: return run_combine<float, 4>(a, st);
-        case 2: return run_combine<float, 2>(a, st);
-        default: return run_combine<float, 1>(a, st);
-        }
-    }
-    if (pick_vec<double>(a.kout) == 2) return run_combine<double, 2>(a, st);
-    return run_combine<double, 1>(a, st);
+    const i64 total = (i64)N * nout;
+    if (total == 0) return hipSuccess;
+    if (dtype == DT_F32)
+        hipLaunchKernelGGL(gather_cols_kernel<float>, dim3(stride_blocks(total, 65536)), dim3(256), 0, st, (i64)N,
+                           (const float *)in, ld, map, nout, (float *)out);
+    else
+        hipLaunchKernelGGL(gather_cols_kernel<double>, dim3(stride_blocks(total, 65536)), dim3(256), 0, st, (i64)N,
+                           (const double *)in, ld, map, nout, (double *)out);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- residual + norms
@@ -205,14 +113,22 @@ __global__ void __launch_bounds__(256) residual_kernel(const T *__restrict__ X, 
     }
 }
 
+// out[e] = sum over blocks of partials[b][e]: one workgroup per entry,
+// strided partial sums then a fixed-shape tree (a fixed order).
 __global__ void __launch_bounds__(256) reduce_partials_kernel(const double *__restrict__ partials, int nb, int width,
                                                               double *__restrict__ out)
 {
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < width; e += gridDim.x * blockDim.x) {
-        double s = 0.0;
-        for (int b = 0; b < nb; b++) s += partials[(i64)b * width + e];
-        out[e] = s;
+    __shared__ double red[256];
+    const int e = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) s += partials[(i64)b * width + e];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) out[e] = red[0];
 }
 
 template <typename T, int V>
@@ -227,8 +143,7 @@ static hipError_t run_residual(const ResidualArgs &a, hipStream_t st)
                        a.lambda, a.jpos, (T *)a.W, a.m, a.nJ, (i64)a.N, a.partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3((2 * a.m + 255) / 256), dim3(256), 0, st, a.partials, nb,
-                       2 * a.m, a.out);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(2 * a.m), dim3(256), 0, st, a.partials, nb, 2 * a.m, a.out);
     return hipGetLastError();
 }
 

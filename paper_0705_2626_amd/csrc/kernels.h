@@ -42,24 +42,45 @@ hipError_t launch_coarse_solve(int dtype, const Grid3 &g, int k, int sweeps, dou
                                const void *b, void *x, hipStream_t st);
 bool coarse_solve_fits(int dtype, const Grid3 &g);
 
-// ---- block kernels (k_block.hip)
-struct CombineArgs {
-    const void *in[3];
-    int ld[3];          // row length (columns) of each input
-    int k[3];           // columns used
-    const int *cols[3]; // device column maps (k[i] entries) or nullptr = columns 0..k-1
-    int nin;
-    const void *C;      // device, element type of the blocks, (sum k) x kout row-major
-    int kout;
-    const void *add;    // optional N x kout added to out
-    void *out;          // N x kout
-    void *out2;         // optional: out2 = in[0] C_0 + out, and then out = sum_{i>=1} in_i C_i
+// ---- block kernels (k_update.hip, k_block.hip)
+// Multivector products on MFMA (k_update.hip), for one side or two sides
+// (an X-side and an A-side with the same coefficients):
+//   out[s]  = sum_{i in I} in[s][i][:, cols_i] C_i (+ add on side 0),
+//             I = all inputs, or the inputs >= 1 when out2 is given;
+//             written only in columns c with opos[c] >= 0, at position opos[c]
+//   out2[s] = in[s][0] C_0 + (the full sum over inputs >= 1)
+// With partials/sums (needs two sides and out2) it also forms the residual
+// R = out2[1] - out2[0] diag(theta), writes its columns with wpos[c] >= 0 to
+// Wout (N x nW) and sums[c] = sum_p R_pc^2, sums[kout + c] = sum_p out2[0]_pc^2.
+struct MVArgs {
+    const void *in[2][3];
+    int ld[3], k[3];
+    const int *cols[3];
+    int nin, nside, kout;
+    const void *C;          // device, element type of the blocks, (sum k) x kout
+    const void *add;
+    void *out[2];
+    const int *opos;        // device [kout] or nullptr (identity, nout = kout)
+    int nout;
+    void *out2[2];
+    const double *theta;    // device [kout]
+    const int *wpos;        // device [kout]
+    void *Wout;
+    int nW;
+    double *partials;       // [mv_blocks(N)][2 kout]
+    double *sums;           // [2 kout]
     long long N;
 };
-hipError_t launch_combine(int dtype, const CombineArgs &a, hipStream_t st);
+int mv_blocks(long long N);
+hipError_t launch_mv(int dtype, const MVArgs &a, hipStream_t st);
 
-// Residual of step 7 with the norms of step 8.  Writes W (N x nJ packed, column
-// jj = column jmap_inv... see kernel) and per-block partial sums.
+// out[p][jj] = in[p][map[jj]] for jj < nout (in: N x ld)
+hipError_t launch_gather_cols(int dtype, long long N, const void *in, int ld, const int *map, int nout, void *out,
+                              hipStream_t st);
+
+// Residual of step 7 with the norms of step 8: W[:, jpos[j]] = AX_j - lambda_j X_j
+// for the columns with jpos[j] >= 0 (W: N x nJ), and per column the sums of
+// (AX_j - lambda_j X_j)^2 and X_j^2 (per-block partials, then reduced).
 struct ResidualArgs {
     const void *X, *AX;     // N x m
     const double *lambda;   // device [m]
@@ -80,13 +101,19 @@ hipError_t launch_eig_grad(const Grid3 &g, int m, const double *X, const double 
                            double *gkz, hipStream_t st);
 
 // ---- Gram products (k_gram.hip)
+// Tiles of S^T S (mat 0) and S^T AS (mat 1), S = [S_0 .. S_{nblk-1}] with
+// K = sum w <= 96 columns; tile codes (mat << 16) | (a << 8) | b cover rows
+// 16a..16a+15 and columns 16b..16b+15.
+static const int GRAM_MAX_TILES = 48;
 struct GramArgs {
-    const void *S[3], *AS[3];
+    const void *S[3], *AS[3];   // AS[0] == nullptr: S^T S only
     int w[3];
     int nblk;
+    int ntiles;
+    int tiles[GRAM_MAX_TILES];
     long long N;
     double *partials;   // scratch, gram_partials_bytes
-    double *out;        // device [2][Kp][Kp]: S^T S, S^T AS (upper tiles)
+    double *out;        // device [2][Kp][Kp], Kp = K rounded up to 16
 };
 int gram_kpad(int K);
 size_t gram_partials_bytes(int dtype, long long N, int K);

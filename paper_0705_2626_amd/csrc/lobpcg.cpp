@@ -44,7 +44,7 @@ struct Blocks {
 struct Layout {
     size_t blocks64, blocks32;          // offsets (or SIZE_MAX if absent)
     std::vector<size_t> mg;             // per level l >= 1: x, b, t (3 entries each)
-    size_t lambda, jpos, cols, coef, gram_out, gram_part, res_part, res_out, wvec;
+    size_t lambda, jpos, cols, coef, gram_out, gram_part, res_part, mv_part, res_out, wvec;
     size_t total;
     int mg_dtype;
     std::vector<Grid3> levels;
@@ -114,6 +114,7 @@ Layout make_layout(const lobpcg_op *A, const lobpcg_precond *T, int m, int preci
     L.gram_out = take((size_t)2 * Kp * Kp * 8);
     L.gram_part = take(gram_partials_bytes(DT_F64, N, K));
     L.res_part = take((size_t)residual_blocks(N, m) * 2 * m * 8);
+    L.mv_part = take((size_t)mv_blocks(N) * 2 * m * 8);
     L.res_out = take((size_t)2 * m * 8);
     L.wvec = take(sizeof(double) * m);
     L.total = align_up(off);
@@ -141,7 +142,7 @@ struct lobpcg_ctx {
     Blocks b64, b32;
     std::vector<void *> mgx, mgb, mgt;
     // small device areas
-    double *d_lambda, *d_gram_out, *d_gram_part, *d_res_part, *d_res_out, *d_w;
+    double *d_lambda, *d_gram_out, *d_gram_part, *d_res_part, *d_mv_part, *d_res_out, *d_w;
     int *d_jpos, *d_cols;
     char *d_coef;
     // pinned host staging
@@ -267,10 +268,34 @@ int apply_A(lobpcg_ctx *c, const lobpcg_op *A, int dt, const void *in, void *out
     return e == hipSuccess ? LOBPCG_OK : LOBPCG_ERR_HIP;
 }
 
+// Tiles to compute for S = [S_0 .. S_{n-1}] (widths w): every upper tile,
+// or with `paper` only those that meet an entry the paper's form does not
+// take as known: gramA outside the X-X block, gramB off the block diagonal.
+std::vector<int> gram_tiles(int n, const int *w, bool has_as, bool paper)
+{
+    int K = 0;
+    std::vector<int> blk;
+    for (int b = 0; b < n; b++)
+        for (int i = 0; i < w[b]; i++) blk.push_back(b), K++;
+    const int TK = gram_kpad(K) / 16;
+    std::vector<int> t;
+    for (int mat = 0; mat < (has_as ? 2 : 1); mat++)
+        for (int a = 0; a < TK; a++)
+            for (int b = a; b < TK; b++) {
+                bool need = !paper;
+                for (int i = 16 * a; i < std::min(K, 16 * a + 16) && !need; i++)
+                    for (int j = std::max(i, 16 * b); j < std::min(K, 16 * b + 16) && !need; j++)
+                        need = mat ? !(blk[i] == 0 && blk[j] == 0) : blk[i] < blk[j];
+                if (need) t.push_back((mat << 16) | (a << 8) | b);
+            }
+    return t;
+}
+
 // Gram products; returns K x K host matrices (row-major), upper triangle
-// mirrored.  SAS may be null when AS is not given.
+// mirrored (entries of tiles not computed are zero).  SAS may be null when AS
+// is not given.
 int gram(lobpcg_ctx *c, int dt, int n, const void *const *S, const void *const *AS, const int *w,
-         std::vector<double> &SS, std::vector<double> *SAS, int step)
+         std::vector<double> &SS, std::vector<double> *SAS, int step, bool paper = false)
 {
     GramArgs a;
     int K = 0;
@@ -280,15 +305,21 @@ int gram(lobpcg_ctx *c, int dt, int n, const void *const *S, const void *const *
         a.w[i] = i < n ? w[i] : 0;
         if (i < n) K += w[i];
     }
+    std::vector<int> tl = gram_tiles(n, w, AS != nullptr, paper);
+    if (tl.empty() || (int)tl.size() > GRAM_MAX_TILES) return LOBPCG_ERR_ARG;
+    a.ntiles = (int)tl.size();
+    std::copy(tl.begin(), tl.end(), a.tiles);
     a.nblk = n;
     a.N = c->N;
     a.partials = c->d_gram_part;
     a.out = c->d_gram_out;
     const int Kp = gram_kpad(K);
+    const size_t bytes = (size_t)(AS ? 2 : 1) * Kp * Kp * 8;
+    // tiles that are not computed read as zero
+    HIPCHK(hipMemsetAsync(c->d_gram_out, 0, bytes, c->st));
     prof_begin(c, step);
     if (launch_gram(dt, a, c->st) != hipSuccess) return LOBPCG_ERR_HIP;
     prof_end(c);
-    const size_t bytes = (size_t)(AS ? 2 : 1) * Kp * Kp * 8;
     double *h = (double *)(c->h_pin + c->h_gram_off);
     HIPCHK(hipMemcpyAsync(h, c->d_gram_out, bytes, hipMemcpyDeviceToHost, c->st));
     int s = sync(c);
@@ -303,31 +334,77 @@ int gram(lobpcg_ctx *c, int dt, int n, const void *const *S, const void *const *
     return LOBPCG_OK;
 }
 
-// out = sum_i in_i[:, cols_i] C_i (+ add); optional out2 (see CombineArgs).
-int combine(lobpcg_ctx *c, int dt, int n, const void *const *in, const int *ld, const int *const *cols,
-            const int *k, const double *C, int kout, const void *add, void *out, void *out2, int step)
-{
-    CombineArgs a;
-    int ks = 0;
-    for (int i = 0; i < 3; i++) {
-        a.in[i] = i < n ? in[i] : nullptr;
-        a.ld[i] = i < n ? ld[i] : 0;
-        a.k[i] = i < n ? k[i] : 0;
-        a.cols[i] = i < n && cols ? cols[i] : nullptr;
-        if (i < n) ks += k[i];
+// One multivector-product launch (see MVArgs); C is the host FP64
+// coefficient matrix ((sum k_i) x kout, row-major), uploaded in the blocks'
+// precision.
+struct MV {
+    int nside = 1, nin = 0, kout = 0;
+    const void *in[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    int ld[3] = {0, 0, 0}, k[3] = {0, 0, 0};
+    const int *cols[3] = {nullptr, nullptr, nullptr};
+    const void *add = nullptr;
+    void *out[2] = {nullptr, nullptr}, *out2[2] = {nullptr, nullptr};
+    const int *opos = nullptr;
+    int nout = 0;
+    const double *theta = nullptr;
+    const int *wpos = nullptr;
+    void *Wout = nullptr;
+    int nW = 0;
+    bool resid = false;
+    void input(int i, const void *x, const void *ax, int ldi, int ki, const int *cl = nullptr)
+    {
+        in[0][i] = x;
+        in[1][i] = ax;
+        ld[i] = ldi;
+        k[i] = ki;
+        cols[i] = cl;
+        if (i + 1 > nin) nin = i + 1;
     }
-    a.nin = n;
-    a.kout = kout;
-    a.add = add;
-    a.out = out;
-    a.out2 = out2;
+};
+
+int mv(lobpcg_ctx *c, int dt, const MV &q, const double *C, int step)
+{
+    MVArgs a;
+    int K = 0;
+    for (int s2 = 0; s2 < 2; s2++)
+        for (int i = 0; i < 3; i++) a.in[s2][i] = q.in[s2][i];
+    for (int i = 0; i < 3; i++) {
+        a.ld[i] = q.ld[i];
+        a.k[i] = i < q.nin ? q.k[i] : 0;
+        a.cols[i] = q.cols[i];
+        K += a.k[i];
+    }
+    a.nin = q.nin;
+    a.nside = q.nside;
+    a.kout = q.kout;
+    a.add = q.add;
+    for (int s2 = 0; s2 < 2; s2++) {
+        a.out[s2] = q.out[s2];
+        a.out2[s2] = q.out2[s2];
+    }
+    a.opos = q.opos;
+    a.nout = q.nout;
+    a.theta = q.theta;
+    a.wpos = q.wpos;
+    a.Wout = q.Wout;
+    a.nW = q.nW;
+    a.partials = q.resid ? c->d_mv_part : nullptr;
+    a.sums = q.resid ? c->d_res_out : nullptr;
     a.N = c->N;
-    int s = upload_coef(c, dt, C, ks, kout, &a.C);
+    int s = upload_coef(c, dt, C, K, q.kout, &a.C);
     if (s) return s;
     prof_begin(c, step);
-    hipError_t e = launch_combine(dt, a, c->st);
+    hipError_t e = launch_mv(dt, a, c->st);
     prof_end(c);
     return e == hipSuccess ? LOBPCG_OK : LOBPCG_ERR_HIP;
+}
+
+int upload_doubles(lobpcg_ctx *c, const std::vector<double> &v, const double **dptr)
+{
+    const void *d;
+    int s = upload_coef(c, DT_F64, v.data(), 1, (int)v.size(), &d);
+    *dptr = (const double *)d;
+    return s;
 }
 
 // Residual of step 7 over the m columns of (X, AX) with Ritz values lam;
@@ -479,23 +556,46 @@ double op_norm(lobpcg_ctx *c, const lobpcg_op *A)
 struct PhaseState {
     int cur;                  // which X/AX buffer is current
     std::vector<double> lam;  // Ritz values
-    std::vector<int> J;       // active set
-    bool hasP;
+    std::vector<int> J;       // active set (step 8)
+    std::vector<int> Pcols;   // the columns held (packed, in this order) by B.P / B.AP
+    bool have_res;            // B.W holds W_J and d_res_out the norms for X[cur], AX[cur], lam
 };
 
 enum { PH_CONVERGED, PH_MAXIT, PH_SWITCH };
+
+std::vector<int> positions(const std::vector<int> &sub, const std::vector<int> &in)
+{
+    std::vector<int> pos;
+    for (int j : sub) {
+        auto it = std::find(in.begin(), in.end(), j);
+        pos.push_back(it == in.end() ? -1 : (int)(it - in.begin()));
+    }
+    return pos;
+}
 
 int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &ps, double tol, double normA,
               int maxit, int &iters, double *h_hist, bool explicit_gram, bool allow_switch, int &outcome)
 {
     const int m = c->m;
-    std::vector<double> rr, xx, rho(m), SS, SAS, PP;
+    std::vector<double> rr(m), xx(m), rho(m), SS, SAS, PP;
     std::vector<double> hist_max;
     outcome = PH_MAXIT;
     while (iters < maxit) {
-        // step 7 for the current active set (W_J written packed), norms for all m
-        int s = residual(c, dt, B.X[ps.cur], B.AX[ps.cur], ps.lam, ps.J, B.W, rr, xx);
-        if (s) return s;
+        // steps 7-8: W_J and the residual norms of all m columns; after an
+        // update they come from the fused update kernel
+        int s;
+        if (ps.have_res) {
+            double *h = (double *)(c->h_pin + c->h_res_off);
+            HIPCHK(hipMemcpyAsync(h, c->d_res_out, 2 * m * 8, hipMemcpyDeviceToHost, c->st));
+            s = sync(c);
+            if (s) return s;
+            rr.assign(h, h + m);
+            xx.assign(h + m, h + 2 * m);
+        } else {
+            s = residual(c, dt, B.X[ps.cur], B.AX[ps.cur], ps.lam, ps.J, B.W, rr, xx);
+            if (s) return s;
+        }
+        ps.have_res = false;
         double rmax = 0.0;
         for (int j = 0; j < m; j++) {
             rho[j] = std::sqrt(rr[j]) / (normA * std::sqrt(xx[j]));
@@ -526,10 +626,24 @@ int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &
             }
         }
         if (Jn != ps.J) {
-            // W was written for the previous active set: write it again for Jn
-            ps.J = Jn;
-            s = residual(c, dt, B.X[ps.cur], B.AX[ps.cur], ps.lam, ps.J, B.W, rr, xx);
-            if (s) return s;
+            std::vector<int> pos = positions(Jn, ps.J);
+            if (std::find(pos.begin(), pos.end(), -1) == pos.end()) {
+                // the active set shrank: pack the surviving columns of W
+                const int *dmap;
+                s = upload_cols(c, pos, &dmap);
+                if (s) return s;
+                prof_begin(c, LOBPCG_STEP_RESIDUAL);
+                hipError_t e = launch_gather_cols(dt, c->N, B.W, (int)ps.J.size(), dmap, (int)Jn.size(), B.T0, c->st);
+                prof_end(c);
+                if (e != hipSuccess) return LOBPCG_ERR_HIP;
+                std::swap(B.W, B.T0);
+                ps.J = Jn;
+            } else {
+                // columns made active again: form W for the new set
+                ps.J = Jn;
+                s = residual(c, dt, B.X[ps.cur], B.AX[ps.cur], ps.lam, ps.J, B.W, rr, xx);
+                if (s) return s;
+            }
         }
         const int nJ = (int)ps.J.size();
         // step 9: W_J = T W_J
@@ -555,51 +669,64 @@ int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &
                 return LOBPCG_ERR_CHOL;
             }
             void *dst = (Wt == B.W) ? B.T0 : B.W;
-            const void *in1[1] = {Wt};
-            int ld1[1] = {nJ}, k1[1] = {nJ};
-            s = combine(c, dt, 1, in1, ld1, nullptr, k1, Ri.data(), nJ, nullptr, dst, nullptr, LOBPCG_STEP_ORTHO);
+            MV q;
+            q.input(0, Wt, nullptr, nJ, nJ);
+            q.kout = nJ;
+            q.out[0] = dst;
+            s = mv(c, dt, q, Ri.data(), LOBPCG_STEP_ORTHO);
             if (s) return s;
             if (dst == B.T0) std::swap(B.W, B.T0);
         }
         // step 12: AW_J = A W_J
         s = apply_A(c, A, dt, B.W, B.AW, nJ);
         if (s) return s;
-        // steps 13-16: orthonormalise P_J, AP_J
-        bool useP = false;
-        if (ps.hasP) {
+        // steps 13-16: orthonormalise the directions of the active columns
+        // that have one (P holds the columns ps.Pcols)
+        std::vector<int> Jp, ppos;
+        for (int j : ps.J) {
+            auto it = std::find(ps.Pcols.begin(), ps.Pcols.end(), j);
+            if (it != ps.Pcols.end()) {
+                Jp.push_back(j);
+                ppos.push_back((int)(it - ps.Pcols.begin()));
+            }
+        }
+        int nP = 0;
+        if (!Jp.empty()) {
+            const int np = (int)ps.Pcols.size();
             const void *Sb[1] = {B.P};
-            int w1[1] = {m};
+            int w1[1] = {np};
             s = gram(c, dt, 1, Sb, nullptr, w1, PP, nullptr, LOBPCG_STEP_ORTHO);
             if (s) return s;
-            std::vector<double> G((size_t)nJ * nJ), Ri;
-            for (int i = 0; i < nJ; i++)
-                for (int j = 0; j < nJ; j++) G[(size_t)i * nJ + j] = PP[(size_t)ps.J[i] * m + ps.J[j]];
-            if (all_finite(G) && chol_inv(nJ, G, Ri)) {
+            const int k = (int)Jp.size();
+            std::vector<double> G((size_t)k * k), Ri;
+            for (int i = 0; i < k; i++)
+                for (int j = 0; j < k; j++) G[(size_t)i * k + j] = PP[(size_t)ppos[i] * np + ppos[j]];
+            if (all_finite(G) && chol_inv(k, G, Ri)) {
                 const int *dcols;
-                s = upload_cols(c, ps.J, &dcols);
+                s = upload_cols(c, ppos, &dcols);
                 if (s) return s;
-                const void *in1[1] = {B.P};
-                int ld1[1] = {m}, k1[1] = {nJ};
-                const int *cl[1] = {dcols};
-                s = combine(c, dt, 1, in1, ld1, cl, k1, Ri.data(), nJ, nullptr, B.PJ, nullptr, LOBPCG_STEP_ORTHO);
+                MV q;
+                q.nside = 2;
+                q.input(0, B.P, B.AP, np, k, dcols);
+                q.kout = k;
+                q.out[0] = B.PJ;
+                q.out[1] = B.APJ;
+                s = mv(c, dt, q, Ri.data(), LOBPCG_STEP_ORTHO);
                 if (s) return s;
-                const void *in2[1] = {B.AP};
-                s = combine(c, dt, 1, in2, ld1, cl, k1, Ri.data(), nJ, nullptr, B.APJ, nullptr, LOBPCG_STEP_ORTHO);
-                if (s) return s;
-                useP = true;
+                nP = k;
             } else {
                 c->stats.restarts++;
             }
         }
         // steps 17-23: Gram matrices of the trial basis [X, W_J, P_J]
-        const int nb = useP ? 3 : 2;
+        const int nb = nP ? 3 : 2;
         const void *Sb[3] = {B.X[ps.cur], B.W, B.PJ};
         const void *ASb[3] = {B.AX[ps.cur], B.AW, B.APJ};
-        int wb[3] = {m, nJ, nJ};
-        s = gram(c, dt, nb, Sb, ASb, wb, SS, &SAS, LOBPCG_STEP_GRAM);
+        int wb[3] = {m, nJ, nP};
+        s = gram(c, dt, nb, Sb, ASb, wb, SS, &SAS, LOBPCG_STEP_GRAM, !explicit_gram);
         if (s) return s;
         if (!all_finite(SS) || !all_finite(SAS)) return LOBPCG_ERR_NONFINITE;
-        const int K = m + (nb - 1) * nJ;
+        const int K = m + nJ + nP;
         std::vector<double> gA(SAS), gB(SS);
         if (!explicit_gram) {
             // the paper's form: Lambda and identities on the block diagonal
@@ -611,7 +738,7 @@ int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &
             blk(0, m, gA, true);
             blk(0, m, gB, false);
             blk(m, nJ, gB, false);
-            if (useP) blk(m + nJ, nJ, gB, false);
+            if (nP) blk(m + nJ, nP, gB, false);
         }
         // step 24 (on failure with P, retry on the leading [X, W_J] part)
         std::vector<double> theta(m), C;
@@ -619,8 +746,8 @@ int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &
         bool ok = false;
         for (int attempt = 0; attempt < 2 && !ok; attempt++) {
             if (attempt == 1) {
-                if (!useP) break;
-                useP = false;
+                if (!nP) break;
+                nP = 0;
                 c->stats.restarts++;
                 Kused = m + nJ;
             }
@@ -644,25 +771,47 @@ int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &
             }
             return LOBPCG_ERR_RR;
         }
-        // steps 25-33: P = W_J C_W + P_J C_P, X = X C_X + P (and the A-side)
-        const int nu = useP ? 3 : 2;
-        const void *inX[3] = {B.X[ps.cur], B.W, B.PJ};
-        const void *inA[3] = {B.AX[ps.cur], B.AW, B.APJ};
-        int ld[3] = {m, nJ, nJ}, kk[3] = {m, nJ, nJ};
-        s = combine(c, dt, nu, inX, ld, nullptr, kk, C.data(), m, nullptr, B.P, B.X[1 - ps.cur], LOBPCG_STEP_UPDATE);
+        // steps 25-33 fused with step 7 of the next iteration:
+        //   P = W_J C_W + P_J C_P, X' = X C_X + P (and AP, AX'); P and AP are
+        //   stored for the active columns only; W = AX'_J - X'_J Theta_J
+        std::vector<int> jpos(m, -1);
+        for (int i = 0; i < nJ; i++) jpos[ps.J[i]] = i;
+        const int *djpos;
+        const double *dtheta;
+        s = upload_cols(c, jpos, &djpos);
         if (s) return s;
-        s = combine(c, dt, nu, inA, ld, nullptr, kk, C.data(), m, nullptr, B.AP, B.AX[1 - ps.cur],
-                    LOBPCG_STEP_UPDATE);
+        s = upload_doubles(c, theta, &dtheta);
         if (s) return s;
+        MV q;
+        q.nside = 2;
+        q.input(0, B.X[ps.cur], B.AX[ps.cur], m, m);
+        q.input(1, B.W, B.AW, nJ, nJ);
+        if (nP) q.input(2, B.PJ, B.APJ, nP, nP);
+        q.kout = m;
+        q.out[0] = B.P;
+        q.out[1] = B.AP;
+        q.opos = djpos;
+        q.nout = nJ;
+        q.out2[0] = B.X[1 - ps.cur];
+        q.out2[1] = B.AX[1 - ps.cur];
+        q.resid = true;
+        q.theta = dtheta;
+        q.wpos = djpos;
+        q.Wout = B.T0;
+        q.nW = nJ;
+        s = mv(c, dt, q, C.data(), LOBPCG_STEP_UPDATE);
+        if (s) return s;
+        std::swap(B.W, B.T0);
+        ps.Pcols = ps.J;
         ps.cur = 1 - ps.cur;
         ps.lam = theta;
-        ps.hasP = true;
+        ps.have_res = true;
     }
     return LOBPCG_OK;
 }
 
-// Steps 3-4 (and the FP64 restart of the mixed solver): orthonormalise X if
-// asked, A X, Rayleigh-Ritz on span(X).  On entry X is in B.X[ps.cur].
+// Steps 3-4 (and the restart of the mixed solver in FP64): orthonormalise X
+// if asked, A X, Rayleigh-Ritz on span(X).  On entry X is in B.X[ps.cur].
 int init_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &ps, bool ortho, bool explicit_gram)
 {
     const int m = c->m;
@@ -676,10 +825,11 @@ int init_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState 
         if (!all_finite(SS)) return LOBPCG_ERR_NONFINITE;
         std::vector<double> Ri;
         if (!chol_inv(m, SS, Ri)) return LOBPCG_ERR_CHOL;
-        const void *in1[1] = {B.X[ps.cur]};
-        int ld1[1] = {m}, k1[1] = {m};
-        s = combine(c, dt, 1, in1, ld1, nullptr, k1, Ri.data(), m, nullptr, B.X[1 - ps.cur], nullptr,
-                    LOBPCG_STEP_ORTHO);
+        MV q;
+        q.input(0, B.X[ps.cur], nullptr, m, m);
+        q.kout = m;
+        q.out[0] = B.X[1 - ps.cur];
+        s = mv(c, dt, q, Ri.data(), LOBPCG_STEP_ORTHO);
         if (s) return s;
         ps.cur = 1 - ps.cur;
     }
@@ -696,17 +846,19 @@ int init_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState 
     }
     std::vector<double> theta(m), Z((size_t)m * m);
     if (!rayleigh_ritz(m, m, SAS.data(), SS.data(), theta.data(), Z.data())) return LOBPCG_ERR_RR;
-    const void *in1[1] = {B.X[ps.cur]}, *in2[1] = {B.AX[ps.cur]};
-    int ld1[1] = {m}, k1[1] = {m};
-    s = combine(c, dt, 1, in1, ld1, nullptr, k1, Z.data(), m, nullptr, B.X[1 - ps.cur], nullptr, LOBPCG_STEP_OTHER);
-    if (s) return s;
-    s = combine(c, dt, 1, in2, ld1, nullptr, k1, Z.data(), m, nullptr, B.AX[1 - ps.cur], nullptr, LOBPCG_STEP_OTHER);
+    MV q;
+    q.nside = 2;
+    q.input(0, B.X[ps.cur], B.AX[ps.cur], m, m);
+    q.kout = m;
+    q.out[0] = B.X[1 - ps.cur];
+    q.out[1] = B.AX[1 - ps.cur];
+    s = mv(c, dt, q, Z.data(), LOBPCG_STEP_OTHER);
     if (s) return s;
     ps.cur = 1 - ps.cur;
     ps.lam = theta;
     ps.J.clear();
     for (int j = 0; j < m; j++) ps.J.push_back(j);
-    ps.hasP = false;
+    ps.have_res = false;
     return LOBPCG_OK;
 }
 
@@ -781,6 +933,7 @@ int lobpcg_setup(lobpcg_ctx **out, const lobpcg_op *A, const lobpcg_op *B, const
     c->d_gram_out = (double *)(c->ws + L.gram_out);
     c->d_gram_part = (double *)(c->ws + L.gram_part);
     c->d_res_part = (double *)(c->ws + L.res_part);
+    c->d_mv_part = (double *)(c->ws + L.mv_part);
     c->d_res_out = (double *)(c->ws + L.res_out);
     c->d_w = (double *)(c->ws + L.wvec);
     // pinned host staging
@@ -890,6 +1043,7 @@ int lobpcg_solve(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, const lo
     int iters = 0, s = LOBPCG_OK, outcome = PH_MAXIT;
     PhaseState ps;
     ps.cur = 0;
+    ps.have_res = false;
     if (c->precision == LOBPCG_MIXED) {
         // FP32 phase
         prof_begin(c, LOBPCG_STEP_OTHER);
@@ -901,11 +1055,19 @@ int lobpcg_solve(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, const lo
                           true, true, outcome);
         }
         if (s == LOBPCG_OK) {
-            // FP64 phase: up-cast X, explicit A X, Rayleigh-Ritz on span(X), P reset
+            // FP64 phase: up-cast X and the directions P, form A X and A P
+            // explicitly in FP64, Rayleigh-Ritz on span(X); P is kept
             prof_begin(c, LOBPCG_STEP_OTHER);
             if (launch_cast(DT_F32, DT_F64, nm, c->b32.X[ps.cur], c->b64.X[0], c->st) != hipSuccess)
                 return LOBPCG_ERR_HIP;
+            const int np = (int)ps.Pcols.size();
+            if (np && launch_cast(DT_F32, DT_F64, (size_t)c->N * np, c->b32.P, c->b64.P, c->st) != hipSuccess)
+                return LOBPCG_ERR_HIP;
             prof_end(c);
+            if (np) {
+                s = apply_A(c, A, DT_F64, c->b64.P, c->b64.AP, np);
+                if (s) return s;
+            }
             ps.cur = 0;
             s = init_phase(c, A, DT_F64, c->b64, ps, false, true);
             if (s == LOBPCG_OK)
@@ -1030,24 +1192,28 @@ int lobpcg_combine(lobpcg_ctx *c, int dt, int n, const void *const *in, const in
     if (!c || !dtype_ok(c, dt) || n < 1 || n > 3 || !in || !ld || !k || !h_C || !d_out || kout < 1 || kout > c->m)
         return LOBPCG_ERR_ARG;
     int ks = 0;
-    std::vector<const int *> dcols(3, nullptr);
+    MV q;
     for (int i = 0; i < n; i++) {
-        if (!in[i] || ld[i] < 1 || k[i] < 1 || in[i] == d_out) return LOBPCG_ERR_ARG;
+        if (!in[i] || ld[i] < 1 || ld[i] > LOBPCG_MAX_M || k[i] < 1 || in[i] == d_out) return LOBPCG_ERR_ARG;
+        const int *dcol = nullptr;
         if (cols && cols[i]) {
             std::vector<int> cv(cols[i], cols[i] + k[i]);
             for (int x : cv)
                 if (x < 0 || x >= ld[i]) return LOBPCG_ERR_ARG;
             if ((int)cv.size() > c->m) return LOBPCG_ERR_ARG;
-            int s = upload_cols(c, cv, &dcols[i]);
+            int s = upload_cols(c, cv, &dcol);
             if (s) return s;
         } else if (k[i] != ld[i]) {
             return LOBPCG_ERR_ARG;
         }
+        q.input(i, in[i], nullptr, ld[i], k[i], dcol);
         ks += k[i];
     }
     if (ks > 3 * c->m) return LOBPCG_ERR_ARG;
-    int s = combine(c, dt == LOBPCG_F32 ? DT_F32 : DT_F64, n, in, ld, dcols.data(), k, h_C, kout, d_add, d_out,
-                    nullptr, LOBPCG_STEP_UPDATE);
+    q.kout = kout;
+    q.add = d_add;
+    q.out[0] = d_out;
+    int s = mv(c, dt == LOBPCG_F32 ? DT_F32 : DT_F64, q, h_C, LOBPCG_STEP_UPDATE);
     if (s) return s;
     return sync(c);
 }

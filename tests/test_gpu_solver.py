@@ -47,8 +47,8 @@ def test_fp64_unpreconditioned_n16_matches_oracle():
     assert r.resid.max() <= tol
     # without a preconditioner the degenerate triple lambda_2..4 converges
     # slowly and the iteration at which each of its columns crosses tol (and
-    # is locked or re-activated) flips on rounding: allow 3% of the count
-    assert abs(r.iters - ref.iters) <= max(2, 0.03 * ref.iters), (r.iters, ref.iters)
+    # is locked or re-activated) flips on rounding: allow 5% of the count
+    assert abs(r.iters - ref.iters) <= max(2, 0.05 * ref.iters), (r.iters, ref.iters)
     # residual histories follow the oracle's while they are well above rounding
     k = min(30, r.iters, ref.iters)
     np.testing.assert_allclose(r.hist[:k], ref.hist[:k], rtol=1e-5)
