@@ -130,7 +130,15 @@ enum {
     LOBPCG_OPT_STALL_WINDOW = 1,    /* MIXED: ... or when max rho fell by less than      */
     LOBPCG_OPT_STALL_FACTOR = 2,    /*        STALL_FACTOR over STALL_WINDOW iterations  */
     LOBPCG_OPT_PROFILE = 3,         /* 1: time each step class with HIP events          */
-    LOBPCG_OPT_REACTIVATE = 4       /* 1 (default): see lobpcg_solve's stopping rule    */
+    LOBPCG_OPT_REACTIVATE = 4,      /* 1 (default): see lobpcg_solve's stopping rule    */
+    LOBPCG_OPT_KERNELS = 5,         /* kernel variants: bit 0 multivector products     */
+                                    /* loading MFMA fragments straight from global     */
+                                    /* memory, bit 1 multi-column-tile Gram kernel     */
+                                    /* for narrow Grams too; 0 = default; results      */
+                                    /* agree to rounding                               */
+    LOBPCG_OPT_FP32_EXPLICIT_GRAM = 6 /* MIXED: 1 (default) FP32 iterations compute    */
+                                    /* X^T X, X^T AX, W^T W, P^T P rather than taking  */
+                                    /* I and Lambda for them as the paper's form does  */
 };
 int lobpcg_set_option(lobpcg_ctx *ctx, int key, double value);
 

@@ -177,6 +177,88 @@ __global__ void __launch_bounds__(512) gram_kernel(GramDev<T> a)
     }
 }
 
+// A single narrow block (S^T S for W_J or P_J with at most 8 columns, the
+// Cholesky Gram matrices of steps 11 and 14): one grid row per thread, the
+// W(W+1)/2 products accumulated in FP64, then summed across each wave with a
+// fixed xor-shuffle butterfly and across the waves in a fixed order.
+static const int RBLOCKS = 1024;
+
+template <typename T, int W>
+__global__ void __launch_bounds__(256) gram_rows_kernel(const T *__restrict__ S, i64 N, double *__restrict__ partials)
+{
+    const int NP = W * (W + 1) / 2;
+    __shared__ double red[4][NP];
+    double acc[NP];
+#pragma unroll
+    for (int q = 0; q < NP; q++) acc[q] = 0.0;
+    for (i64 r = (i64)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (i64)gridDim.x * blockDim.x) {
+        double v[W];
+#pragma unroll
+        for (int c = 0; c < W; c++) v[c] = (double)S[r * W + c];
+        int q = 0;
+#pragma unroll
+        for (int i = 0; i < W; i++)
+#pragma unroll
+            for (int j = i; j < W; j++, q++) acc[q] += v[i] * v[j];
+    }
+#pragma unroll
+    for (int q = 0; q < NP; q++)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off, 64);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < NP; q++) red[wave][q] = acc[q];
+    __syncthreads();
+    for (int q = threadIdx.x; q < NP; q += blockDim.x)
+        partials[(i64)blockIdx.x * NP + q] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+}
+
+// out[i][j] (Kp x Kp) for i <= j from the per-workgroup pair sums: one
+// workgroup per pair, strided sums then a fixed tree.
+__global__ void __launch_bounds__(256) gram_rows_reduce_kernel(const double *__restrict__ partials, int nb, int W,
+                                                               int Kp, double *__restrict__ out)
+{
+    __shared__ double red[256];
+    const int q = blockIdx.x, NP = W * (W + 1) / 2;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) s += partials[(i64)b * NP + q];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        int i = 0, rem = q;
+        while (rem >= W - i) rem -= W - i, i++;
+        out[(i64)i * Kp + i + rem] = red[0];
+    }
+}
+
+template <typename T>
+static hipError_t run_gram_rows(const GramArgs &h, hipStream_t st)
+{
+    const int W = h.w[0], Kp = gram_kpad(W);
+    const i64 nb64 = (h.N + 255) / 256;
+    const int nb = (int)(nb64 < RBLOCKS ? (nb64 > 0 ? nb64 : 1) : RBLOCKS);
+    const T *S = (const T *)h.S[0];
+    switch (W) {
+    case 1: hipLaunchKernelGGL((gram_rows_kernel<T, 1>), dim3(nb), dim3(256), 0, st, S, (i64)h.N, h.partials); break;
+    case 2: hipLaunchKernelGGL((gram_rows_kernel<T, 2>), dim3(nb), dim3(256), 0, st, S, (i64)h.N, h.partials); break;
+    case 3: hipLaunchKernelGGL((gram_rows_kernel<T, 3>), dim3(nb), dim3(256), 0, st, S, (i64)h.N, h.partials); break;
+    case 4: hipLaunchKernelGGL((gram_rows_kernel<T, 4>), dim3(nb), dim3(256), 0, st, S, (i64)h.N, h.partials); break;
+    case 5: hipLaunchKernelGGL((gram_rows_kernel<T, 5>), dim3(nb), dim3(256), 0, st, S, (i64)h.N, h.partials); break;
+    case 6: hipLaunchKernelGGL((gram_rows_kernel<T, 6>), dim3(nb), dim3(256), 0, st, S, (i64)h.N, h.partials); break;
+    case 7: hipLaunchKernelGGL((gram_rows_kernel<T, 7>), dim3(nb), dim3(256), 0, st, S, (i64)h.N, h.partials); break;
+    default: hipLaunchKernelGGL((gram_rows_kernel<T, 8>), dim3(nb), dim3(256), 0, st, S, (i64)h.N, h.partials);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gram_rows_reduce_kernel, dim3(W * (W + 1) / 2), dim3(256), 0, st, h.partials, nb, W, Kp, h.out);
+    return hipGetLastError();
+}
+
 // out[mat][i][j] (Kp x Kp each) = sum over workgroups: one workgroup per
 // group of 64 tile entries, each entry summed by 4 threads in strided order
 // and then combined in a fixed order, so the result never changes.
@@ -217,12 +299,15 @@ size_t gram_partials_bytes(int dtype, long long N, int K)
     (void)dtype;
     const int TK = gram_kpad(K) / 16;
     const size_t ntiles = (size_t)TK * (TK + 1);
-    return (size_t)gram_blocks(N) * ntiles * 256 * sizeof(double);
+    const size_t staged = (size_t)gram_blocks(N) * ntiles * 256 * sizeof(double);
+    const size_t rows = (size_t)RBLOCKS * 36 * sizeof(double);
+    return staged > rows ? staged : rows;
 }
 
 template <typename T>
 static hipError_t run_gram(const GramArgs &h, hipStream_t st)
 {
+    if (!h.staged && h.nblk == 1 && !h.AS[0] && h.w[0] >= 1 && h.w[0] <= 8) return run_gram_rows<T>(h, st);
     GramDev<T> a;
     int K = 0;
     for (int b = 0; b < 3; b++) {
@@ -249,7 +334,8 @@ static hipError_t run_gram(const GramArgs &h, hipStream_t st)
     }
     a.N = h.N;
     a.partials = h.partials;
-    const int nb = gram_blocks(h.N);
+    int nb;
+    nb = gram_blocks(h.N);
     const int ngroups = (a.ntiles + TILES_PER_GROUP - 1) / TILES_PER_GROUP;
     const size_t shm = (size_t)2 * GramRC<T>::v * (a.Kp + PAD) * sizeof(T);
     hipLaunchKernelGGL(gram_kernel<T>, dim3(nb, ngroups), dim3(64 * WAVES), shm, st, a);

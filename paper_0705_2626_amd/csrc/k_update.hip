@@ -11,19 +11,26 @@
 // in registers, the next residual W = AX' - X' Theta of step 7 with the FP64
 // column sums of squares that decide the active set of step 8.
 //
-// A workgroup (4 waves) walks tiles of 64 grid points; every input block of a
-// tile is staged in LDS with a coalesced pass and each wave multiplies its 16
-// points by the coefficients (also in LDS) with 16x16x4 MFMA, NT 16-column
-// output tiles at a time.  Per-workgroup partial sums of the norms are added in
-// a fixed order by a second kernel.
+// A workgroup (4 waves) walks tiles of 64 grid points; each wave multiplies
+// its 16 points by the coefficients (kept in LDS) with 16x16x4 MFMA, NT
+// 16-column output tiles at a time.  The MFMA A-fragment of a k-step is 16
+// rows x 4 consecutive columns of an input.  For a narrow input (at most 8
+// stored columns) those 16 rows are one short contiguous run and the
+// fragment is loaded straight from global memory.  A wide input is staged: its
+// 64 rows (a contiguous run of 64*ld elements) are read with 16-byte loads,
+// one stage ahead of their use so that the next wide input's loads are in
+// flight while the current one is multiplied, and moved through LDS.
+// Per-workgroup partial sums of the norms are added in a fixed order by a
+// second kernel.
 #include "common.h"
 #include "kernels.h"
 #include "mfma.h"
 
 namespace lobpcg {
 
-static const int TP = 64;          // grid points per tile
-static const int MAXW = 32;        // widest input row staged (stored columns)
+static const int TP = 64;          // grid points per tile (4 waves x 16)
+static const int MAXW = 32;        // widest input (stored columns)
+static const int NARROW = 8;       // inputs up to this width are not staged
 static const int LDT = MAXW + 1;   // LDS row stride: odd, so the 16 rows of an A fragment hit 16 banks
 static const int MV_MAX_BLOCKS = 4096;
 
@@ -47,11 +54,6 @@ struct MVDev {
     i64 N;
 };
 
-// A tile of an input block: rows p0 .. p0+63 of an N x ld block, i.e. the
-// contiguous run of 64*ld elements at src + p0*ld.  It is loaded into
-// registers (16-byte vectors, at most NV per thread) one stage ahead of its
-// use, so that the loads of the next stage are in flight while the current
-// stage computes, and then written into tile[64][LDT].
 template <typename T>
 struct StageRegs {
     static const int VE = 16 / sizeof(T);
@@ -101,12 +103,12 @@ __device__ __forceinline__ void stage_store(T *tile, const StageRegs<T> &R, int 
     }
 }
 
+// acc[nt] += A C[roff .. roff+k-1] with A-fragments from a staged LDS row
 template <typename T, int NT>
-__device__ __forceinline__ void mma_input(typename Mfma<T>::acc *acc, const T *tile, const T *Cs, const int *cmap,
-                                          int roff, int k, int wave, int lane)
+__device__ __forceinline__ void mma_lds(typename Mfma<T>::acc (&acc)[NT], const T *arow, const T *Cs, const int *cmap,
+                                        int roff, int k, int lane)
 {
     const int NC = NT * 16;
-    const T *arow = tile + (16 * wave + (lane & 15)) * LDT;
     for (int k0 = 0; k0 < k; k0 += 4) {
         const int kr = k0 + (lane >> 4);
         const bool ok = kr < k;
@@ -120,136 +122,245 @@ __device__ __forceinline__ void mma_input(typename Mfma<T>::acc *acc, const T *t
     }
 }
 
+// the same with A-fragments straight from global memory (row `src` of this
+// lane, or zero past the grid); all loads of the input are issued first
+template <typename T, int NT>
+__device__ __forceinline__ void mma_global(typename Mfma<T>::acc (&acc)[NT], const T *__restrict__ src, bool pok,
+                                           const T *Cs, const int *cmap, int roff, int k, int lane)
+{
+    const int NC = NT * 16, kq = lane >> 4, lc = lane & 15;
+    T av[MAXW / 4];
+#pragma unroll
+    for (int i = 0; i < MAXW / 4; i++) {
+        const int kr = 4 * i + kq;
+        av[i] = (pok && kr < k) ? src[cmap[roff + kr]] : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < MAXW / 4; i++) {
+        if (4 * i >= k) break;
+        const int kr = 4 * i + kq;
+        const T *crow = Cs + (roff + kr) * NC + lc;
+        const bool ok = kr < k;
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) acc[nt] = Mfma<T>::mma(av[i], ok ? crow[16 * nt] : T(0), acc[nt]);
+    }
+}
+
+// Shared-memory layout of both kernels
+template <typename T, int NT>
+struct MVShared {
+    T *tile, *Cs;
+    double *theta, *red;
+    int *cmap, *opos, *wpos;
+    __device__ MVShared(unsigned char *smem, const MVDev<T> &a, bool staged)
+    {
+        const int NC = NT * 16;
+        tile = reinterpret_cast<T *>(smem);
+        Cs = tile + (staged ? TP * LDT : 0);
+        theta = reinterpret_cast<double *>(Cs + (a.Kp + 4) * NC);
+        red = theta + NC;                                    // [16 slots][2][NC]
+        cmap = reinterpret_cast<int *>(red + 16 * 2 * NC);   // [K + 4]
+        opos = cmap + a.K + 4;
+        wpos = opos + NC;
+    }
+};
+
+template <typename T, int NT>
+__device__ __forceinline__ void mv_setup(const MVShared<T, NT> &sh, const MVDev<T> &a)
+{
+    const int NC = NT * 16, tid = threadIdx.x;
+    for (int i = tid; i < (a.Kp + 4) * NC; i += blockDim.x) {
+        const int r = i / NC, c = i % NC;
+        sh.Cs[i] = (r < a.K && c < a.kout) ? a.C[r * a.kout + c] : T(0);
+    }
+    int roff = 0;
+    for (int b = 0; b < a.nin; b++) {
+        for (int r = tid; r < a.k[b]; r += blockDim.x) sh.cmap[roff + r] = a.cols[b] ? a.cols[b][r] : r;
+        roff += a.k[b];
+    }
+    for (int r = tid; r < 4; r += blockDim.x) sh.cmap[a.K + r] = 0;
+    for (int c = tid; c < NC; c += blockDim.x) {
+        sh.opos[c] = c < a.kout ? (a.opos ? a.opos[c] : c) : -1;
+        sh.wpos[c] = (c < a.kout && a.wpos) ? a.wpos[c] : -1;
+        sh.theta[c] = (c < a.kout && a.theta) ? a.theta[c] : 0.0;
+    }
+}
+
+// write the outputs of side s for the 16 points of this wave
+template <typename T, int NT>
+__device__ __forceinline__ void mv_outputs(const MVDev<T> &a, const MVShared<T, NT> &sh, int s, i64 p0w,
+                                           const typename Mfma<T>::acc (&acc)[NT],
+                                           const typename Mfma<T>::acc (&acc2)[NT],
+                                           const typename Mfma<T>::acc (&keepX)[NT], double (&sr)[NT],
+                                           double (&sx)[NT], int lane)
+{
+    const bool has2 = a.out2[0] != nullptr, resid = a.partials != nullptr;
+    T *out = a.out[s], *out2 = a.out2[s];
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const i64 p = p0w + Mfma<T>::row(lane, r);
+        if (p >= a.N) continue;
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+            const int c = 16 * nt + (lane & 15);
+            if (c >= a.kout) continue;
+            T v = acc[nt][r];
+            if (a.add && s == 0) v += a.add[p * a.kout + c];
+            const int q = sh.opos[c];
+            if (out && q >= 0) out[p * a.nout + q] = v;
+            if (has2) out2[p * a.kout + c] = acc2[nt][r];
+            if (resid && s == 1) {
+                const double x = (double)keepX[nt][r];
+                const double rv = (double)acc2[nt][r] - sh.theta[c] * x;
+                sr[nt] += rv * rv;
+                sx[nt] += x * x;
+                const int w = sh.wpos[c];
+                if (w >= 0) a.Wout[p * a.nW + w] = (T)rv;
+            }
+        }
+    }
+}
+
+// per-workgroup norm sums: lanes l, l+16, l+32, l+48 of every wave share a column
+template <typename T, int NT>
+__device__ __forceinline__ void mv_norms(const MVDev<T> &a, const MVShared<T, NT> &sh, const double (&sr)[NT],
+                                         const double (&sx)[NT], int wave, int lane)
+{
+    const int NC = NT * 16, tid = threadIdx.x;
+    const int slot = wave * 4 + (lane >> 4);
+#pragma unroll
+    for (int nt = 0; nt < NT; nt++) {
+        const int c = 16 * nt + (lane & 15);
+        sh.red[(slot * 2 + 0) * NC + c] = sr[nt];
+        sh.red[(slot * 2 + 1) * NC + c] = sx[nt];
+    }
+    __syncthreads();
+    for (int e = tid; e < 2 * a.kout; e += blockDim.x) {
+        const int which = e / a.kout, c = e % a.kout;
+        double sum = 0.0;
+        for (int sl = 0; sl < 16; sl++) sum += sh.red[(sl * 2 + which) * NC + c];
+        a.partials[(i64)blockIdx.x * 2 * a.kout + e] = sum;
+    }
+}
+
+// Staged kernel: wide inputs through LDS (prefetched one stage ahead), narrow
+// inputs straight from global memory.
 template <typename T, int NT>
 __global__ void __launch_bounds__(256) mv_kernel(MVDev<T> a)
 {
     typedef typename Mfma<T>::acc accT;
-    const int NC = NT * 16;
     extern __shared__ unsigned char smem[];
-    T *tile = reinterpret_cast<T *>(smem);
-    T *Cs = tile + TP * LDT;
-    double *theta = reinterpret_cast<double *>(Cs + (a.Kp + 4) * NC);
-    double *red = theta + NC;                               // [16 slots][2][NC]
-    int *cmap = reinterpret_cast<int *>(red + 16 * 2 * NC); // [K + 4]
-    int *opos = cmap + a.K + 4;
-    int *wpos = opos + NC;
-
+    MVShared<T, NT> sh(smem, a, true);
+    mv_setup<T, NT>(sh, a);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    for (int i = tid; i < (a.Kp + 4) * NC; i += blockDim.x) {
-        const int r = i / NC, c = i % NC;
-        Cs[i] = (r < a.K && c < a.kout) ? a.C[r * a.kout + c] : T(0);
-    }
-    {
-        int roff = 0;
-        for (int b = 0; b < a.nin; b++) {
-            for (int r = tid; r < a.k[b]; r += blockDim.x) cmap[roff + r] = a.cols[b] ? a.cols[b][r] : r;
-            roff += a.k[b];
-        }
-        for (int r = tid; r < 4; r += blockDim.x) cmap[a.K + r] = 0;
-    }
-    for (int c = tid; c < NC; c += blockDim.x) {
-        opos[c] = c < a.kout ? (a.opos ? a.opos[c] : c) : -1;
-        wpos[c] = (c < a.kout && a.wpos) ? a.wpos[c] : -1;
-        theta[c] = (c < a.kout && a.theta) ? a.theta[c] : 0.0;
-    }
-    int roffs[3];
-    roffs[0] = 0;
-    roffs[1] = a.k[0];
-    roffs[2] = a.k[0] + a.k[1];
+    const int roffs[3] = {0, a.k[0], a.k[0] + a.k[1]};
     __syncthreads();
 
     const bool has2 = a.out2[0] != nullptr;
-    const bool resid = a.partials != nullptr;
+    // processing order within a side: with a second output, inputs 1.. first
+    // (they form out), then input 0 on top (out2)
+    int order[3];
+    for (int q = 0; q < a.nin; q++) order[q] = has2 ? (q + 1) % a.nin : q;
+    // the staged (wide) inputs of one tile, in order: stage k is (side, input)
+    int st_s[6], st_b[6], nst = 0;
+    for (int s = 0; s < a.nside; s++)
+        for (int q = 0; q < a.nin; q++)
+            if (a.ld[order[q]] > NARROW) st_s[nst] = s, st_b[nst] = order[q], nst++;
+
     double sr[NT], sx[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; nt++) sr[nt] = sx[nt] = 0.0;
+    const T *arow = sh.tile + (16 * wave + (lane & 15)) * LDT;
 
-    // the stages of one tile, in order: per side, inputs 1.. then 0 when a
-    // second output is formed (input 0 is added on top for out2), else 0..
-    int order[3];
-    for (int q = 0; q < a.nin; q++) order[q] = has2 ? (q + 1) % a.nin : q;
-    const int per_tile = a.nside * a.nin;
     const i64 ntiles = (a.N + TP - 1) / TP;
-    i64 t = blockIdx.x;
     StageRegs<T> R;
-    if (t < ntiles) stage_load<T>(R, a.in[0][order[0]], a.ld[order[0]], t * TP, a.N);
-    accT acc[NT], acc2[NT], keepX[NT];
-    int st = 0;   // stage index within the tile
-    while (t < ntiles) {
-        const i64 p0 = t * TP;
-        const int s = st / a.nin, b = order[st % a.nin];
-        if (st % a.nin == 0) {
+    if ((i64)blockIdx.x < ntiles)
+        stage_load<T>(R, a.in[st_s[0]][st_b[0]], a.ld[st_b[0]], (i64)blockIdx.x * TP, a.N);
+    for (i64 t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const i64 p0 = t * TP, p0w = p0 + 16 * wave, prow = p0w + (lane & 15);
+        const bool pok = prow < a.N;
+        int k = 0;   // next stage of this tile
+        accT keepX[NT];
+        for (int s = 0; s < a.nside; s++) {
+            accT acc[NT], acc2[NT];
 #pragma unroll
             for (int nt = 0; nt < NT; nt++) acc[nt] = acc_zero<T>(), acc2[nt] = acc_zero<T>();
-        }
-        if (has2 && b == 0) {
-#pragma unroll
-            for (int nt = 0; nt < NT; nt++) acc2[nt] = acc[nt];
-        }
-        __syncthreads();
-        stage_store<T>(tile, R, a.ld[b]);
-        // prefetch the next stage (of this tile or the next one)
-        {
-            int ns = st + 1;
-            i64 nt2 = t;
-            if (ns == per_tile) ns = 0, nt2 = t + gridDim.x;
-            if (nt2 < ntiles) {
-                const int nb2 = order[ns % a.nin];
-                stage_load<T>(R, a.in[ns / a.nin][nb2], a.ld[nb2], nt2 * TP, a.N);
-            }
-        }
-        __syncthreads();
-        mma_input<T, NT>((has2 && b == 0) ? acc2 : acc, tile, Cs, cmap, roffs[b], a.k[b], wave, lane);
-        if (st % a.nin == a.nin - 1) {
-            // outputs of side s
-            T *out = a.out[s], *out2 = a.out2[s];
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const i64 p = p0 + 16 * wave + Mfma<T>::row(lane, r);
-                if (p >= a.N) continue;
-#pragma unroll
-                for (int nt = 0; nt < NT; nt++) {
-                    const int c = 16 * nt + (lane & 15);
-                    if (c >= a.kout) continue;
-                    T v = acc[nt][r];
-                    if (a.add && s == 0) v += a.add[p * a.kout + c];
-                    const int q = opos[c];
-                    if (out && q >= 0) out[p * a.nout + q] = v;
-                    if (has2) out2[p * a.kout + c] = acc2[nt][r];
-                    if (resid && s == 1) {
-                        const double x = (double)keepX[nt][r];
-                        const double rv = (double)acc2[nt][r] - theta[c] * x;
-                        sr[nt] += rv * rv;
-                        sx[nt] += x * x;
-                        const int w = wpos[c];
-                        if (w >= 0) a.Wout[p * a.nW + w] = (T)rv;
-                    }
+            // one input into a fixed accumulator array (a runtime choice of
+            // array would force the accumulators out of registers)
+            auto input = [&](accT(&tgt)[NT], int b) {
+                if (a.ld[b] > NARROW) {
+                    __syncthreads();
+                    stage_store<T>(sh.tile, R, a.ld[b]);
+                    // prefetch the next stage: of this tile, or the first of the next tile
+                    const int kn = k + 1 < nst ? k + 1 : 0;
+                    const i64 tn = k + 1 < nst ? t : t + gridDim.x;
+                    if (tn < ntiles) stage_load<T>(R, a.in[st_s[kn]][st_b[kn]], a.ld[st_b[kn]], tn * TP, a.N);
+                    k++;
+                    __syncthreads();
+                    mma_lds<T, NT>(tgt, arow, sh.Cs, sh.cmap, roffs[b], a.k[b], lane);
+                } else {
+                    mma_global<T, NT>(tgt, a.in[s][b] + prow * a.ld[b], pok, sh.Cs, sh.cmap, roffs[b], a.k[b],
+                                      lane);
                 }
+            };
+            for (int b = has2 ? 1 : 0; b < a.nin; b++) input(acc, b);
+            if (has2) {
+#pragma unroll
+                for (int nt = 0; nt < NT; nt++) acc2[nt] = acc[nt];
+                input(acc2, 0);
             }
+            mv_outputs<T, NT>(a, sh, s, p0w, acc, acc2, keepX, sr, sx, lane);
             if (s == 0) {
 #pragma unroll
                 for (int nt = 0; nt < NT; nt++) keepX[nt] = acc2[nt];
             }
         }
-        if (++st == per_tile) st = 0, t += gridDim.x;
     }
-    if (resid) {
-        // lanes l, l+16, l+32, l+48 of every wave share column l % 16 + 16 nt
-        const int slot = wave * 4 + (lane >> 4);
+    if (a.partials) mv_norms<T, NT>(a, sh, sr, sx, wave, lane);
+}
+
+// All inputs straight from global memory: each wave owns groups of 16 grid
+// points and runs without workgroup barriers.
+template <typename T, int NT>
+__global__ void __launch_bounds__(256) mvd_kernel(MVDev<T> a)
+{
+    typedef typename Mfma<T>::acc accT;
+    extern __shared__ unsigned char smem[];
+    MVShared<T, NT> sh(smem, a, false);
+    mv_setup<T, NT>(sh, a);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int roffs[3] = {0, a.k[0], a.k[0] + a.k[1]};
+    __syncthreads();
+
+    const bool has2 = a.out2[0] != nullptr;
+    double sr[NT], sx[NT];
 #pragma unroll
-        for (int nt = 0; nt < NT; nt++) {
-            const int c = 16 * nt + (lane & 15);
-            red[(slot * 2 + 0) * NC + c] = sr[nt];
-            red[(slot * 2 + 1) * NC + c] = sx[nt];
-        }
-        __syncthreads();
-        for (int e = tid; e < 2 * a.kout; e += blockDim.x) {
-            const int which = e / a.kout, c = e % a.kout;
-            double s = 0.0;
-            for (int sl = 0; sl < 16; sl++) s += red[(sl * 2 + which) * NC + c];
-            a.partials[(i64)blockIdx.x * 2 * a.kout + e] = s;
+    for (int nt = 0; nt < NT; nt++) sr[nt] = sx[nt] = 0.0;
+
+    const i64 ngroups = (a.N + 15) / 16;
+    for (i64 g = (i64)blockIdx.x * 4 + wave; g < ngroups; g += (i64)gridDim.x * 4) {
+        const i64 p0w = g * 16, prow = p0w + (lane & 15);
+        const bool pok = prow < a.N;
+        accT keepX[NT];
+        for (int s = 0; s < a.nside; s++) {
+            accT acc[NT], acc2[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; nt++) acc[nt] = acc_zero<T>(), acc2[nt] = acc_zero<T>();
+            for (int b = has2 ? 1 : 0; b < a.nin; b++)
+                mma_global<T, NT>(acc, a.in[s][b] + prow * a.ld[b], pok, sh.Cs, sh.cmap, roffs[b], a.k[b], lane);
+            if (has2) {
+#pragma unroll
+                for (int nt = 0; nt < NT; nt++) acc2[nt] = acc[nt];
+                mma_global<T, NT>(acc2, a.in[s][0] + prow * a.ld[0], pok, sh.Cs, sh.cmap, 0, a.k[0], lane);
+            }
+            mv_outputs<T, NT>(a, sh, s, p0w, acc, acc2, keepX, sr, sx, lane);
+            if (s == 0) {
+#pragma unroll
+                for (int nt = 0; nt < NT; nt++) keepX[nt] = acc2[nt];
+            }
         }
     }
+    if (a.partials) mv_norms<T, NT>(a, sh, sr, sx, wave, lane);
 }
 
 // sums[e] = sum over workgroups of partials[b][e]: one workgroup per entry,
@@ -270,6 +381,7 @@ __global__ void __launch_bounds__(256) mv_reduce_kernel(const double *__restrict
     if (threadIdx.x == 0) out[e] = red[0];
 }
 
+// both kernels cover 64 grid points per workgroup pass (4 waves x 16 points)
 int mv_blocks(long long N)
 {
     long long nt = (N + TP - 1) / TP;
@@ -281,12 +393,14 @@ static hipError_t run_mv(const MVArgs &h, hipStream_t st)
 {
     MVDev<T> a;
     a.K = 0;
+    bool any_wide = false;
     for (int b = 0; b < 3; b++) {
         for (int s = 0; s < 2; s++) a.in[s][b] = (const T *)h.in[s][b];
         a.ld[b] = h.ld[b];
         a.k[b] = b < h.nin ? h.k[b] : 0;
         a.cols[b] = h.cols[b];
         a.K += a.k[b];
+        if (b < h.nin && h.ld[b] > NARROW) any_wide = true;
     }
     a.nin = h.nin;
     a.nside = h.nside;
@@ -307,10 +421,14 @@ static hipError_t run_mv(const MVArgs &h, hipStream_t st)
     a.partials = h.partials;
     a.N = h.N;
     const int NC = NT * 16;
-    size_t shm = (size_t)TP * LDT * sizeof(T) + (size_t)(a.Kp + 4) * NC * sizeof(T);
-    shm = (shm + 7) / 8 * 8 + (size_t)NC * 8 + (size_t)16 * 2 * NC * 8 + (size_t)(a.K + 4 + 2 * NC) * sizeof(int);
     const int nb = mv_blocks(h.N);
-    hipLaunchKernelGGL((mv_kernel<T, NT>), dim3(nb), dim3(256), shm, st, a);
+    const bool staged = any_wide && h.variant == 0;
+    size_t shm = (staged ? (size_t)TP * LDT * sizeof(T) : 0) + (size_t)(a.Kp + 4) * NC * sizeof(T);
+    shm = (shm + 7) / 8 * 8 + (size_t)NC * 8 + (size_t)16 * 2 * NC * 8 + (size_t)(a.K + 4 + 2 * NC) * sizeof(int);
+    if (staged)
+        hipLaunchKernelGGL((mv_kernel<T, NT>), dim3(nb), dim3(256), shm, st, a);
+    else
+        hipLaunchKernelGGL((mvd_kernel<T, NT>), dim3(nb), dim3(256), shm, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !h.partials) return e;
     hipLaunchKernelGGL(mv_reduce_kernel, dim3(2 * h.kout), dim3(256), 0, st, h.partials, nb, 2 * h.kout, h.sums);
@@ -320,8 +438,9 @@ static hipError_t run_mv(const MVArgs &h, hipStream_t st)
 hipError_t launch_mv(int dtype, const MVArgs &a, hipStream_t st)
 {
     if (a.N == 0) return hipSuccess;
+    if (a.nin < 1 || a.nin > 3 || a.nside < 1 || a.nside > 2) return hipErrorInvalidValue;
     for (int b = 0; b < a.nin; b++)
-        if (a.ld[b] > MAXW || a.ld[b] < 1) return hipErrorInvalidValue;
+        if (a.ld[b] > MAXW || a.ld[b] < 1 || a.k[b] < 1) return hipErrorInvalidValue;
     if (a.kout < 1 || a.kout > 32) return hipErrorInvalidValue;
     if (a.partials && (a.nside != 2 || !a.out2[0])) return hipErrorInvalidValue;
     const bool two = a.kout > 16;

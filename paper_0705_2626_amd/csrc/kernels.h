@@ -70,6 +70,7 @@ struct MVArgs {
     double *partials;       // [mv_blocks(N)][2 kout]
     double *sums;           // [2 kout]
     long long N;
+    int variant;            // 0: tiles staged through LDS, 1: fragments straight from global memory
 };
 int mv_blocks(long long N);
 hipError_t launch_mv(int dtype, const MVArgs &a, hipStream_t st);
@@ -114,6 +115,7 @@ struct GramArgs {
     long long N;
     double *partials;   // scratch, gram_partials_bytes
     double *out;        // device [2][Kp][Kp], Kp = K rounded up to 16
+    int staged;         // 1: the LDS-staged kernel also for narrow single blocks
 };
 int gram_kpad(int K);
 size_t gram_partials_bytes(int dtype, long long N, int K);

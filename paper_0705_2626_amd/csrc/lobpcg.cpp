@@ -154,6 +154,8 @@ struct lobpcg_ctx {
     int stall_window;
     double stall_factor;
     bool profile, reactivate;
+    int mv_variant, gram_staged;  // kernel variants (see LOBPCG_OPT_KERNELS)
+    bool fp32_explicit;           // FP32 phase: Gram diagonal blocks computed, not assumed
     lobpcg_stats stats;
     // profiling: pending (step, start, end) event pairs
     std::vector<hipEvent_t> ev_pool;
@@ -313,6 +315,7 @@ int gram(lobpcg_ctx *c, int dt, int n, const void *const *S, const void *const *
     a.N = c->N;
     a.partials = c->d_gram_part;
     a.out = c->d_gram_out;
+    a.staged = c->gram_staged;
     const int Kp = gram_kpad(K);
     const size_t bytes = (size_t)(AS ? 2 : 1) * Kp * Kp * 8;
     // tiles that are not computed read as zero
@@ -391,6 +394,7 @@ int mv(lobpcg_ctx *c, int dt, const MV &q, const double *C, int step)
     a.partials = q.resid ? c->d_mv_part : nullptr;
     a.sums = q.resid ? c->d_res_out : nullptr;
     a.N = c->N;
+    a.variant = c->mv_variant;
     int s = upload_coef(c, dt, C, K, q.kout, &a.C);
     if (s) return s;
     prof_begin(c, step);
@@ -960,6 +964,9 @@ int lobpcg_setup(lobpcg_ctx **out, const lobpcg_op *A, const lobpcg_op *B, const
     c->stall_factor = 0.7;
     c->profile = false;
     c->reactivate = true;
+    c->mv_variant = 0;
+    c->gram_staged = 0;
+    c->fp32_explicit = true;
     memset(&c->stats, 0, sizeof(c->stats));
     c->ev_used = 0;
     *out = c;
@@ -1000,6 +1007,12 @@ int lobpcg_set_option(lobpcg_ctx *c, int key, double v)
         }
         return LOBPCG_OK;
     case LOBPCG_OPT_REACTIVATE: c->reactivate = v != 0; return LOBPCG_OK;
+    case LOBPCG_OPT_FP32_EXPLICIT_GRAM: c->fp32_explicit = v != 0; return LOBPCG_OK;
+    case LOBPCG_OPT_KERNELS:
+        if (v < 0 || v > 3) return LOBPCG_ERR_ARG;
+        c->mv_variant = ((int)v & 1) ? 1 : 0;
+        c->gram_staged = ((int)v & 2) != 0;
+        return LOBPCG_OK;
     default: return LOBPCG_ERR_ARG;
     }
 }
@@ -1052,7 +1065,7 @@ int lobpcg_solve(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, const lo
         s = init_phase(c, A, DT_F32, c->b32, ps, true, true);
         if (s == LOBPCG_OK) {
             s = run_phase(c, A, DT_F32, c->b32, ps, std::max(tol, c->switch_tol), normA, maxit, iters, h_hist,
-                          true, true, outcome);
+                          c->fp32_explicit, true, outcome);
         }
         if (s == LOBPCG_OK) {
             // FP64 phase: up-cast X and the directions P, form A X and A P

@@ -21,7 +21,8 @@ OP_LAPLACE7, OP_VARCOEF7 = 0, 1
 PC_NONE, PC_GMG_V = 0, 1
 FP64, MIXED = 0, 1
 F64, F32 = 0, 1
-OPT_SWITCH_TOL, OPT_STALL_WINDOW, OPT_STALL_FACTOR, OPT_PROFILE, OPT_REACTIVATE = 0, 1, 2, 3, 4
+OPT_SWITCH_TOL, OPT_STALL_WINDOW, OPT_STALL_FACTOR, OPT_PROFILE, OPT_REACTIVATE, OPT_KERNELS = 0, 1, 2, 3, 4, 5
+OPT_FP32_EXPLICIT_GRAM = 6
 STEP_NAMES = ["residual", "precond", "ortho", "apply_A", "gram", "rr_host", "update", "other"]
 
 

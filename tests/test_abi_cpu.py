@@ -54,7 +54,7 @@ def test_workspace_bytes_scales_with_problem():
     assert s1 == s2 == s3 == L.OK
     N, m = 64 ** 3, 8
     assert n1 >= 11 * N * m * 8 and n2 >= 11 * N * m * (8 + 4)
-    assert n3 > 1.9 * n1
+    assert n3 - n1 >= 11 * N * m * 8     # the N x m blocks double with N
 
 
 @pytest.mark.parametrize("dims,levels,m,prec,want", [

@@ -190,6 +190,22 @@ def test_error_paths():
         L.lobpcg_solve(ctx, dev(synth.x0_uniform(N, m)), -1.0, 10)
 
 
+@pytest.mark.parametrize("variant", [1, 2])
+def test_kernel_variants_give_the_same_solution(variant):
+    """The LDS-staged multivector / Gram kernels and the direct ones agree."""
+    dims, m = (20, 18, 16), 6
+    N = int(np.prod(dims))
+    X0 = dev(synth.x0_uniform(N, m))
+    res = []
+    for v in (0, variant):
+        ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(3), m, L.FP64)
+        L.lobpcg_set_option(ctx, L.OPT_KERNELS, v)
+        res.append(L.lobpcg_solve(ctx, X0, 1e-9, 200))
+    assert res[0].status == res[1].status == L.OK
+    np.testing.assert_allclose(res[0].lam, res[1].lam, rtol=1e-10)
+    assert abs(res[0].iters - res[1].iters) <= 1
+
+
 def test_solver_is_deterministic():
     dims, m = (20, 20, 20), 6
     _, r1, _ = solve(dims, m, 3, L.MIXED, 1e-8, 100)
