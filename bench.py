@@ -84,8 +84,11 @@ def main():
         steps = None
         if args.profile_steps:
             L.lobpcg_set_option(ctx, L.OPT_PROFILE, 1)
-            L.lobpcg_solve(ctx, X0, tol, args.maxit, hist=False)
-            steps = L.lobpcg_get_stats(ctx)["step_ms"]
+            rp = L.lobpcg_solve(ctx, X0, tol, args.maxit, hist=True)
+            steps = dict(L.lobpcg_get_stats(ctx)["step_ms"])
+            # active-set sizes (soft locking: a column leaves J once its residual is below tol)
+            h = np.asarray(rp.hist)
+            steps["active_cols_per_iter"] = np.logical_and.accumulate(h > tol, axis=0).sum(axis=1).tolist()
         for r in results:
             assert r.status == L.OK, L.status_string(r.status)
         r = results[-1]

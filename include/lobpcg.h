@@ -126,16 +126,18 @@ const char *lobpcg_status_string(int status);
 
 /* ---------------------------------------------------------------- options and statistics */
 enum {
-    LOBPCG_OPT_SWITCH_TOL = 0,      /* MIXED: FP32 phase ends at max rho <= this (default 1e-5) */
-    LOBPCG_OPT_STALL_WINDOW = 1,    /* MIXED: ... or when max rho fell by less than      */
-    LOBPCG_OPT_STALL_FACTOR = 2,    /*        STALL_FACTOR over STALL_WINDOW iterations  */
+    LOBPCG_OPT_SWITCH_TOL = 0,      /* MIXED: FP32 phase ends at max rho <= this (default 3e-7) */
+    LOBPCG_OPT_STALL_WINDOW = 1,    /* MIXED: ... or when max rho fell by less than a    */
+    LOBPCG_OPT_STALL_FACTOR = 2,    /*        factor STALL_FACTOR (default 0.95) over    */
+                                    /*        STALL_WINDOW (default 10) iterations       */
     LOBPCG_OPT_PROFILE = 3,         /* 1: time each step class with HIP events          */
     LOBPCG_OPT_REACTIVATE = 4,      /* 1 (default): see lobpcg_solve's stopping rule    */
-    LOBPCG_OPT_KERNELS = 5,         /* kernel variants: bit 0 multivector products     */
-                                    /* loading MFMA fragments straight from global     */
-                                    /* memory, bit 1 multi-column-tile Gram kernel     */
-                                    /* for narrow Grams too; 0 = default; results      */
-                                    /* agree to rounding                               */
+    LOBPCG_OPT_KERNELS = 5,         /* kernel variants, 0 = default; results agree to  */
+                                    /* rounding.  Bits 0-1, multivector products:      */
+                                    /* 1 = per-element fragment loads, 2 = tiles       */
+                                    /* staged through LDS (3 is invalid); bit 2: the   */
+                                    /* multi-column-tile Gram kernel also for narrow   */
+                                    /* single-block Grams                              */
     LOBPCG_OPT_FP32_EXPLICIT_GRAM = 6 /* MIXED: 1 (default) FP32 iterations compute    */
                                     /* X^T X, X^T AX, W^T W, P^T P rather than taking  */
                                     /* I and Lambda for them as the paper's form does  */

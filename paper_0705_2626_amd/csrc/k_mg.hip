@@ -33,44 +33,66 @@ hipError_t launch_scale(int dtype, long long n, const void *b, void *out, double
     return hipGetLastError();
 }
 
-// bc[P] = sum over the 27 fine neighbours of fine node (2X+1, 2Y+1, 2Z+1) of
-// w(a) w(b) w(c) rf / 64, w = (1, 2, 1); fine nodes beyond the grid are zero.
+// Launch shape of the transfer kernels: one thread per (x, y) column of the
+// output level and V-column chunk, marching in z over a chunk of planes; the
+// planes are split into enough chunks to give about 2048 workgroups.
+static void march_geometry(int nx, int ny, int nz, int L, dim3 &grid, int &zchunk)
+{
+    const i64 plane = (i64)nx * ny * L;
+    const unsigned pb = (unsigned)((plane + 255) / 256);
+    int zc = (int)((2048 + pb - 1) / pb);
+    if (zc < 1) zc = 1;
+    if (zc > nz) zc = nz;
+    zchunk = (nz + zc - 1) / zc;
+    grid = dim3(pb, (nz + zchunk - 1) / zchunk, 1);
+}
+
+// bc at coarse node (X, Y, Z) = sum over the 27 fine nodes (2X+a, 2Y+b, 2Z+c),
+// a, b, c in {0, 1, 2}, of w_a w_b w_c rf / 64 with w = (1, 2, 1); fine
+// nodes beyond the grid are zero.  The thread of coarse column (X, Y) forms
+// the in-plane 3x3 sum of each fine plane once and combines three of them
+// per coarse plane (the plane 2Z+2 is shared with Z+1).
 template <typename T, int V>
 __global__ void __launch_bounds__(256) restrict_kernel(int nxf, int nyf, int nzf, int nxc, int nyc, int nzc, int L,
-                                                       const T *__restrict__ rf, T *__restrict__ bc)
+                                                       int zchunk, const T *__restrict__ rf, T *__restrict__ bc)
 {
-    const i64 total = (i64)nxc * nyc * nzc * L;
-    for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (i64)gridDim.x * blockDim.x) {
-    const int c = (int)(t % L);
-    const i64 P = t / L;
-    const int X = (int)(P % nxc);
-    const int Y = (int)((P / nxc) % nyc);
-    const int Z = (int)(P / ((i64)nxc * nyc));
-    T acc[V];
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (unsigned)(nxc * nyc * L)) return;
+    const int c = (int)(t % (unsigned)L);
+    const unsigned pxy = t / (unsigned)L;
+    const int X = (int)(pxy % (unsigned)nxc), Y = (int)(pxy / (unsigned)nxc);
+    const int Z0 = blockIdx.y * zchunk, Z1 = min(nzc, Z0 + zchunk);
+    const i64 k = (i64)L * V;
+    const i64 fplane = (i64)nxf * nyf;
+    auto plane_sum = [&](int zf) {
+        vec<T, V> s = vzero<T, V>();
+        if (zf >= nzf) return s;
 #pragma unroll
-    for (int q = 0; q < V; q++) acc[q] = T(0);
-    const T w[3] = {T(1), T(2), T(1)};
-    for (int cz = 0; cz < 3; cz++) {
-        const int zf = 2 * Z + cz;
-        if (zf >= nzf) continue;
-        for (int cy = 0; cy < 3; cy++) {
-            const int yf = 2 * Y + cy;
+        for (int b = 0; b < 3; b++) {
+            const int yf = 2 * Y + b;
             if (yf >= nyf) continue;
-            for (int cx = 0; cx < 3; cx++) {
-                const int xf = 2 * X + cx;
-                if (xf >= nxf) continue;
-                const T wt = w[cx] * w[cy] * w[cz];
-                const i64 p = (i64)xf + (i64)nxf * ((i64)yf + (i64)nyf * zf);
-                vec<T, V> r = vload<T, V>(rf + (p * L + c) * V);
+            const T wb = b == 1 ? T(2) : T(1);
 #pragma unroll
-                for (int q = 0; q < V; q++) acc[q] += wt * r.v[q];
+            for (int a = 0; a < 3; a++) {
+                const int xf = 2 * X + a;
+                if (xf >= nxf) continue;
+                const T w = wb * (a == 1 ? T(2) : T(1));
+                const vec<T, V> r = vload<T, V>(rf + ((i64)xf + (i64)nxf * yf + fplane * zf) * k + c * V);
+#pragma unroll
+                for (int q = 0; q < V; q++) s.v[q] += w * r.v[q];
             }
         }
-    }
-    vec<T, V> o;
+        return s;
+    };
+    vec<T, V> s0 = plane_sum(2 * Z0);
+    const i64 cplane = (i64)nxc * nyc;
+    for (int Z = Z0; Z < Z1; Z++) {
+        const vec<T, V> s1 = plane_sum(2 * Z + 1), s2 = plane_sum(2 * Z + 2);
+        vec<T, V> o;
 #pragma unroll
-    for (int q = 0; q < V; q++) o.v[q] = acc[q] * T(1.0 / 64.0);
-    vstore<T, V>(bc + (P * L + c) * V, o);
+        for (int q = 0; q < V; q++) o.v[q] = (s0.v[q] + T(2) * s1.v[q] + s2.v[q]) * T(1.0 / 64.0);
+        vstore<T, V>(bc + ((i64)X + (i64)nxc * Y + cplane * Z) * k + c * V, o);
+        s0 = s2;
     }
 }
 
@@ -89,37 +111,58 @@ __device__ __forceinline__ int prolong_1d(int i, int nc, int *I, float *w)
     return n;
 }
 
+// xf += P ec.  The thread of fine column (x, y) forms the bilinear in-plane
+// interpolation q(I) of each coarse plane I once; fine plane 2I+1 takes q(I),
+// fine plane 2I takes (q(I-1) + q(I))/2 (q of a plane beyond the grid is 0).
 template <typename T, int V>
 __global__ void __launch_bounds__(256) prolong_add_kernel(int nxf, int nyf, int nzf, int nxc, int nyc, int nzc,
-                                                          int L, const T *__restrict__ ec, T *__restrict__ xf)
+                                                          int L, int zchunk, const T *__restrict__ ec,
+                                                          T *__restrict__ xf)
 {
-    const i64 total = (i64)nxf * nyf * nzf * L;
-    for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (i64)gridDim.x * blockDim.x) {
-    const int c = (int)(t % L);
-    const i64 p = t / L;
-    const int x = (int)(p % nxf);
-    const int y = (int)((p / nxf) % nyf);
-    const int z = (int)(p / ((i64)nxf * nyf));
-    int Ix[2], Iy[2], Iz[2];
-    float wx[2], wy[2], wz[2];
-    const int nx_ = prolong_1d(x, nxc, Ix, wx), ny_ = prolong_1d(y, nyc, Iy, wy), nz_ = prolong_1d(z, nzc, Iz, wz);
-    T acc[V];
+    const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (unsigned)(nxf * nyf * L)) return;
+    const int c = (int)(t % (unsigned)L);
+    const unsigned pxy = t / (unsigned)L;
+    const int x = (int)(pxy % (unsigned)nxf), y = (int)(pxy / (unsigned)nxf);
+    const int z0 = blockIdx.y * zchunk, z1 = min(nzf, z0 + zchunk);
+    const i64 k = (i64)L * V;
+    int Ix[2], Iy[2];
+    float wx[2], wy[2];
+    const int nxt = prolong_1d(x, nxc, Ix, wx), nyt = prolong_1d(y, nyc, Iy, wy);
+    const i64 cplane = (i64)nxc * nyc;
+    auto q = [&](int I) {
+        vec<T, V> s = vzero<T, V>();
+        if (I < 0 || I >= nzc) return s;
+        for (int b = 0; b < nyt; b++)
+            for (int a = 0; a < nxt; a++) {
+                const T w = (T)(wx[a] * wy[b]);
+                const vec<T, V> e = vload<T, V>(ec + ((i64)Ix[a] + (i64)nxc * Iy[b] + cplane * I) * k + c * V);
 #pragma unroll
-    for (int q = 0; q < V; q++) acc[q] = T(0);
-    for (int a = 0; a < nz_; a++)
-        for (int b2 = 0; b2 < ny_; b2++)
-            for (int d = 0; d < nx_; d++) {
-                const T wt = (T)(wx[d] * wy[b2] * wz[a]);
-                const i64 P = (i64)Ix[d] + (i64)nxc * ((i64)Iy[b2] + (i64)nyc * Iz[a]);
-                vec<T, V> e = vload<T, V>(ec + (P * L + c) * V);
-#pragma unroll
-                for (int q = 0; q < V; q++) acc[q] += wt * e.v[q];
+                for (int r = 0; r < V; r++) s.v[r] += w * e.v[r];
             }
-    T *dst = xf + (p * L + c) * V;
-    vec<T, V> o = vload<T, V>(dst);
+        return s;
+    };
+    int Ic = -2;          // coarse plane held in qc
+    vec<T, V> qc = vzero<T, V>();
+    const i64 fplane = (i64)nxf * nyf;
+    for (int z = z0; z < z1; z++) {
+        vec<T, V> val;
+        if (z & 1) {
+            const int I = (z - 1) >> 1;
+            if (I != Ic) qc = q(I), Ic = I;
+            val = qc;
+        } else {
+            const int I = z >> 1;
+            const vec<T, V> qa = (Ic == I - 1) ? qc : q(I - 1);
+            qc = q(I), Ic = I;
 #pragma unroll
-    for (int q = 0; q < V; q++) o.v[q] += acc[q];
-    vstore<T, V>(dst, o);
+            for (int r = 0; r < V; r++) val.v[r] = T(0.5) * (qa.v[r] + qc.v[r]);
+        }
+        T *dst = xf + ((i64)x + (i64)nxf * y + fplane * z) * k + c * V;
+        vec<T, V> o = vload<T, V>(dst);
+#pragma unroll
+        for (int r = 0; r < V; r++) o.v[r] += val.v[r];
+        vstore<T, V>(dst, o);
     }
 }
 
@@ -144,9 +187,11 @@ template <typename T, int V>
 static hipError_t run_restrict(const Grid3 &f, const Grid3 &c, int k, const void *rf, void *bc, hipStream_t st)
 {
     const int L = k / V;
-    const i64 total = c.n() * L;
-    hipLaunchKernelGGL((restrict_kernel<T, V>), dim3(stride_blocks(total)), dim3(256), 0, st, f.nx,
-                       f.ny, f.nz, c.nx, c.ny, c.nz, L, (const T *)rf, (T *)bc);
+    dim3 grid;
+    int zchunk;
+    march_geometry(c.nx, c.ny, c.nz, L, grid, zchunk);
+    hipLaunchKernelGGL((restrict_kernel<T, V>), grid, dim3(256), 0, st, f.nx, f.ny, f.nz, c.nx, c.ny, c.nz, L,
+                       zchunk, (const T *)rf, (T *)bc);
     return hipGetLastError();
 }
 
@@ -154,9 +199,11 @@ template <typename T, int V>
 static hipError_t run_prolong(const Grid3 &f, const Grid3 &c, int k, const void *ec, void *xf, hipStream_t st)
 {
     const int L = k / V;
-    const i64 total = f.n() * L;
-    hipLaunchKernelGGL((prolong_add_kernel<T, V>), dim3(stride_blocks(total)), dim3(256), 0, st, f.nx,
-                       f.ny, f.nz, c.nx, c.ny, c.nz, L, (const T *)ec, (T *)xf);
+    dim3 grid;
+    int zchunk;
+    march_geometry(f.nx, f.ny, f.nz, L, grid, zchunk);
+    hipLaunchKernelGGL((prolong_add_kernel<T, V>), grid, dim3(256), 0, st, f.nx, f.ny, f.nz, c.nx, c.ny, c.nz, L,
+                       zchunk, (const T *)ec, (T *)xf);
     return hipGetLastError();
 }
 
@@ -178,6 +225,7 @@ hipError_t launch_restrict(int dtype, const Grid3 &f, const Grid3 &c, int k, con
 hipError_t launch_prolong_add(int dtype, const Grid3 &f, const Grid3 &c, int k, const void *ec, void *xf,
                               hipStream_t st)
 {
+    if (f.n() == 0) return hipSuccess;
     if (dtype == DT_F32) {
         switch (pick_vec<float>(k)) {
         case 4: return run_prolong<float, 4>(f, c, k, ec, xf, st);

@@ -16,7 +16,7 @@
 
 namespace lobpcg {
 
-enum { EPI_APPLY = 0, EPI_JACOBI = 1, EPI_RESID = 2 };
+enum { EPI_APPLY = 0, EPI_JACOBI = 1, EPI_RESID = 2, EPI_JACOBI2 = 3 };
 
 template <typename T, int V>
 __device__ __forceinline__ vec<T, V> lap(const vec<T, V> &c, const vec<T, V> &zm, const vec<T, V> &zp,
@@ -33,6 +33,8 @@ __device__ __forceinline__ vec<T, V> lap(const vec<T, V> &c, const vec<T, V> &zm
 // EPI_APPLY : out = s * L7 u
 // EPI_JACOBI: out = u + c1 * (b - s * L7 u)
 // EPI_RESID : out = b - s * L7 u
+// EPI_JACOBI2: two sweeps from zero with right-hand side u:
+//             x1 = c1 u, out = x1 + c1 (u - s L7 x1)
 template <typename T, int V, int EPI>
 __global__ void __launch_bounds__(256) stencil7_kernel(int nx, int ny, int nz, int L, int zchunk,
                                                        const T *__restrict__ u, T *__restrict__ out,
@@ -66,6 +68,9 @@ __global__ void __launch_bounds__(256) stencil7_kernel(int nx, int ny, int nz, i
         if (EPI == EPI_APPLY) {
 #pragma unroll
             for (int q = 0; q < V; q++) o.v[q] = s * au.v[q];
+        } else if (EPI == EPI_JACOBI2) {
+#pragma unroll
+            for (int q = 0; q < V; q++) o.v[q] = c1 * cur.v[q] + c1 * (cur.v[q] - s * (c1 * au.v[q]));
         } else {
             vec<T, V> bb = vload<T, V>(b + i);
 #pragma unroll
@@ -183,6 +188,7 @@ static hipError_t dispatch_epi(int epi, const Grid3 &g, int k, const void *u, vo
     switch (epi) {
     case EPI_APPLY: return dispatch_vec<T, EPI_APPLY>(g, k, u, out, b, s, c1, st);
     case EPI_JACOBI: return dispatch_vec<T, EPI_JACOBI>(g, k, u, out, b, s, c1, st);
+    case EPI_JACOBI2: return dispatch_vec<T, EPI_JACOBI2>(g, k, u, out, b, s, c1, st);
     default: return dispatch_vec<T, EPI_RESID>(g, k, u, out, b, s, c1, st);
     }
 }
@@ -199,6 +205,14 @@ hipError_t launch_jacobi(int dtype, const Grid3 &g, int k, const void *x, const 
     const double c1 = omega / (6.0 * s);
     if (dtype == DT_F32) return dispatch_epi<float>(EPI_JACOBI, g, k, x, out, b, s, c1, st);
     return dispatch_epi<double>(EPI_JACOBI, g, k, x, out, b, s, c1, st);
+}
+
+hipError_t launch_jacobi2_zero(int dtype, const Grid3 &g, int k, const void *b, void *out, double s, double omega,
+                               hipStream_t st)
+{
+    const double c1 = omega / (6.0 * s);
+    if (dtype == DT_F32) return dispatch_epi<float>(EPI_JACOBI2, g, k, b, out, nullptr, s, c1, st);
+    return dispatch_epi<double>(EPI_JACOBI2, g, k, b, out, nullptr, s, c1, st);
 }
 
 hipError_t launch_resid7(int dtype, const Grid3 &g, int k, const void *x, const void *b, void *out, double s,

@@ -187,8 +187,8 @@ __device__ __forceinline__ void mv_setup(const MVShared<T, NT> &sh, const MVDev<
 }
 
 // write the outputs of side s for the 16 points of this wave
-template <typename T, int NT>
-__device__ __forceinline__ void mv_outputs(const MVDev<T> &a, const MVShared<T, NT> &sh, int s, i64 p0w,
+template <typename T, int NT, typename SH>
+__device__ __forceinline__ void mv_outputs(const MVDev<T> &a, const SH &sh, int s, i64 p0w,
                                            const typename Mfma<T>::acc (&acc)[NT],
                                            const typename Mfma<T>::acc (&acc2)[NT],
                                            const typename Mfma<T>::acc (&keepX)[NT], double (&sr)[NT],
@@ -222,8 +222,8 @@ __device__ __forceinline__ void mv_outputs(const MVDev<T> &a, const MVShared<T, 
 }
 
 // per-workgroup norm sums: lanes l, l+16, l+32, l+48 of every wave share a column
-template <typename T, int NT>
-__device__ __forceinline__ void mv_norms(const MVDev<T> &a, const MVShared<T, NT> &sh, const double (&sr)[NT],
+template <typename T, int NT, typename SH>
+__device__ __forceinline__ void mv_norms(const MVDev<T> &a, const SH &sh, const double (&sr)[NT],
                                          const double (&sx)[NT], int wave, int lane)
 {
     const int NC = NT * 16, tid = threadIdx.x;
@@ -363,6 +363,245 @@ __global__ void __launch_bounds__(256) mvd_kernel(MVDev<T> a)
     if (a.partials) mv_norms<T, NT>(a, sh, sr, sx, wave, lane);
 }
 
+// Fragment kernel: A-fragments loaded straight from global memory with
+// 16-byte loads.  The k-sum of an input is split among the four lane groups
+// of the MFMA's A operand by contiguous quarters instead of by residues mod 4:
+// at k-step i lane l holds column (l/16)*k4 + i of its row (k4 = ceil(k/4)),
+// so a lane's k4 values are consecutive in memory.  The coefficient operand
+// follows the same permutation and is kept in LDS in fragment order
+// (Cf[step][nt][lane]), so that its reads are conflict-free and need no index
+// arithmetic.  Each wave owns groups of 16 grid points; no workgroup barrier
+// after the set-up.
+static const int KQ = MAXW / 4;    // most k-steps of one input
+
+template <typename T, int NT>
+struct MVFShared {
+    T *Cf;                 // [sum k4][NT][64]
+    double *theta, *red;
+    int *cmap, *opos, *wpos;
+    __device__ MVFShared(unsigned char *smem, const MVDev<T> &a, int nsteps)
+    {
+        const int NC = NT * 16;
+        Cf = reinterpret_cast<T *>(smem);
+        theta = reinterpret_cast<double *>(Cf + nsteps * NT * 64);
+        red = theta + NC;
+        cmap = reinterpret_cast<int *>(red + 16 * 2 * NC);
+        opos = cmap + a.K + 4;
+        wpos = opos + NC;
+    }
+};
+
+// av[i] = column (l/16)*k4 + i of this lane's row (zero past k or the grid)
+template <typename T>
+__device__ __forceinline__ void frag_load(T (&av)[KQ], const T *__restrict__ base, int ld, int k, int k4,
+                                          const int *__restrict__ cmap, bool mapped, bool pok, int kq)
+{
+    const int VE = 16 / sizeof(T);
+    const int j0 = kq * k4;
+    const bool vec_ok = !mapped && (k4 % VE) == 0 && (ld % VE) == 0 && j0 + k4 <= ld;
+    if (vec_ok) {
+#pragma unroll
+        for (int i = 0; i < KQ; i += VE) {
+            if (i >= k4) break;
+            vec<T, VE> v = pok ? vload<T, VE>(base + j0 + i) : vzero<T, VE>();
+#pragma unroll
+            for (int q = 0; q < VE; q++) av[i + q] = (j0 + i + q < k) ? v.v[q] : T(0);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < KQ; i++) {
+            if (i >= k4) break;
+            const int j = j0 + i;
+            av[i] = (pok && j < k) ? base[mapped ? cmap[j] : j] : T(0);
+        }
+    }
+}
+
+template <typename T, int NT>
+__global__ void __launch_bounds__(256) mvf_kernel(MVDev<T> a)
+{
+    typedef typename Mfma<T>::acc accT;
+    extern __shared__ unsigned char smem[];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, kq = lane >> 4;
+    const int NC = NT * 16;
+    int k4[3], soff[3], roffs[3];
+    int nsteps = 0, roff = 0;
+    for (int b = 0; b < 3; b++) {
+        k4[b] = b < a.nin ? (a.k[b] + 3) / 4 : 0;
+        soff[b] = nsteps;
+        roffs[b] = roff;
+        nsteps += k4[b];
+        roff += b < a.nin ? a.k[b] : 0;
+    }
+    MVFShared<T, NT> sh(smem, a, nsteps);
+    // coefficients in fragment order
+    for (int e = tid; e < nsteps * NT * 64; e += blockDim.x) {
+        const int l = e & 63, nt = (e >> 6) % NT, st = (e >> 6) / NT;
+        int b = 0;
+        while (b + 1 < a.nin && st >= soff[b + 1]) b++;
+        const int i = st - soff[b];
+        const int j = (l >> 4) * k4[b] + i, c = 16 * nt + (l & 15);
+        sh.Cf[e] = (j < a.k[b] && c < a.kout) ? a.C[(roffs[b] + j) * a.kout + c] : T(0);
+    }
+    for (int b = 0; b < a.nin; b++)
+        for (int r = tid; r < a.k[b]; r += blockDim.x) sh.cmap[roffs[b] + r] = a.cols[b] ? a.cols[b][r] : r;
+    for (int c = tid; c < NC; c += blockDim.x) {
+        sh.opos[c] = c < a.kout ? (a.opos ? a.opos[c] : c) : -1;
+        sh.wpos[c] = (c < a.kout && a.wpos) ? a.wpos[c] : -1;
+        sh.theta[c] = (c < a.kout && a.theta) ? a.theta[c] : 0.0;
+    }
+    __syncthreads();
+
+    const bool has2 = a.out2[0] != nullptr;
+    double sr[NT], sx[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; nt++) sr[nt] = sx[nt] = 0.0;
+
+    // one input into a fixed accumulator array
+    auto input = [&](accT(&tgt)[NT], int s, int b, i64 prow, bool pok) {
+        T av[KQ];
+        frag_load<T>(av, a.in[s][b] + prow * a.ld[b], a.ld[b], a.k[b], k4[b], sh.cmap + roffs[b],
+                     a.cols[b] != nullptr, pok, kq);
+        const T *cf = sh.Cf + soff[b] * NT * 64 + lane;
+#pragma unroll
+        for (int i = 0; i < KQ; i++) {
+            if (i >= k4[b]) break;
+#pragma unroll
+            for (int nt = 0; nt < NT; nt++) tgt[nt] = Mfma<T>::mma(av[i], cf[(i * NT + nt) * 64], tgt[nt]);
+        }
+    };
+
+    const i64 ngroups = (a.N + 15) / 16;
+    for (i64 g = (i64)blockIdx.x * 4 + wave; g < ngroups; g += (i64)gridDim.x * 4) {
+        const i64 p0w = g * 16, prow = p0w + (lane & 15);
+        const bool pok = prow < a.N;
+        accT keepX[NT];
+        for (int s = 0; s < a.nside; s++) {
+            accT acc[NT], acc2[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; nt++) acc[nt] = acc_zero<T>(), acc2[nt] = acc_zero<T>();
+            for (int b = has2 ? 1 : 0; b < a.nin; b++) input(acc, s, b, prow, pok);
+            if (has2) {
+#pragma unroll
+                for (int nt = 0; nt < NT; nt++) acc2[nt] = acc[nt];
+                input(acc2, s, 0, prow, pok);
+            }
+            mv_outputs<T, NT>(a, sh, s, p0w, acc, acc2, keepX, sr, sx, lane);
+            if (s == 0) {
+#pragma unroll
+                for (int nt = 0; nt < NT; nt++) keepX[nt] = acc2[nt];
+            }
+        }
+    }
+    if (a.partials) mv_norms<T, NT>(a, sh, sr, sx, wave, lane);
+}
+
+// Narrow kernel (every input at most NARROW stored columns, at most NARROW
+// outputs): one thread per grid point, plain FMA with the coefficients read
+// from LDS (every lane reads the same word: a broadcast).  The k-sum runs in
+// input order, columns ascending.
+template <typename T>
+__global__ void __launch_bounds__(256) mvn_kernel(MVDev<T> a)
+{
+    extern __shared__ unsigned char smem[];
+    double *theta = reinterpret_cast<double *>(smem);       // [NARROW]
+    double *red = theta + NARROW;                           // [256][2][NARROW] -> reused
+    T *Cs = reinterpret_cast<T *>(red + 2 * NARROW * 256);  // [K][NARROW]
+    int *cmap = reinterpret_cast<int *>(Cs + a.K * NARROW); // [K]
+    int *opos = cmap + a.K, *wpos = opos + NARROW;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < a.K * NARROW; e += blockDim.x) {
+        const int r = e / NARROW, c = e % NARROW;
+        Cs[e] = c < a.kout ? a.C[r * a.kout + c] : T(0);
+    }
+    int roffs[3], roff = 0;
+    for (int b = 0; b < 3; b++) {
+        roffs[b] = roff;
+        if (b < a.nin) {
+            for (int r = tid; r < a.k[b]; r += blockDim.x) cmap[roff + r] = a.cols[b] ? a.cols[b][r] : r;
+            roff += a.k[b];
+        }
+    }
+    for (int c = tid; c < NARROW; c += blockDim.x) {
+        opos[c] = c < a.kout ? (a.opos ? a.opos[c] : c) : -1;
+        wpos[c] = (c < a.kout && a.wpos) ? a.wpos[c] : -1;
+        theta[c] = (c < a.kout && a.theta) ? a.theta[c] : 0.0;
+    }
+    __syncthreads();
+    const bool has2 = a.out2[0] != nullptr, resid = a.partials != nullptr;
+    double sr[NARROW], sx[NARROW];
+#pragma unroll
+    for (int c = 0; c < NARROW; c++) sr[c] = sx[c] = 0.0;
+
+    for (i64 p = (i64)blockIdx.x * blockDim.x + tid; p < a.N; p += (i64)gridDim.x * blockDim.x) {
+        T keepX[NARROW];
+        for (int s = 0; s < a.nside; s++) {
+            T acc[NARROW], acc2[NARROW];
+#pragma unroll
+            for (int c = 0; c < NARROW; c++) acc[c] = T(0);
+            auto input = [&](T(&tgt)[NARROW], int b) {
+                const T *row = a.in[s][b] + p * a.ld[b];
+                const int *cm = cmap + roffs[b];
+                const T *cr = Cs + roffs[b] * NARROW;
+                T v[NARROW];
+#pragma unroll
+                for (int j = 0; j < NARROW; j++) v[j] = j < a.k[b] ? row[cm[j]] : T(0);
+#pragma unroll
+                for (int j = 0; j < NARROW; j++) {
+                    if (j >= a.k[b]) break;
+#pragma unroll
+                    for (int c = 0; c < NARROW; c++) tgt[c] += v[j] * cr[j * NARROW + c];
+                }
+            };
+            for (int b = has2 ? 1 : 0; b < a.nin; b++) input(acc, b);
+            if (has2) {
+#pragma unroll
+                for (int c = 0; c < NARROW; c++) acc2[c] = acc[c];
+                input(acc2, 0);
+            }
+            T *out = a.out[s], *out2 = a.out2[s];
+#pragma unroll
+            for (int c = 0; c < NARROW; c++) {
+                if (c >= a.kout) break;
+                T v = acc[c];
+                if (a.add && s == 0) v += a.add[p * a.kout + c];
+                if (out && opos[c] >= 0) out[p * a.nout + opos[c]] = v;
+                if (has2) out2[p * a.kout + c] = acc2[c];
+                if (resid && s == 1) {
+                    const double x = (double)keepX[c];
+                    const double rv = (double)acc2[c] - theta[c] * x;
+                    sr[c] += rv * rv;
+                    sx[c] += x * x;
+                    if (wpos[c] >= 0) a.Wout[p * a.nW + wpos[c]] = (T)rv;
+                }
+            }
+            if (s == 0 && has2) {
+#pragma unroll
+                for (int c = 0; c < NARROW; c++) keepX[c] = acc2[c];
+            }
+        }
+    }
+    if (resid) {
+        // fixed-order workgroup sum: per thread slots, then a tree over threads
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < NARROW; c++) {
+            red[(0 * NARROW + c) * 256 + tid] = sr[c];
+            red[(1 * NARROW + c) * 256 + tid] = sx[c];
+        }
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (tid < h)
+                for (int e = 0; e < 2 * NARROW; e++) red[e * 256 + tid] += red[e * 256 + tid + h];
+            __syncthreads();
+        }
+        for (int e = tid; e < 2 * a.kout; e += blockDim.x) {
+            const int which = e / a.kout, c = e % a.kout;
+            a.partials[(i64)blockIdx.x * 2 * a.kout + e] = red[(which * NARROW + c) * 256];
+        }
+    }
+}
+
 // sums[e] = sum over workgroups of partials[b][e]: one workgroup per entry,
 // strided partial sums then a fixed-shape tree, so the order never changes.
 __global__ void __launch_bounds__(256) mv_reduce_kernel(const double *__restrict__ partials, int nb, int width,
@@ -422,13 +661,27 @@ static hipError_t run_mv(const MVArgs &h, hipStream_t st)
     a.N = h.N;
     const int NC = NT * 16;
     const int nb = mv_blocks(h.N);
-    const bool staged = any_wide && h.variant == 0;
-    size_t shm = (staged ? (size_t)TP * LDT * sizeof(T) : 0) + (size_t)(a.Kp + 4) * NC * sizeof(T);
-    shm = (shm + 7) / 8 * 8 + (size_t)NC * 8 + (size_t)16 * 2 * NC * 8 + (size_t)(a.K + 4 + 2 * NC) * sizeof(int);
-    if (staged)
-        hipLaunchKernelGGL((mv_kernel<T, NT>), dim3(nb), dim3(256), shm, st, a);
-    else
-        hipLaunchKernelGGL((mvd_kernel<T, NT>), dim3(nb), dim3(256), shm, st, a);
+    bool narrow = h.kout <= NARROW;
+    for (int b = 0; b < h.nin; b++) narrow = narrow && h.ld[b] <= NARROW;
+    const size_t tail = (size_t)NC * 8 + (size_t)16 * 2 * NC * 8 + (size_t)(a.K + 4 + 2 * NC) * sizeof(int);
+    if (h.variant == 0 && narrow) {
+        const size_t shm = (size_t)NARROW * 8 + (size_t)2 * NARROW * 256 * 8 + (size_t)a.K * NARROW * sizeof(T) +
+                           (size_t)(a.K + 2 * NARROW) * sizeof(int);
+        hipLaunchKernelGGL((mvn_kernel<T>), dim3(nb), dim3(256), shm, st, a);
+    } else if (h.variant == 0) {
+        int nsteps = 0;
+        for (int b = 0; b < h.nin; b++) nsteps += (h.k[b] + 3) / 4;
+        const size_t shm = (size_t)nsteps * NT * 64 * sizeof(T) + tail;
+        hipLaunchKernelGGL((mvf_kernel<T, NT>), dim3(nb), dim3(256), shm, st, a);
+    } else {
+        const bool staged = any_wide && h.variant == 2;
+        size_t shm = (staged ? (size_t)TP * LDT * sizeof(T) : 0) + (size_t)(a.Kp + 4) * NC * sizeof(T);
+        shm = (shm + 7) / 8 * 8 + tail;
+        if (staged)
+            hipLaunchKernelGGL((mv_kernel<T, NT>), dim3(nb), dim3(256), shm, st, a);
+        else
+            hipLaunchKernelGGL((mvd_kernel<T, NT>), dim3(nb), dim3(256), shm, st, a);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !h.partials) return e;
     hipLaunchKernelGGL(mv_reduce_kernel, dim3(2 * h.kout), dim3(256), 0, st, h.partials, nb, 2 * h.kout, h.sums);

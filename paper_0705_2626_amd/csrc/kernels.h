@@ -20,6 +20,9 @@ hipError_t launch_laplace7(int dtype, const Grid3 &g, int k, const void *u, void
 // out = x + omega/(6 s) (b - s L7 x)        (weighted Jacobi on s*L7)
 hipError_t launch_jacobi(int dtype, const Grid3 &g, int k, const void *x, const void *b, void *out, double s,
                          double omega, hipStream_t st);
+// out = two weighted-Jacobi sweeps on s*L7 from x = 0 with right-hand side b
+hipError_t launch_jacobi2_zero(int dtype, const Grid3 &g, int k, const void *b, void *out, double s, double omega,
+                               hipStream_t st);
 // out = b - s L7 x
 hipError_t launch_resid7(int dtype, const Grid3 &g, int k, const void *x, const void *b, void *out, double s,
                          hipStream_t st);
@@ -70,7 +73,8 @@ struct MVArgs {
     double *partials;       // [mv_blocks(N)][2 kout]
     double *sums;           // [2 kout]
     long long N;
-    int variant;            // 0: tiles staged through LDS, 1: fragments straight from global memory
+    int variant;            // 0: by shape (narrow: one point per thread; else 16-byte fragment loads),
+                            // 1: per-element fragment loads, 2: tiles staged through LDS
 };
 int mv_blocks(long long N);
 hipError_t launch_mv(int dtype, const MVArgs &a, hipStream_t st);

@@ -472,8 +472,14 @@ void *vcycle(lobpcg_ctx *c, int l, const void *b, void *xa, void *xb, int k, hip
         return cur;
     }
     void *cur = xa, *oth = xb;
-    chk(launch_scale(dt, g.n() * k, b, cur, c->T.nu_pre > 0 ? om / (6.0 * s) : 0.0, c->st));
-    for (int i = 1; i < c->T.nu_pre; i++) {
+    int pre = 1;
+    if (c->T.nu_pre >= 2) {
+        chk(launch_jacobi2_zero(dt, g, k, b, cur, s, om, c->st));
+        pre = 2;
+    } else {
+        chk(launch_scale(dt, g.n() * k, b, cur, c->T.nu_pre > 0 ? om / (6.0 * s) : 0.0, c->st));
+    }
+    for (int i = pre; i < c->T.nu_pre; i++) {
         chk(launch_jacobi(dt, g, k, cur, b, oth, s, om, c->st));
         std::swap(cur, oth);
     }
@@ -959,9 +965,9 @@ int lobpcg_setup(lobpcg_ctx **out, const lobpcg_op *A, const lobpcg_op *B, const
         return LOBPCG_ERR_HIP;
     }
     c->coef_slot = 0;
-    c->switch_tol = 1e-5;
-    c->stall_window = 5;
-    c->stall_factor = 0.7;
+    c->switch_tol = 3e-7;
+    c->stall_window = 10;
+    c->stall_factor = 0.95;
     c->profile = false;
     c->reactivate = true;
     c->mv_variant = 0;
@@ -1009,9 +1015,9 @@ int lobpcg_set_option(lobpcg_ctx *c, int key, double v)
     case LOBPCG_OPT_REACTIVATE: c->reactivate = v != 0; return LOBPCG_OK;
     case LOBPCG_OPT_FP32_EXPLICIT_GRAM: c->fp32_explicit = v != 0; return LOBPCG_OK;
     case LOBPCG_OPT_KERNELS:
-        if (v < 0 || v > 3) return LOBPCG_ERR_ARG;
-        c->mv_variant = ((int)v & 1) ? 1 : 0;
-        c->gram_staged = ((int)v & 2) != 0;
+        if (v < 0 || v > 7 || ((int)v & 3) == 3) return LOBPCG_ERR_ARG;
+        c->mv_variant = (int)v & 3;
+        c->gram_staged = ((int)v & 4) != 0;
         return LOBPCG_OK;
     default: return LOBPCG_ERR_ARG;
     }

@@ -141,8 +141,8 @@ def test_vcycle_large_coarsest_grid_uses_global_sweeps():
 # ---------------------------------------------------------------- Gram products (steps 17-23, 3, 11, 14)
 
 # variant 0: the kernel chosen by shape (one row per thread for a single block
-# of at most 8 columns), 2: always the LDS-staged MFMA kernel
-@pytest.mark.parametrize("variant", [0, 2])
+# of at most 8 columns), 4: always the LDS-staged MFMA kernel
+@pytest.mark.parametrize("variant", [0, 4])
 @pytest.mark.parametrize("N,widths", [(4096, (8, 3, 3)), (33 * 17 * 9, (32, 32, 32)), (1000, (4,)),
                                       (70001, (16, 16)), (5003, (5, 7, 2)), (200000, (32, 17, 17)),
                                       (300007, (1,)), (12345, (32, 1, 1))])
@@ -161,7 +161,7 @@ def test_gram_fp64(N, widths, variant):
     np.testing.assert_allclose(SS, SS.T)      # lower triangle mirrored
 
 
-@pytest.mark.parametrize("variant", [0, 2])
+@pytest.mark.parametrize("variant", [0, 4])
 @pytest.mark.parametrize("N,widths", [(4096, (8, 3, 3)), (70001, (32, 32, 32)), (5003, (5, 7, 2)),
                                       (99999, (32, 1, 1)), (77777, (2,))])
 def test_gram_fp32(N, widths, variant):
@@ -199,13 +199,16 @@ def test_gram_is_deterministic():
 
 # ---------------------------------------------------------------- combinations (steps 3-4, 11, 14-15, 27-32)
 
+# shapes: narrow (one point per thread), wide with 16-byte fragment loads,
+# wide with a column map, ragged k (not a multiple of 4) and tiny N
 @pytest.mark.parametrize("N,ks,kout,use_cols", [(5000, (8,), 8, False), (4099, (8, 3, 3), 8, False),
                                                 (70001, (32, 32, 32), 32, False), (1234, (6, 5), 4, True),
-                                                (9999, (7,), 7, True)])
+                                                (9999, (7,), 7, True), (3001, (5, 2), 3, True), (3, (1,), 1, False),
+                                                (777, (30, 9), 17, False), (2049, (12, 4), 12, True)])
 @pytest.mark.parametrize("prec", [L.FP64, L.MIXED])
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_combine(N, ks, kout, use_cols, prec, variant):
-    ctx = ctx_for((N, 1, 1), 32, None, L.MIXED)
+    ctx = ctx_for((N, 1, 1), min(32, N // 3), None, L.MIXED)
     L.lobpcg_set_option(ctx, L.OPT_KERNELS, variant)
     dtype = torch.float64 if prec == L.FP64 else torch.float32
     rng = np.random.default_rng(N + kout)

@@ -190,10 +190,11 @@ def test_error_paths():
         L.lobpcg_solve(ctx, dev(synth.x0_uniform(N, m)), -1.0, 10)
 
 
-@pytest.mark.parametrize("variant", [1, 2])
-def test_kernel_variants_give_the_same_solution(variant):
-    """The LDS-staged multivector / Gram kernels and the direct ones agree."""
-    dims, m = (20, 18, 16), 6
+@pytest.mark.parametrize("variant", [1, 2, 4])
+@pytest.mark.parametrize("m", [6, 12])
+def test_kernel_variants_give_the_same_solution(variant, m):
+    """The default multivector / Gram kernels and the other variants agree."""
+    dims = (20, 18, 16)
     N = int(np.prod(dims))
     X0 = dev(synth.x0_uniform(N, m))
     res = []
