@@ -9,10 +9,16 @@ time (FP32 iterations, FP64 refinement); the plain FP64 solve is timed beside
 it.  The start block is resident in HBM before the timed region starts.
 
 Also reported:
-  roofline      the 7-point block stencil (the "SpMM" of the metric) on the
+  spmm          the 7-point block stencil (the "SpMM" of the metric) on the
                 N x 32 FP32 block, timed with HIP events on the library's
                 stream: algorithmic bytes 2*N*m*4 per launch / average launch
-                time, against 8 TB/s
+                time
+  steps         one more mixed (and FP64) solve with HIP events around every
+                step class on the library's stream: time, calls, the
+                algorithmic bytes the library counts for the step's kernels
+                (operands read once, results written once) and their ratio
+  roofline      that ratio for the step class with the most time in the
+                mixed solve, against 8 TB/s
   cpu_baseline  the FP64 CPU oracle on the host's cores: its setup plus one
                 LOBPCG iteration at the same size, extrapolated to the
                 iteration count of the FP64 GPU solve
@@ -46,7 +52,8 @@ def main():
     ap.add_argument("--spmm-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--profile-steps", action="store_true", help="one extra solve with per-step HIP-event timing")
+    ap.add_argument("--no-profile-steps", action="store_true",
+                    help="skip the extra solve with per-step HIP-event timing (then the roofline is the stencil's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see the design notes on how "
@@ -82,13 +89,19 @@ def main():
         dt = (time.perf_counter() - t0) / K
         stats = L.lobpcg_get_stats(ctx)
         steps = None
-        if args.profile_steps:
+        if not args.no_profile_steps:
+            # one more solve with HIP events around every step class on the
+            # library's stream; the library also counts each step's
+            # algorithmic bytes, so achieved GB/s = bytes / event time
             L.lobpcg_set_option(ctx, L.OPT_PROFILE, 1)
-            rp = L.lobpcg_solve(ctx, X0, tol, args.maxit, hist=True)
-            steps = dict(L.lobpcg_get_stats(ctx)["step_ms"])
-            # active-set sizes (soft locking: a column leaves J once its residual is below tol)
-            h = np.asarray(rp.hist)
-            steps["active_cols_per_iter"] = np.logical_and.accumulate(h > tol, axis=0).sum(axis=1).tolist()
+            L.lobpcg_solve(ctx, X0, tol, args.maxit, hist=False)
+            st = L.lobpcg_get_stats(ctx)
+            steps = {}
+            for k in st["step_ms"]:
+                ms, by, calls = st["step_ms"][k], st["step_bytes"][k], st["step_calls"][k]
+                steps[k] = {"ms": ms, "calls": calls, "GB": by / 1e9,
+                            "GBps": (by / (ms * 1e-3) / 1e9) if ms > 0 and by > 0 else None}
+            L.lobpcg_set_option(ctx, L.OPT_PROFILE, 0)
         for r in results:
             assert r.status == L.OK, L.status_string(r.status)
         r = results[-1]
@@ -105,7 +118,7 @@ def main():
         t64, acc64, steps64, r64 = run(L.FP64, args.steps, args.warmup)
         fp64 = {"value": t64, "unit": "s", "ms_per_step": 1e3 * t64, **acc64}
         if steps64:
-            fp64["steps_ms"] = steps64
+            fp64["steps"] = steps64
         lam_agree = float(np.max(np.abs(r_mixed.lam / r64.lam - 1)))
     else:
         lam_agree = None
@@ -148,11 +161,23 @@ def main():
         "speedup_mixed_vs_fp64": (fp64["value"] / t_mixed) if fp64 else None,
         "mixed_vs_fp64_max_rel_lambda_diff": lam_agree,
         "spmm": {"GBps": spmm_gbps, "dtype": "f32", "block": [N, m], "ms": spmm_ms},
-        "roofline": {"bound": "hbm", "achieved": spmm_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": spmm_gbps / HBM_PEAK_GBPS, "traffic": None, "kernel": "stencil7 f32 N x 32"},
     }
     if steps_mixed:
-        out["mixed"]["steps_ms"] = steps_mixed
+        out["mixed"]["steps"] = steps_mixed
+        # the dominant step class of the headline (mixed) solve
+        kern = {"precond": "V-cycle kernels (stencil7 Jacobi/residual, restrict, prolong_add)",
+                "gram": "gram_kernel / gram_rows_kernel (steps 17-23)",
+                "update": "mvf_kernel / mvn_kernel, fused Ritz update + residual (steps 25-33, 7)",
+                "ortho": "Cholesky-QR Grams and multivector products (steps 11, 14-15)",
+                "apply_A": "stencil7 A*W (step 12)", "residual": "residual_kernel (step 7)"}
+        name = max(kern, key=lambda k: steps_mixed[k]["ms"])
+        d = steps_mixed[name]
+        out["roofline"] = {"bound": "hbm", "achieved": d["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                           "frac": d["GBps"] / HBM_PEAK_GBPS, "traffic": None, "step": name, "kernel": kern[name],
+                           "ms": d["ms"], "calls": d["calls"], "algorithmic_GB": d["GB"]}
+    else:
+        out["roofline"] = {"bound": "hbm", "achieved": spmm_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                           "frac": spmm_gbps / HBM_PEAK_GBPS, "traffic": None, "kernel": "stencil7 f32 N x 32"}
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dims, m, levels, X0.cpu().numpy(),

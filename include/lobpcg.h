@@ -137,7 +137,8 @@ enum {
                                     /* 1 = per-element fragment loads, 2 = tiles       */
                                     /* staged through LDS (3 is invalid); bit 2: the   */
                                     /* multi-column-tile Gram kernel also for narrow   */
-                                    /* single-block Grams                              */
+                                    /* single-block Grams; bit 3: up to four Gram      */
+                                    /* tiles per wave (default two)                    */
     LOBPCG_OPT_FP32_EXPLICIT_GRAM = 6 /* MIXED: 1 (default) FP32 iterations compute    */
                                     /* X^T X, X^T AX, W^T W, P^T P rather than taking  */
                                     /* I and Lambda for them as the paper's form does  */
@@ -162,6 +163,10 @@ typedef struct lobpcg_stats {
     double solve_ms;            /* host wall time of the last lobpcg_solve  */
     double step_ms[LOBPCG_NSTEP];   /* summed HIP-event times (OPT_PROFILE)  */
     int step_calls[LOBPCG_NSTEP];
+    double step_bytes[LOBPCG_NSTEP];/* algorithmic HBM bytes of the step's   */
+                                    /* kernels: each operand the arithmetic  */
+                                    /* needs read once, each result written  */
+                                    /* once (always counted)                 */
 } lobpcg_stats;
 int lobpcg_get_stats(const lobpcg_ctx *ctx, lobpcg_stats *stats);
 
@@ -181,9 +186,12 @@ int lobpcg_apply_T(lobpcg_ctx *ctx, int dtype, const void *d_in, void *d_out, in
  * n <= 3 blocks of widths w_i (sum K <= 3m), all N x w_i of type dtype:
  * h_SS = S^T S and h_SAS = S^T AS, K x K row-major FP64 on the host, upper
  * triangle (entries (a, b), a <= b) computed, the strict lower triangle
- * mirrored from it.  Accumulation is FP64 across row chunks. */
+ * mirrored from it.  Accumulation is FP64 across row chunks.  paper_form = 1
+ * (needs AS and n >= 2) computes only the entries the paper's form of steps
+ * 17-23 does not take as known -- S^T S off the block diagonal, S^T AS outside
+ * the S_0-S_0 block -- and returns zero for the others. */
 int lobpcg_gram(lobpcg_ctx *ctx, int dtype, int n, const void *const *d_S, const void *const *d_AS,
-                const int *w, double *h_SS, double *h_SAS);
+                const int *w, int paper_form, double *h_SS, double *h_SAS);
 
 /* Multivector combination used by steps 3-4, 11, 14-15 and 25-33:
  * d_out (N x kout) = sum_i in_i[:, cols_i] C_i (+ d_add if not NULL), with

@@ -1,180 +1,197 @@
 // Tall-skinny Gram products of LOBPCG on MFMA (gfx950).
 //
-// For S = [S_0 S_1 S_2] (the blocks X, W_J, P_J; N x K in total) and
-// AS = [AS_0 AS_1 AS_2] it computes chosen 16x16 tiles of S^T S and S^T AS:
-// the blocks of gramB and gramA that the Rayleigh-Ritz procedure of steps
-// 17-23 needs, and the Cholesky Gram matrices of steps 3, 11 and 14 (one
-// block, S^T S only).  The host lists the tiles, so blocks the paper's form
-// takes as known (Lambda and I on the block diagonal) are not computed.
+// The Rayleigh-Ritz matrices of steps 17-23 and the Cholesky Gram matrices
+// of steps 3, 11 and 14 are all entries of Lm^T Rm, where the columns of the
+// N x KL matrix Lm and of the N x KR matrix Rm are columns of the blocks X,
+// W_J, P_J, AX, AW_J, AP_J.  The host lists the columns of Lm and Rm (so that
+// thin blocks can share one 16-column MFMA tile: Rm = [W P AW AP] in the
+// paper's form) and the 16 x 16 tiles of Lm^T Rm that hold a needed entry.
 //
-// Each workgroup (8 waves) stages a chunk of RC rows of S and AS in LDS
-// (zero-padded to a multiple of 16 columns and past the end of the grid);
-// each wave accumulates up to MAXT output tiles with
-// v_mfma_f64_16x16x4f64 (FP64 blocks, accumulated in FP64 throughout) or
-// v_mfma_f32_16x16x4f32 (FP32 blocks: FP32 only within one RC-row chunk,
-// then added into FP64 accumulators).  Per-workgroup partial tiles are
-// summed in a fixed order by a second kernel: results are reproducible bit
-// for bit.
+// Each wave computes up to GX_MAXB tiles that share one 16-column block of
+// Lm, with 16x16x4 MFMA whose operands are loaded straight from global
+// memory: at k-step q lane l holds Lm[4q + l/16][16a + l%16] and
+// Rm[4q + l/16][16b + l%16], 16 consecutive elements of a row for 16 lanes.
+// There is no workgroup barrier in the main loop; waves of a workgroup walk
+// the same rows, so operand blocks shared by several waves are served by the
+// cache.  FP64 blocks accumulate in FP64 throughout; FP32 blocks use FP32
+// MFMA within one 64-row chunk, then add the chunk into FP64 accumulators.
+// Per-workgroup partial tiles are summed in a fixed order by a second
+// kernel: results are reproducible bit for bit.
 #include "common.h"
 #include "kernels.h"
 #include "mfma.h"
 
+#include <algorithm>
+
 namespace lobpcg {
 
-static const int WAVES = 8;
-static const int MAXT = 6;                // tiles per wave per pass
-static const int TILES_PER_GROUP = WAVES * MAXT;
-static const int PAD = 16;                // LDS row padding (elements)
-static const int GRAM_BLOCKS = 512;
+static const int GX_WAVES = 4;
+static const int GX_CH = 64;              // rows per chunk (16 k-steps)
+static const int GX_BLOCKS = 1024;
 
 template <typename T>
-struct GramRC;
-template <>
-struct GramRC<float> {
-    static const int v = 64;
-};
-template <>
-struct GramRC<double> {
-    static const int v = 32;
-};
-
-template <typename T>
-struct GramDev {
-    const T *S[3], *AS[3];
-    int w[3], off[3];
-    int nblk, K, Kp, ntiles, has_as;
-    int tiles[GRAM_MAX_TILES];   // (mat << 16) | (a << 8) | b
+struct GXDev {
+    const T *arr[GX_MAX_ARR];
+    int ld[GX_MAX_ARR];
+    int KL, KR;
+    unsigned short lmap[GX_MAX_L], rmap[GX_MAX_R];   // (array << 8) | column
+    int ngroups, ntiles;
+    unsigned char ga[GX_MAX_TILES];                 // per group: Lm block
+    unsigned char gtile[GX_MAX_TILES][GX_MAXB];     // per group: its tiles (255: an empty slot)
+    unsigned char tb[GX_MAX_TILES];                 // per tile: Rm block
     i64 N;
-    double *partials;
+    double *partials;   // [gridDim.x][ntiles][256]
 };
 
-template <typename T>
-__global__ void __launch_bounds__(512) gram_kernel(GramDev<T> a)
+template <typename T, int NT, int UNR>
+__global__ void __launch_bounds__(256) gramx_kernel(GXDev<T> a)
 {
     typedef typename Mfma<T>::acc accT;
-    const int RC = GramRC<T>::v;
-    extern __shared__ unsigned char smem[];
-    const int ldl = a.Kp + PAD;
-    T *Ss = reinterpret_cast<T *>(smem);
-    T *As = Ss + RC * ldl;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int tbase = blockIdx.y * TILES_PER_GROUP + wave;
+    __shared__ double red[GX_WAVES][NT][256];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, kq = lane >> 4, lc = lane & 15;
+    // workgroup -> (row slice, tile group), consecutive ids on one XCD: the
+    // groups of one row slice read the same rows, so they share that L2
+    const unsigned id = xcd_remap(blockIdx.x, gridDim.x);
+    const int g = (int)(id % (unsigned)a.ngroups);
+    const unsigned slice = id / (unsigned)a.ngroups, nslices = gridDim.x / (unsigned)a.ngroups;
+    const int rsub = wave, nsub = GX_WAVES;   // the waves split the rows of a chunk
 
-    int tmat[MAXT], ta[MAXT], tb[MAXT];
-#pragma unroll
-    for (int j = 0; j < MAXT; j++) {
-        const int t = tbase + WAVES * j;
-        if (t < a.ntiles) {
-            const int code = a.tiles[t];
-            tmat[j] = code >> 16;
-            ta[j] = (code >> 8) & 255;
-            tb[j] = code & 255;
-        } else {
-            tmat[j] = -1, ta[j] = tb[j] = 0;
+    // this lane's column of Lm and of the Rm blocks of the group's tiles
+    const T *pl = a.arr[0];
+    int ldl = 0;
+    bool okl = false;
+    {
+        const int cl = 16 * a.ga[g] + lc;
+        if (cl < a.KL) {
+            const int code = a.lmap[cl];
+            pl = a.arr[code >> 8] + (code & 255);
+            ldl = a.ld[code >> 8];
+            okl = true;
         }
     }
-    accT acc[MAXT];      // FP64: running sums; FP32: the current chunk
-    double acc64[MAXT][4];
+    const T *pr[NT];
+    int ldr[NT];
+    bool okr[NT];
 #pragma unroll
-    for (int j = 0; j < MAXT; j++) {
+    for (int j = 0; j < NT; j++) {
+        pr[j] = a.arr[0], ldr[j] = 0, okr[j] = false;
+        const int t = a.gtile[g][j];
+        if (t != 255) {
+            const int cr = 16 * a.tb[t] + lc;
+            if (cr < a.KR) {
+                const int code = a.rmap[cr];
+                pr[j] = a.arr[code >> 8] + (code & 255);
+                ldr[j] = a.ld[code >> 8];
+                okr[j] = true;
+            }
+        }
+    }
+
+    accT acc[NT];
+    double acc64[NT][4];
+#pragma unroll
+    for (int j = 0; j < NT; j++) {
         acc[j] = acc_zero<T>();
 #pragma unroll
         for (int r = 0; r < 4; r++) acc64[j][r] = 0.0;
     }
-    // zero the padding columns once; staging never writes them
-    const int npad = a.Kp - a.K;
-    for (int e = tid; e < RC * npad; e += blockDim.x) {
-        const int row = e / npad, col = a.K + e % npad;
-        Ss[row * ldl + col] = T(0);
-        As[row * ldl + col] = T(0);
-    }
-
-    // Chunk ch of block b is the contiguous run of RC*w_b elements at
-    // S_b + ch*RC*w_b; every thread moves at most one 16-byte vector of each
-    // of S_b and AS_b per chunk.  The next chunk is loaded into registers
-    // while the current one is multiplied.
-    const int VE = 16 / sizeof(T);
-    const i64 nchunks = (a.N + RC - 1) / RC;
-    const int lrow = lane >> 4, lcol = lane & 15;
-    vec<T, VE> rs[3], ra[3];
-    auto load = [&](i64 ch) {
-        const i64 r0 = ch * RC;
-        const int nvalid = (int)(((a.N - r0) < RC ? (a.N - r0) : RC));
+    // the wave's share of a chunk: k-steps s0 .. s0+ksteps-1 (4 rows each),
+    // taken UNR at a time; the loads of the next UNR k-steps (of this chunk or
+    // the next) are in flight while the current ones are multiplied
+    const int ksteps = (GX_CH / 4) / nsub, s0 = rsub * ksteps;
+    const int gpc = ksteps / UNR;                     // step groups per chunk
+    const i64 nchunks = (a.N + GX_CH - 1) / GX_CH;
+    const i64 mychunks = nchunks > (i64)slice ? (nchunks - 1 - slice) / nslices + 1 : 0;
+    const i64 ngrp = mychunks * gpc;
+    auto rowof = [&](i64 ch, int gi) { return ch * GX_CH + 4 * (s0 + gi * UNR) + kq; };
+    auto load = [&](T(&av)[UNR], T(&bv)[UNR][NT], i64 row) {
+        const T *ql = pl + row * ldl;
+        const T *qr[NT];
 #pragma unroll
-        for (int b = 0; b < 3; b++) {
-            if (b >= a.nblk) break;
-            const int wb = a.w[b];
-            const int e0 = tid * VE;
-            if (e0 >= RC * wb) continue;
-            const T *sb = a.S[b] + r0 * wb;
-            const T *ab = a.has_as ? a.AS[b] + r0 * wb : nullptr;
-            if (e0 + VE <= nvalid * wb) {
-                rs[b] = vload<T, VE>(sb + e0);
-                if (ab) ra[b] = vload<T, VE>(ab + e0);
-            } else {
+        for (int j = 0; j < NT; j++) qr[j] = pr[j] + row * ldr[j];
+        if (row + 4 * (UNR - 1) < a.N) {
+            // every row present: plain loads (a lane without a column reads
+            // element 0 of array 0 and drops it)
 #pragma unroll
-                for (int q = 0; q < VE; q++) {
-                    const bool ok = e0 + q < nvalid * wb;
-                    rs[b].v[q] = ok ? sb[e0 + q] : T(0);
-                    if (ab) ra[b].v[q] = ok ? ab[e0 + q] : T(0);
-                }
+            for (int u = 0; u < UNR; u++) {
+                av[u] = ql[4 * u * ldl];
+#pragma unroll
+                for (int j = 0; j < NT; j++) bv[u][j] = qr[j][4 * u * ldr[j]];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < UNR; u++) {
+                const bool rok = row + 4 * u < a.N;
+                av[u] = rok ? ql[4 * u * ldl] : T(0);
+#pragma unroll
+                for (int j = 0; j < NT; j++) bv[u][j] = rok ? qr[j][4 * u * ldr[j]] : T(0);
             }
         }
     };
-    if ((i64)blockIdx.x < nchunks) load(blockIdx.x);
-    for (i64 ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-        __syncthreads();
+    T av[UNR], bv[UNR][NT];
+    i64 ch = slice;        // chunk and step group of the loads in flight
+    int gi = 0;
+    if (ngrp > 0) load(av, bv, rowof(ch, gi));
+    for (i64 idx = 0; idx < ngrp; idx++) {
+        T an[UNR], bn[UNR][NT];
+        const bool more = idx + 1 < ngrp;
+        const bool chunk_end = gi == gpc - 1;
+        if (++gi == gpc) gi = 0, ch += nslices;
+        if (more) load(an, bn, rowof(ch, gi));
 #pragma unroll
-        for (int b = 0; b < 3; b++) {
-            if (b >= a.nblk) break;
-            const int wb = a.w[b];
-            const int e0 = tid * VE;
-            if (e0 >= RC * wb) continue;
-            const float inv = 1.0f / (float)wb;
+        for (int u = 0; u < UNR; u++) {
+            const T x = okl ? av[u] : T(0);
 #pragma unroll
-            for (int q = 0; q < VE; q++) {
-                // e < 64*32: the float quotient is within 2e-4 of e/wb, and
-                // (e + 0.5)/wb is at least 0.5/32 away from an integer
-                const int e = e0 + q;
-                const int row = (int)(((float)e + 0.5f) * inv);
-                const int col = a.off[b] + e - row * wb;
-                Ss[row * ldl + col] = rs[b].v[q];
-                if (a.has_as) As[row * ldl + col] = ra[b].v[q];
-            }
+            for (int j = 0; j < NT; j++) acc[j] = Mfma<T>::mma(x, okr[j] ? bv[u][j] : T(0), acc[j]);
         }
-        if (ch + gridDim.x < nchunks) load(ch + gridDim.x);
-        __syncthreads();
-#pragma unroll 2
-        for (int kk = 0; kk < RC; kk += 4) {
-            const T *srow = Ss + (kk + lrow) * ldl + lcol;
-            const T *arow = As + (kk + lrow) * ldl + lcol;
+        if (sizeof(T) == 4 && chunk_end) {
+            // end of a chunk: FP32 partial sums into the FP64 accumulators
 #pragma unroll
-            for (int j = 0; j < MAXT; j++) {
-                if (tmat[j] < 0) continue;
-                const T x = srow[16 * ta[j]];
-                const T y = tmat[j] ? arow[16 * tb[j]] : srow[16 * tb[j]];
-                acc[j] = Mfma<T>::mma(x, y, acc[j]);
-            }
-        }
-        if (sizeof(T) == 4) {
-#pragma unroll
-            for (int j = 0; j < MAXT; j++) {
+            for (int j = 0; j < NT; j++) {
 #pragma unroll
                 for (int r = 0; r < 4; r++) acc64[j][r] += (double)acc[j][r];
                 acc[j] = acc_zero<T>();
             }
         }
-    }
-    // partials[bx][tile][r*64 + lane]
-    double *dst = a.partials + (i64)blockIdx.x * a.ntiles * 256;
+        if (more) {
 #pragma unroll
-    for (int j = 0; j < MAXT; j++) {
-        const int t = tbase + WAVES * j;
-        if (t >= a.ntiles) continue;
+            for (int u = 0; u < UNR; u++) {
+                av[u] = an[u];
 #pragma unroll
-        for (int r = 0; r < 4; r++)
-            dst[(i64)t * 256 + r * 64 + lane] = sizeof(T) == 4 ? acc64[j][r] : (double)acc[j][r];
+                for (int j = 0; j < NT; j++) bv[u][j] = bn[u][j];
+            }
+        }
     }
+    // the four waves' sums in a fixed order: one partial tile per row slice
+#pragma unroll
+    for (int j = 0; j < NT; j++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) red[wave][j][r * 64 + lane] = sizeof(T) == 4 ? acc64[j][r] : (double)acc[j][r];
+    __syncthreads();
+    for (int e = tid; e < NT * 256; e += blockDim.x) {
+        const int j = e / 256, q = e % 256;
+        const int t = a.gtile[g][j];
+        if (t == 255) continue;
+        const double s = (red[0][j][q] + red[1][j][q]) + (red[2][j][q] + red[3][j][q]);
+        a.partials[((i64)slice * a.ntiles + t) * 256 + q] = s;
+    }
+}
+
+// out[t][e] = sum over workgroups of partials[b][t][e]: 4 threads per entry
+// in strided order, then a fixed combination.
+__global__ void __launch_bounds__(256) gramx_reduce_kernel(const double *__restrict__ partials, int nb, int ntiles,
+                                                           double *__restrict__ out)
+{
+    __shared__ double red[4][64];
+    const i64 total = (i64)ntiles * 256;
+    const int sub = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const i64 q = (i64)blockIdx.x * 64 + lane;
+    double s = 0.0;
+    if (q < total)
+        for (int b = sub; b < nb; b += 4) s += partials[(i64)b * total + q];
+    red[sub][lane] = s;
+    __syncthreads();
+    if (sub == 0 && q < total) out[q] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
 }
 
 // A single narrow block (S^T S for W_J or P_J with at most 8 columns, the
@@ -237,120 +254,119 @@ __global__ void __launch_bounds__(256) gram_rows_reduce_kernel(const double *__r
 }
 
 template <typename T>
-static hipError_t run_gram_rows(const GramArgs &h, hipStream_t st)
+static hipError_t run_gram_rows(const T *S, int W, long long N, double *partials, double *out, int Kp, hipStream_t st)
 {
-    const int W = h.w[0], Kp = gram_kpad(W);
-    const i64 nb64 = (h.N + 255) / 256;
+    const i64 nb64 = (N + 255) / 256;
     const int nb = (int)(nb64 < RBLOCKS ? (nb64 > 0 ? nb64 : 1) : RBLOCKS);
-    const T *S = (const T *)h.S[0];
     switch (W) {
-    case 1: hipLaunchKernelGGL((gram_rows_kernel<T, 1>), dim3(nb), dim3(256), 0, st, S, (i64)h.N, h.partials); break;
-    case 2: hipLaunchKernelGGL((gram_rows_kernel<T, 2>), dim3(nb), dim3(256), 0, st, S, (i64)h.N, h.partials); break;
-    case 3: hipLaunchKernelGGL((gram_rows_kernel<T, 3>), dim3(nb), dim3(256), 0, st, S, (i64)h.N, h.partials); break;
-    case 4: hipLaunchKernelGGL((gram_rows_kernel<T, 4>), dim3(nb), dim3(256), 0, st, S, (i64)h.N, h.partials); break;
-    case 5: hipLaunchKernelGGL((gram_rows_kernel<T, 5>), dim3(nb), dim3(256), 0, st, S, (i64)h.N, h.partials); break;
-    case 6: hipLaunchKernelGGL((gram_rows_kernel<T, 6>), dim3(nb), dim3(256), 0, st, S, (i64)h.N, h.partials); break;
-    case 7: hipLaunchKernelGGL((gram_rows_kernel<T, 7>), dim3(nb), dim3(256), 0, st, S, (i64)h.N, h.partials); break;
-    default: hipLaunchKernelGGL((gram_rows_kernel<T, 8>), dim3(nb), dim3(256), 0, st, S, (i64)h.N, h.partials);
+    case 1: hipLaunchKernelGGL((gram_rows_kernel<T, 1>), dim3(nb), dim3(256), 0, st, S, (i64)N, partials); break;
+    case 2: hipLaunchKernelGGL((gram_rows_kernel<T, 2>), dim3(nb), dim3(256), 0, st, S, (i64)N, partials); break;
+    case 3: hipLaunchKernelGGL((gram_rows_kernel<T, 3>), dim3(nb), dim3(256), 0, st, S, (i64)N, partials); break;
+    case 4: hipLaunchKernelGGL((gram_rows_kernel<T, 4>), dim3(nb), dim3(256), 0, st, S, (i64)N, partials); break;
+    case 5: hipLaunchKernelGGL((gram_rows_kernel<T, 5>), dim3(nb), dim3(256), 0, st, S, (i64)N, partials); break;
+    case 6: hipLaunchKernelGGL((gram_rows_kernel<T, 6>), dim3(nb), dim3(256), 0, st, S, (i64)N, partials); break;
+    case 7: hipLaunchKernelGGL((gram_rows_kernel<T, 7>), dim3(nb), dim3(256), 0, st, S, (i64)N, partials); break;
+    default: hipLaunchKernelGGL((gram_rows_kernel<T, 8>), dim3(nb), dim3(256), 0, st, S, (i64)N, partials);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(gram_rows_reduce_kernel, dim3(W * (W + 1) / 2), dim3(256), 0, st, h.partials, nb, W, Kp, h.out);
+    hipLaunchKernelGGL(gram_rows_reduce_kernel, dim3(W * (W + 1) / 2), dim3(256), 0, st, partials, nb, W, Kp, out);
     return hipGetLastError();
 }
 
-// out[mat][i][j] (Kp x Kp each) = sum over workgroups: one workgroup per
-// group of 64 tile entries, each entry summed by 4 threads in strided order
-// and then combined in a fixed order, so the result never changes.
-template <typename T>
-__global__ void __launch_bounds__(256) gram_reduce_kernel(const double *__restrict__ partials, int nb, GramDev<T> a,
-                                                          double *__restrict__ out)
+int gram_blocks(long long N)
 {
-    __shared__ double red[4][64];
-    const i64 total = (i64)a.ntiles * 256;
-    const int sub = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const i64 q = (i64)blockIdx.x * 64 + lane;
-    double s = 0.0;
-    if (q < total)
-        for (int b = sub; b < nb; b += 4) s += partials[(i64)b * total + q];
-    red[sub][lane] = s;
-    __syncthreads();
-    if (sub == 0 && q < total) {
-        s = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
-        const int t = (int)(q / 256), e = (int)(q % 256);
-        const int r = e / 64, ln = e % 64;
-        const int code = a.tiles[t];
-        const int mat = code >> 16, ta = (code >> 8) & 255, tb = code & 255;
-        const int i = 16 * ta + Mfma<T>::row(ln, r), j = 16 * tb + (ln & 15);
-        out[(i64)mat * a.Kp * a.Kp + (i64)i * a.Kp + j] = s;
-    }
+    const long long nch = (N + GX_CH - 1) / GX_CH;
+    return (int)(nch < GX_BLOCKS ? (nch > 0 ? nch : 1) : GX_BLOCKS);
 }
 
-int gram_kpad(int K) { return (K + 15) / 16 * 16; }
-
-static int gram_blocks(long long N)
+size_t gram_partials_bytes(long long N)
 {
-    const long long nch = (N + 31) / 32;
-    return (int)(nch < GRAM_BLOCKS ? (nch > 0 ? nch : 1) : GRAM_BLOCKS);
-}
-
-size_t gram_partials_bytes(int dtype, long long N, int K)
-{
-    (void)dtype;
-    const int TK = gram_kpad(K) / 16;
-    const size_t ntiles = (size_t)TK * (TK + 1);
-    const size_t staged = (size_t)gram_blocks(N) * ntiles * 256 * sizeof(double);
+    const size_t tiles = (size_t)gram_blocks(N) * GX_MAX_TILES * 256 * sizeof(double);
     const size_t rows = (size_t)RBLOCKS * 36 * sizeof(double);
-    return staged > rows ? staged : rows;
+    return tiles > rows ? tiles : rows;
 }
 
 template <typename T>
-static hipError_t run_gram(const GramArgs &h, hipStream_t st)
+static hipError_t run_gramx(const GramXArgs &h, hipStream_t st)
 {
-    if (!h.staged && h.nblk == 1 && !h.AS[0] && h.w[0] >= 1 && h.w[0] <= 8) return run_gram_rows<T>(h, st);
-    GramDev<T> a;
-    int K = 0;
-    for (int b = 0; b < 3; b++) {
-        a.S[b] = (const T *)h.S[b];
-        a.AS[b] = (const T *)h.AS[b];
-        a.w[b] = b < h.nblk ? h.w[b] : 0;
-        a.off[b] = K;
-        if (b < h.nblk) K += h.w[b];
+    GXDev<T> a;
+    for (int i = 0; i < GX_MAX_ARR; i++) {
+        a.arr[i] = (const T *)h.arr[i];
+        a.ld[i] = h.ld[i];
     }
-    a.nblk = h.nblk;
-    a.K = K;
-    a.Kp = gram_kpad(K);
-    a.has_as = h.AS[0] != nullptr;
+    a.KL = h.KL;
+    a.KR = h.KR;
+    for (int i = 0; i < h.KL; i++) {
+        const int ar = h.lmap[i] >> 8, col = h.lmap[i] & 255;
+        if (ar >= GX_MAX_ARR || !h.arr[ar] || col >= h.ld[ar]) return hipErrorInvalidValue;
+        a.lmap[i] = h.lmap[i];
+    }
+    for (int i = 0; i < h.KR; i++) {
+        const int ar = h.rmap[i] >> 8, col = h.rmap[i] & 255;
+        if (ar >= GX_MAX_ARR || !h.arr[ar] || col >= h.ld[ar]) return hipErrorInvalidValue;
+        a.rmap[i] = h.rmap[i];
+    }
+    // tiles grouped by their Lm block, NT slots per group (the widest run of
+    // one Lm block, at most GX_MAXB); empty slots compute nothing useful
+    int NT = 1;
+    for (int t = 0; t < h.ntiles;) {
+        int n = 0;
+        while (t + n < h.ntiles && h.ta[t + n] == h.ta[t]) n++;
+        NT = std::max(NT, std::min(n, std::max(1, std::min(h.max_nt, GX_MAXB))));
+        t += n;
+    }
+    if (NT == 3) NT = 4;
     a.ntiles = h.ntiles;
-    if (a.ntiles < 1 || a.ntiles > GRAM_MAX_TILES || K > 96) return hipErrorInvalidValue;
-    // one 16-byte vector per thread and block covers a chunk: RC*w_b <= 512*VE
-    for (int b = 0; b < a.nblk; b++)
-        if (a.w[b] < 1 || (size_t)GramRC<T>::v * a.w[b] > 512 * (16 / sizeof(T))) return hipErrorInvalidValue;
-    for (int t = 0; t < a.ntiles; t++) {
-        const int code = h.tiles[t], mat = code >> 16, ta = (code >> 8) & 255, tb = code & 255;
-        if (mat < 0 || mat > 1 || (mat == 1 && !a.has_as) || ta * 16 >= a.Kp || tb * 16 >= a.Kp)
-            return hipErrorInvalidValue;
-        a.tiles[t] = code;
+    a.ngroups = 0;
+    for (int t = 0; t < h.ntiles;) {
+        const int ta = h.ta[t];
+        int n = 0;
+        while (t + n < h.ntiles && h.ta[t + n] == ta && n < NT) n++;
+        if (a.ngroups >= GX_MAX_TILES) return hipErrorInvalidValue;
+        a.ga[a.ngroups] = (unsigned char)ta;
+        for (int j = 0; j < GX_MAXB; j++) a.gtile[a.ngroups][j] = j < n ? (unsigned char)(t + j) : 255;
+        a.ngroups++;
+        t += n;
     }
+    for (int t = 0; t < h.ntiles; t++) a.tb[t] = (unsigned char)h.tb[t];
     a.N = h.N;
     a.partials = h.partials;
-    int nb;
-    nb = gram_blocks(h.N);
-    const int ngroups = (a.ntiles + TILES_PER_GROUP - 1) / TILES_PER_GROUP;
-    const size_t shm = (size_t)2 * GramRC<T>::v * (a.Kp + PAD) * sizeof(T);
-    hipLaunchKernelGGL(gram_kernel<T>, dim3(nb, ngroups), dim3(64 * WAVES), shm, st, a);
+    const int nb = gram_blocks(h.N);   // row slices
+    const dim3 grid(nb * a.ngroups);
+    if (NT == 1)
+        hipLaunchKernelGGL((gramx_kernel<T, 1, 4>), grid, dim3(64 * GX_WAVES), 0, st, a);
+    else if (NT == 2)
+        hipLaunchKernelGGL((gramx_kernel<T, 2, 4>), grid, dim3(64 * GX_WAVES), 0, st, a);
+    else
+        hipLaunchKernelGGL((gramx_kernel<T, 4, 2>), grid, dim3(64 * GX_WAVES), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const i64 total = (i64)a.ntiles * 256;
-    hipLaunchKernelGGL(gram_reduce_kernel<T>, dim3((unsigned)((total + 63) / 64)), dim3(256), 0, st, h.partials, nb,
-                       a, h.out);
+    const i64 total = (i64)h.ntiles * 256;
+    hipLaunchKernelGGL(gramx_reduce_kernel, dim3((unsigned)((total + 63) / 64)), dim3(256), 0, st, h.partials, nb,
+                       h.ntiles, h.out);
     return hipGetLastError();
 }
 
-hipError_t launch_gram(int dtype, const GramArgs &a, hipStream_t st)
+hipError_t launch_gramx(int dtype, const GramXArgs &a, hipStream_t st)
 {
-    if (dtype == DT_F32) return run_gram<float>(a, st);
-    return run_gram<double>(a, st);
+    if (a.N < 1 || a.KL < 1 || a.KR < 1 || a.KL > GX_MAX_L || a.KR > GX_MAX_R || a.ntiles < 1 ||
+        a.ntiles > GX_MAX_TILES)
+        return hipErrorInvalidValue;
+    for (int t = 0; t < a.ntiles; t++) {
+        if (a.ta[t] < 0 || 16 * a.ta[t] >= a.KL || a.tb[t] < 0 || 16 * a.tb[t] >= a.KR) return hipErrorInvalidValue;
+        if (t > 0 && a.ta[t] < a.ta[t - 1]) return hipErrorInvalidValue;   // sorted by Lm block
+    }
+    if (dtype == DT_F32) return run_gramx<float>(a, st);
+    return run_gramx<double>(a, st);
+}
+
+hipError_t launch_gram_rows(int dtype, const void *S, int w, long long N, double *partials, double *out, int ldout,
+                            hipStream_t st)
+{
+    if (w < 1 || w > 8 || N < 1) return hipErrorInvalidValue;
+    if (dtype == DT_F32) return run_gram_rows<float>((const float *)S, w, N, partials, out, ldout, st);
+    return run_gram_rows<double>((const double *)S, w, N, partials, out, ldout, st);
 }
 
 }  // namespace lobpcg

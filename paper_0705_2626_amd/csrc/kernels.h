@@ -106,23 +106,33 @@ hipError_t launch_eig_grad(const Grid3 &g, int m, const double *X, const double 
                            double *gkz, hipStream_t st);
 
 // ---- Gram products (k_gram.hip)
-// Tiles of S^T S (mat 0) and S^T AS (mat 1), S = [S_0 .. S_{nblk-1}] with
-// K = sum w <= 96 columns; tile codes (mat << 16) | (a << 8) | b cover rows
-// 16a..16a+15 and columns 16b..16b+15.
-static const int GRAM_MAX_TILES = 48;
-struct GramArgs {
-    const void *S[3], *AS[3];   // AS[0] == nullptr: S^T S only
-    int w[3];
-    int nblk;
+// Entries of Lm^T Rm for N x KL and N x KR matrices whose columns are
+// columns of up to GX_MAX_ARR point-major arrays: column i of Lm is column
+// lmap[i] & 255 of array lmap[i] >> 8 (likewise Rm).  The listed 16 x 16 tiles
+// (rows 16 ta..16 ta+15 of Lm^T Rm, columns 16 tb..16 tb+15; sorted by ta)
+// are written to out[t][e], e = r*64 + lane of the MFMA accumulator layout
+// (row 16 ta + Mfma<T>::row(lane, r), column 16 tb + lane % 16).
+static const int GX_MAX_ARR = 6;
+static const int GX_MAX_L = 96;
+static const int GX_MAX_R = 192;
+static const int GX_MAX_TILES = 64;
+static const int GX_MAXB = 4;        // tiles per wave (sharing one Lm block)
+struct GramXArgs {
+    const void *arr[GX_MAX_ARR];
+    int ld[GX_MAX_ARR];
+    int KL, KR;
+    unsigned short lmap[GX_MAX_L], rmap[GX_MAX_R];
     int ntiles;
-    int tiles[GRAM_MAX_TILES];
+    int ta[GX_MAX_TILES], tb[GX_MAX_TILES];
     long long N;
-    double *partials;   // scratch, gram_partials_bytes
-    double *out;        // device [2][Kp][Kp], Kp = K rounded up to 16
-    int staged;         // 1: the LDS-staged kernel also for narrow single blocks
+    double *partials;   // scratch, gram_partials_bytes(N)
+    double *out;        // device [ntiles][256]
+    int max_nt;         // most tiles per wave (1, 2 or GX_MAXB)
 };
-int gram_kpad(int K);
-size_t gram_partials_bytes(int dtype, long long N, int K);
-hipError_t launch_gram(int dtype, const GramArgs &a, hipStream_t st);
+size_t gram_partials_bytes(long long N);
+hipError_t launch_gramx(int dtype, const GramXArgs &a, hipStream_t st);
+// S^T S (w x w, w <= 8) of one block, one grid row per thread: out[i*ldout + j], i <= j
+hipError_t launch_gram_rows(int dtype, const void *S, int w, long long N, double *partials, double *out, int ldout,
+                            hipStream_t st);
 
 }  // namespace lobpcg

@@ -106,13 +106,13 @@ Layout make_layout(const lobpcg_op *A, const lobpcg_precond *T, int m, int preci
             for (int j = 0; j < 3; j++) L.mg.push_back(take((size_t)L.levels.back().n() * m * esize(L.mg_dtype)));
         }
     }
-    const int K = 3 * m, Kp = gram_kpad(K);
+    const int K = 3 * m;
     L.lambda = take(sizeof(double) * m);
     L.jpos = take(sizeof(int) * m);
     L.cols = take(sizeof(int) * COEF_SLOTS * m);
     L.coef = take((size_t)COEF_SLOTS * K * m * 8);
-    L.gram_out = take((size_t)2 * Kp * Kp * 8);
-    L.gram_part = take(gram_partials_bytes(DT_F64, N, K));
+    L.gram_out = take((size_t)GX_MAX_TILES * 256 * 8);
+    L.gram_part = take(gram_partials_bytes(N));
     L.res_part = take((size_t)residual_blocks(N, m) * 2 * m * 8);
     L.mv_part = take((size_t)mv_blocks(N) * 2 * m * 8);
     L.res_out = take((size_t)2 * m * 8);
@@ -154,7 +154,7 @@ struct lobpcg_ctx {
     int stall_window;
     double stall_factor;
     bool profile, reactivate;
-    int mv_variant, gram_staged;  // kernel variants (see LOBPCG_OPT_KERNELS)
+    int mv_variant, gram_staged, gram_nt4;  // kernel variants (see LOBPCG_OPT_KERNELS)
     bool fp32_explicit;           // FP32 phase: Gram diagonal blocks computed, not assumed
     lobpcg_stats stats;
     // profiling: pending (step, start, end) event pairs
@@ -195,6 +195,9 @@ void prof_end(lobpcg_ctx *c)
     (void)hipEventRecord(c->ev_pool[c->ev_used], c->st);
     c->ev_used += 1;
 }
+// algorithmic HBM bytes of a step's kernels (operands read once, results written once)
+void add_bytes(lobpcg_ctx *c, int step, double bytes) { c->stats.step_bytes[step] += bytes; }
+
 // called right after a stream synchronisation
 void prof_collect(lobpcg_ctx *c)
 {
@@ -267,73 +270,128 @@ int apply_A(lobpcg_ctx *c, const lobpcg_op *A, int dt, const void *in, void *out
     else
         e = launch_laplace7(dt, c->g, k, in, out, 1.0, c->st);
     prof_end(c);
+    add_bytes(c, LOBPCG_STEP_APPLY_A, 2.0 * c->N * k * esize(dt) +
+                                          (A->kind == LOBPCG_OP_VARCOEF7 ? 8.0 * (3.0 * c->N + c->g.nx * c->g.ny +
+                                                                                  c->g.ny * c->g.nz + c->g.nz * c->g.nx)
+                                                                         : 0.0));
     return e == hipSuccess ? LOBPCG_OK : LOBPCG_ERR_HIP;
 }
 
-// Tiles to compute for S = [S_0 .. S_{n-1}] (widths w): every upper tile,
-// or with `paper` only those that meet an entry the paper's form does not
-// take as known: gramA outside the X-X block, gramB off the block diagonal.
-std::vector<int> gram_tiles(int n, const int *w, bool has_as, bool paper)
-{
-    int K = 0;
-    std::vector<int> blk;
-    for (int b = 0; b < n; b++)
-        for (int i = 0; i < w[b]; i++) blk.push_back(b), K++;
-    const int TK = gram_kpad(K) / 16;
-    std::vector<int> t;
-    for (int mat = 0; mat < (has_as ? 2 : 1); mat++)
-        for (int a = 0; a < TK; a++)
-            for (int b = a; b < TK; b++) {
-                bool need = !paper;
-                for (int i = 16 * a; i < std::min(K, 16 * a + 16) && !need; i++)
-                    for (int j = std::max(i, 16 * b); j < std::min(K, 16 * b + 16) && !need; j++)
-                        need = mat ? !(blk[i] == 0 && blk[j] == 0) : blk[i] < blk[j];
-                if (need) t.push_back((mat << 16) | (a << 8) | b);
-            }
-    return t;
-}
-
-// Gram products; returns K x K host matrices (row-major), upper triangle
-// mirrored (entries of tiles not computed are zero).  SAS may be null when AS
-// is not given.
+// Gram products of S = [S_0 .. S_{n-1}] (widths w, K columns in all) and,
+// when AS is given, AS = [AS_0 .. AS_{n-1}]; returns K x K host matrices
+// (row-major, symmetric).  They are entries of Lm^T Rm with Lm = S and
+//  - no AS: Rm = S (S^T S, the Cholesky Gram matrices of steps 3, 11, 14);
+//  - AS, explicit form: Rm = [S AS], all of S^T S and S^T AS;
+//  - AS, the paper's form (steps 17-23): Rm = [S_1.. AS_1..] (W, P, AW, AP)
+//    and only the entries the paper does not take as known: gramB off the
+//    block diagonal, gramA outside the X-X block (the caller fills Lambda
+//    and the identities; other entries are zero).
+// Entries (i, j) with i <= j are computed and mirrored.
 int gram(lobpcg_ctx *c, int dt, int n, const void *const *S, const void *const *AS, const int *w,
          std::vector<double> &SS, std::vector<double> *SAS, int step, bool paper = false)
 {
-    GramArgs a;
     int K = 0;
-    for (int i = 0; i < 3; i++) {
-        a.S[i] = i < n ? S[i] : nullptr;
-        a.AS[i] = (i < n && AS) ? AS[i] : nullptr;
-        a.w[i] = i < n ? w[i] : 0;
-        if (i < n) K += w[i];
+    std::vector<int> blk, col, off(n + 1, 0);
+    for (int b = 0; b < n; b++) {
+        for (int i = 0; i < w[b]; i++) blk.push_back(b), col.push_back(i);
+        K += w[b];
+        off[b + 1] = K;
     }
-    std::vector<int> tl = gram_tiles(n, w, AS != nullptr, paper);
-    if (tl.empty() || (int)tl.size() > GRAM_MAX_TILES) return LOBPCG_ERR_ARG;
-    a.ntiles = (int)tl.size();
-    std::copy(tl.begin(), tl.end(), a.tiles);
-    a.nblk = n;
+    double *h = (double *)(c->h_pin + c->h_gram_off);
+    if (!AS && n == 1 && w[0] <= 8 && !c->gram_staged) {
+        // one narrow block: one grid row per thread
+        prof_begin(c, step);
+        hipError_t e = launch_gram_rows(dt, S[0], w[0], c->N, c->d_gram_part, c->d_gram_out, w[0], c->st);
+        prof_end(c);
+        if (e != hipSuccess) return LOBPCG_ERR_HIP;
+        add_bytes(c, step, (double)w[0] * c->N * esize(dt));
+        HIPCHK(hipMemcpyAsync(h, c->d_gram_out, (size_t)K * K * 8, hipMemcpyDeviceToHost, c->st));
+        int s = sync(c);
+        if (s) return s;
+        SS.assign((size_t)K * K, 0.0);
+        for (int i = 0; i < K; i++)
+            for (int j = i; j < K; j++) SS[(size_t)i * K + j] = SS[(size_t)j * K + i] = h[(size_t)i * K + j];
+        return LOBPCG_OK;
+    }
+    const bool pform = AS && paper && n > 1;
+    GramXArgs a;
+    for (int b = 0; b < GX_MAX_ARR; b++) a.arr[b] = nullptr, a.ld[b] = 1;
+    for (int b = 0; b < n; b++) {
+        a.arr[b] = S[b], a.ld[b] = w[b];
+        if (AS) a.arr[3 + b] = AS[b], a.ld[3 + b] = w[b];
+    }
+    // Lm = S; Rm as above.  rs[j] / ra[j]: column of Rm holding S_j / AS_j (-1: none)
+    a.KL = K;
+    for (int i = 0; i < K; i++) a.lmap[i] = (unsigned short)((blk[i] << 8) | col[i]);
+    std::vector<int> rs(K, -1), ra(K, -1);
+    int KR = 0;
+    auto addr = [&](int arr, int i, std::vector<int> &pos) {
+        pos[i] = KR;
+        a.rmap[KR++] = (unsigned short)((arr << 8) | col[i]);
+    };
+    if (pform) {
+        for (int i = w[0]; i < K; i++) addr(blk[i], i, rs);
+        for (int i = w[0]; i < K; i++) addr(3 + blk[i], i, ra);
+    } else {
+        for (int i = 0; i < K; i++) addr(blk[i], i, rs);
+        if (AS)
+            for (int i = 0; i < K; i++) addr(3 + blk[i], i, ra);
+    }
+    a.KR = KR;
+    if (K > GX_MAX_L || KR > GX_MAX_R) return LOBPCG_ERR_ARG;
+    // the entries wanted, as (row of Lm, column of Rm) pairs, and their tiles
+    struct Want { int i, j, mat, r; };
+    std::vector<Want> want;
+    for (int i = 0; i < K; i++)
+        for (int j = i; j < K; j++) {
+            if (!pform || blk[i] < blk[j]) want.push_back({i, j, 0, rs[j]});
+            if (AS && (!pform || !(blk[i] == 0 && blk[j] == 0))) want.push_back({i, j, 1, ra[j]});
+        }
+    std::vector<int> tiles;   // (ta << 8) | tb, sorted
+    for (const Want &q : want) tiles.push_back(((q.i / 16) << 8) | (q.r / 16));
+    std::sort(tiles.begin(), tiles.end());
+    tiles.erase(std::unique(tiles.begin(), tiles.end()), tiles.end());
+    if (tiles.empty() || (int)tiles.size() > GX_MAX_TILES) return LOBPCG_ERR_ARG;
+    a.ntiles = (int)tiles.size();
+    for (int t = 0; t < a.ntiles; t++) a.ta[t] = tiles[t] >> 8, a.tb[t] = tiles[t] & 255;
     a.N = c->N;
     a.partials = c->d_gram_part;
     a.out = c->d_gram_out;
-    a.staged = c->gram_staged;
-    const int Kp = gram_kpad(K);
-    const size_t bytes = (size_t)(AS ? 2 : 1) * Kp * Kp * 8;
-    // tiles that are not computed read as zero
-    HIPCHK(hipMemsetAsync(c->d_gram_out, 0, bytes, c->st));
+    a.max_nt = c->gram_nt4 ? GX_MAXB : 2;
     prof_begin(c, step);
-    if (launch_gram(dt, a, c->st) != hipSuccess) return LOBPCG_ERR_HIP;
+    if (launch_gramx(dt, a, c->st) != hipSuccess) return LOBPCG_ERR_HIP;
     prof_end(c);
-    double *h = (double *)(c->h_pin + c->h_gram_off);
-    HIPCHK(hipMemcpyAsync(h, c->d_gram_out, bytes, hipMemcpyDeviceToHost, c->st));
+    {
+        // each array some tile reads, once
+        std::vector<char> used(GX_MAX_ARR, 0);
+        for (int t = 0; t < a.ntiles; t++) {
+            for (int i = 16 * a.ta[t]; i < std::min(K, 16 * a.ta[t] + 16); i++) used[a.lmap[i] >> 8] = 1;
+            for (int j = 16 * a.tb[t]; j < std::min(KR, 16 * a.tb[t] + 16); j++) used[a.rmap[j] >> 8] = 1;
+        }
+        double cols = 0.0;
+        for (int b = 0; b < GX_MAX_ARR; b++)
+            if (used[b]) cols += a.ld[b];
+        add_bytes(c, step, cols * c->N * esize(dt));
+    }
+    HIPCHK(hipMemcpyAsync(h, c->d_gram_out, (size_t)a.ntiles * 256 * 8, hipMemcpyDeviceToHost, c->st));
     int s = sync(c);
     if (s) return s;
-    auto unpack = [&](const double *src, std::vector<double> &dst) {
-        dst.assign((size_t)K * K, 0.0);
-        for (int i = 0; i < K; i++)
-            for (int j = i; j < K; j++) dst[(size_t)i * K + j] = dst[(size_t)j * K + i] = src[(size_t)i * Kp + j];
-    };
-    unpack(h, SS);
-    if (AS && SAS) unpack(h + (size_t)Kp * Kp, *SAS);
+    // tiles -> dense Lm^T Rm (entry e = r*64 + lane of the MFMA accumulator)
+    const int KLp = (K + 15) / 16 * 16, KRp = (KR + 15) / 16 * 16;
+    std::vector<double> M((size_t)KLp * KRp, 0.0);
+    for (int t = 0; t < a.ntiles; t++)
+        for (int e = 0; e < 256; e++) {
+            const int r = e / 64, lane = e % 64;
+            const int row = dt == DT_F32 ? 4 * (lane / 16) + r : lane / 16 + 4 * r;
+            M[(size_t)(16 * a.ta[t] + row) * KRp + 16 * a.tb[t] + lane % 16] = h[(size_t)t * 256 + e];
+        }
+    SS.assign((size_t)K * K, 0.0);
+    if (SAS) SAS->assign((size_t)K * K, 0.0);
+    for (const Want &q : want) {
+        std::vector<double> &D = q.mat ? *SAS : SS;
+        if (q.mat && !SAS) continue;
+        D[(size_t)q.i * K + q.j] = D[(size_t)q.j * K + q.i] = M[(size_t)q.i * KRp + q.r];
+    }
     return LOBPCG_OK;
 }
 
@@ -400,6 +458,13 @@ int mv(lobpcg_ctx *c, int dt, const MV &q, const double *C, int step)
     prof_begin(c, step);
     hipError_t e = launch_mv(dt, a, c->st);
     prof_end(c);
+    {
+        const int nout = q.opos ? q.nout : q.kout;
+        double cols = (double)K * q.nside + (q.add ? q.kout : 0);
+        cols += (double)q.nside * ((q.out[0] ? nout : 0) + (q.out2[0] ? q.kout : 0));
+        if (q.resid && q.Wout) cols += q.nW;
+        add_bytes(c, step, cols * c->N * esize(dt));
+    }
     return e == hipSuccess ? LOBPCG_OK : LOBPCG_ERR_HIP;
 }
 
@@ -438,6 +503,7 @@ int residual(lobpcg_ctx *c, int dt, const void *X, const void *AX, const std::ve
     prof_begin(c, LOBPCG_STEP_RESIDUAL);
     if (launch_residual(dt, a, c->st) != hipSuccess) return LOBPCG_ERR_HIP;
     prof_end(c);
+    add_bytes(c, LOBPCG_STEP_RESIDUAL, (2.0 * m + (W ? a.nJ : 0)) * c->N * esize(dt));
     double *h = (double *)(c->h_pin + c->h_res_off);
     HIPCHK(hipMemcpyAsync(h, c->d_res_out, 2 * m * 8, hipMemcpyDeviceToHost, c->st));
     int s = sync(c);
@@ -458,15 +524,21 @@ void *vcycle(lobpcg_ctx *c, int l, const void *b, void *xa, void *xb, int k, hip
     auto chk = [&](hipError_t e) {
         if (e != hipSuccess && err == hipSuccess) err = e;
     };
+    // algorithmic bytes: passes over level-l blocks of k columns
+    const double lvl = (double)g.n() * k * esize(dt);
+    auto passes = [&](double p) { add_bytes(c, LOBPCG_STEP_PRECOND, p * lvl); };
     if (l == Lv - 1) {
         if (coarse_solve_fits(dt, g)) {
             chk(launch_coarse_solve(dt, g, k, c->T.coarse_sweeps, s, om, b, xa, c->st));
+            passes(2.0);
             return xa;
         }
         chk(launch_scale(dt, g.n() * k, b, xa, om / (6.0 * s), c->st));
+        passes(2.0);
         void *cur = xa, *oth = xb;
         for (int i = 1; i < c->T.coarse_sweeps; i++) {
             chk(launch_jacobi(dt, g, k, cur, b, oth, s, om, c->st));
+            passes(3.0);
             std::swap(cur, oth);
         }
         return cur;
@@ -479,18 +551,24 @@ void *vcycle(lobpcg_ctx *c, int l, const void *b, void *xa, void *xb, int k, hip
     } else {
         chk(launch_scale(dt, g.n() * k, b, cur, c->T.nu_pre > 0 ? om / (6.0 * s) : 0.0, c->st));
     }
+    passes(2.0);
     for (int i = pre; i < c->T.nu_pre; i++) {
         chk(launch_jacobi(dt, g, k, cur, b, oth, s, om, c->st));
+        passes(3.0);
         std::swap(cur, oth);
     }
     chk(launch_resid7(dt, g, k, cur, b, oth, s, c->st));
     const Grid3 &gc = c->L.levels[l + 1];
+    const double ratio = (double)gc.n() / (double)g.n();
     void *bc = c->mgb[l + 1], *xc = c->mgx[l + 1], *tc = c->mgt[l + 1];
     chk(launch_restrict(dt, g, gc, k, oth, bc, c->st));
+    passes(3.0 + 1.0 + ratio);
     void *e = vcycle(c, l + 1, bc, xc, tc, k, err);
     chk(launch_prolong_add(dt, g, gc, k, e, cur, c->st));
+    passes(2.0 + ratio);
     for (int i = 0; i < c->T.nu_post; i++) {
         chk(launch_jacobi(dt, g, k, cur, b, oth, s, om, c->st));
+        passes(3.0);
         std::swap(cur, oth);
     }
     return cur;
@@ -513,6 +591,7 @@ int apply_T(lobpcg_ctx *c, int dt, const void *in, void *fa, void *fb, int k, vo
         if (launch_cast(dt, mdt, n, in, bin, c->st) != hipSuccess) err = hipErrorUnknown;
         void *r = vcycle(c, 0, bin, xa, xb, k, err);
         if (launch_cast(mdt, dt, n, r, fa, c->st) != hipSuccess) err = hipErrorUnknown;
+        add_bytes(c, LOBPCG_STEP_PRECOND, 2.0 * n * (esize(dt) + esize(mdt)));
         *result = fa;
     }
     prof_end(c);
@@ -645,6 +724,7 @@ int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &
                 prof_begin(c, LOBPCG_STEP_RESIDUAL);
                 hipError_t e = launch_gather_cols(dt, c->N, B.W, (int)ps.J.size(), dmap, (int)Jn.size(), B.T0, c->st);
                 prof_end(c);
+                add_bytes(c, LOBPCG_STEP_RESIDUAL, 2.0 * Jn.size() * c->N * esize(dt));
                 if (e != hipSuccess) return LOBPCG_ERR_HIP;
                 std::swap(B.W, B.T0);
                 ps.J = Jn;
@@ -947,7 +1027,6 @@ int lobpcg_setup(lobpcg_ctx **out, const lobpcg_op *A, const lobpcg_op *B, const
     c->d_res_out = (double *)(c->ws + L.res_out);
     c->d_w = (double *)(c->ws + L.wvec);
     // pinned host staging
-    const int Kp = gram_kpad(3 * m);
     size_t off = 0;
     auto take = [&](size_t b) {
         size_t o = align_up(off);
@@ -956,7 +1035,7 @@ int lobpcg_setup(lobpcg_ctx **out, const lobpcg_op *A, const lobpcg_op *B, const
     };
     c->h_coef_off = take((size_t)COEF_SLOTS * 3 * m * m * 8);
     c->h_cols_off = take((size_t)COEF_SLOTS * m * sizeof(int));
-    c->h_gram_off = take((size_t)2 * Kp * Kp * 8);
+    c->h_gram_off = take((size_t)GX_MAX_TILES * 256 * 8);
     c->h_res_off = take((size_t)2 * m * 8);
     c->h_small_off = take((size_t)m * 8 + (size_t)m * sizeof(int));
     c->h_pin_bytes = align_up(off);
@@ -972,6 +1051,7 @@ int lobpcg_setup(lobpcg_ctx **out, const lobpcg_op *A, const lobpcg_op *B, const
     c->reactivate = true;
     c->mv_variant = 0;
     c->gram_staged = 0;
+    c->gram_nt4 = 0;
     c->fp32_explicit = true;
     memset(&c->stats, 0, sizeof(c->stats));
     c->ev_used = 0;
@@ -1015,9 +1095,10 @@ int lobpcg_set_option(lobpcg_ctx *c, int key, double v)
     case LOBPCG_OPT_REACTIVATE: c->reactivate = v != 0; return LOBPCG_OK;
     case LOBPCG_OPT_FP32_EXPLICIT_GRAM: c->fp32_explicit = v != 0; return LOBPCG_OK;
     case LOBPCG_OPT_KERNELS:
-        if (v < 0 || v > 7 || ((int)v & 3) == 3) return LOBPCG_ERR_ARG;
+        if (v < 0 || v > 15 || ((int)v & 3) == 3) return LOBPCG_ERR_ARG;
         c->mv_variant = (int)v & 3;
         c->gram_staged = ((int)v & 4) != 0;
+        c->gram_nt4 = ((int)v & 8) != 0;
         return LOBPCG_OK;
     default: return LOBPCG_ERR_ARG;
     }
@@ -1068,6 +1149,7 @@ int lobpcg_solve(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, const lo
         prof_begin(c, LOBPCG_STEP_OTHER);
         if (launch_cast(DT_F64, DT_F32, nm, d_X0, c->b32.X[0], c->st) != hipSuccess) return LOBPCG_ERR_HIP;
         prof_end(c);
+        add_bytes(c, LOBPCG_STEP_OTHER, 12.0 * nm);
         s = init_phase(c, A, DT_F32, c->b32, ps, true, true);
         if (s == LOBPCG_OK) {
             s = run_phase(c, A, DT_F32, c->b32, ps, std::max(tol, c->switch_tol), normA, maxit, iters, h_hist,
@@ -1083,6 +1165,7 @@ int lobpcg_solve(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, const lo
             if (np && launch_cast(DT_F32, DT_F64, (size_t)c->N * np, c->b32.P, c->b64.P, c->st) != hipSuccess)
                 return LOBPCG_ERR_HIP;
             prof_end(c);
+            add_bytes(c, LOBPCG_STEP_OTHER, 12.0 * (nm + (double)c->N * np));
             if (np) {
                 s = apply_A(c, A, DT_F64, c->b64.P, c->b64.AP, np);
                 if (s) return s;
@@ -1187,10 +1270,11 @@ int lobpcg_apply_T(lobpcg_ctx *c, int dt, const void *in, void *out, int k)
     return sync(c);
 }
 
-int lobpcg_gram(lobpcg_ctx *c, int dt, int n, const void *const *S, const void *const *AS, const int *w, double *h_SS,
-                double *h_SAS)
+int lobpcg_gram(lobpcg_ctx *c, int dt, int n, const void *const *S, const void *const *AS, const int *w,
+                int paper_form, double *h_SS, double *h_SAS)
 {
     if (!c || !dtype_ok(c, dt) || n < 1 || n > 3 || !S || !w || !h_SS) return LOBPCG_ERR_ARG;
+    if (paper_form != 0 && (paper_form != 1 || !AS || n < 2)) return LOBPCG_ERR_ARG;
     int K = 0;
     for (int i = 0; i < n; i++) {
         if (!S[i] || w[i] < 1 || (AS && !AS[i])) return LOBPCG_ERR_ARG;
@@ -1198,7 +1282,8 @@ int lobpcg_gram(lobpcg_ctx *c, int dt, int n, const void *const *S, const void *
     }
     if (K > 3 * c->m || (AS && !h_SAS)) return LOBPCG_ERR_ARG;
     std::vector<double> SS, SAS;
-    int s = gram(c, dt == LOBPCG_F32 ? DT_F32 : DT_F64, n, S, AS, w, SS, AS ? &SAS : nullptr, LOBPCG_STEP_GRAM);
+    int s = gram(c, dt == LOBPCG_F32 ? DT_F32 : DT_F64, n, S, AS, w, SS, AS ? &SAS : nullptr, LOBPCG_STEP_GRAM,
+                 paper_form == 1);
     if (s) return s;
     std::copy(SS.begin(), SS.end(), h_SS);
     if (AS) std::copy(SAS.begin(), SAS.end(), h_SAS);

@@ -48,7 +48,8 @@ NSTEP = 8
 class _Stats(ctypes.Structure):
     _fields_ = [("iters_total", ctypes.c_int), ("iters_fp32", ctypes.c_int), ("iters_fp64", ctypes.c_int),
                 ("restarts", ctypes.c_int), ("status", ctypes.c_int), ("solve_ms", ctypes.c_double),
-                ("step_ms", ctypes.c_double * NSTEP), ("step_calls", ctypes.c_int * NSTEP)]
+                ("step_ms", ctypes.c_double * NSTEP), ("step_calls", ctypes.c_int * NSTEP),
+                ("step_bytes", ctypes.c_double * NSTEP)]
 
 
 _lib = None
@@ -75,7 +76,7 @@ def lib():
             "lobpcg_get_stats": (i, [p, P(_Stats)]),
             "lobpcg_apply_A": (i, [p, P(_Op), i, p, p, i]),
             "lobpcg_apply_T": (i, [p, i, p, p, i]),
-            "lobpcg_gram": (i, [p, i, i, p, p, p, p, p]),
+            "lobpcg_gram": (i, [p, i, i, p, p, p, i, p, p]),
             "lobpcg_combine": (i, [p, i, i, p, p, p, p, p, i, p, p]),
             "lobpcg_residual": (i, [p, i, p, p, i, p, p, i, d, p, p]),
             "lobpcg_dense_chol": (i, [i, p, p]),
@@ -194,7 +195,8 @@ def lobpcg_get_stats(ctx):
     return {"iters_total": s.iters_total, "iters_fp32": s.iters_fp32, "iters_fp64": s.iters_fp64,
             "restarts": s.restarts, "status": s.status, "solve_ms": s.solve_ms,
             "step_ms": dict(zip(STEP_NAMES, list(s.step_ms))),
-            "step_calls": dict(zip(STEP_NAMES, list(s.step_calls)))}
+            "step_calls": dict(zip(STEP_NAMES, list(s.step_calls))),
+            "step_bytes": dict(zip(STEP_NAMES, list(s.step_bytes)))}
 
 
 class SolveResult:
@@ -277,8 +279,9 @@ def lobpcg_apply_T(ctx, X):
     return out
 
 
-def lobpcg_gram(ctx, S, AS=None):
-    """(S^T S, S^T AS) for lists of (N, w_i) blocks, as float64 numpy arrays."""
+def lobpcg_gram(ctx, S, AS=None, paper_form=False):
+    """(S^T S, S^T AS) for lists of (N, w_i) blocks, as float64 numpy arrays
+    (paper_form: only the entries the paper's form of steps 17-23 computes)."""
     S = [_blk(ctx, s, "S", dtype=S[0].dtype) for s in S]
     n = len(S)
     dt = _dt(S[0])
@@ -292,8 +295,8 @@ def lobpcg_gram(ctx, S, AS=None):
         AS = [_blk(ctx, a, "AS", s.shape[1], S[0].dtype) for a, s in zip(AS, S)]
         ap = (ctypes.c_void_p * 3)(*[a.data_ptr() for a in AS])
         SAS = np.zeros((K, K))
-    _check(lib().lobpcg_gram(ctx.h, dt, n, sp, ap, w, _np_ptr(SS), _np_ptr(SAS) if SAS is not None else None),
-           "lobpcg_gram")
+    _check(lib().lobpcg_gram(ctx.h, dt, n, sp, ap, w, int(bool(paper_form)), _np_ptr(SS),
+                             _np_ptr(SAS) if SAS is not None else None), "lobpcg_gram")
     return SS, SAS
 
 

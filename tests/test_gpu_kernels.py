@@ -141,8 +141,8 @@ def test_vcycle_large_coarsest_grid_uses_global_sweeps():
 # ---------------------------------------------------------------- Gram products (steps 17-23, 3, 11, 14)
 
 # variant 0: the kernel chosen by shape (one row per thread for a single block
-# of at most 8 columns), 4: always the LDS-staged MFMA kernel
-@pytest.mark.parametrize("variant", [0, 4])
+# of at most 8 columns), 4: always the MFMA kernel, 8: up to four tiles per wave
+@pytest.mark.parametrize("variant", [0, 4, 8])
 @pytest.mark.parametrize("N,widths", [(4096, (8, 3, 3)), (33 * 17 * 9, (32, 32, 32)), (1000, (4,)),
                                       (70001, (16, 16)), (5003, (5, 7, 2)), (200000, (32, 17, 17)),
                                       (300007, (1,)), (12345, (32, 1, 1))])
@@ -161,7 +161,7 @@ def test_gram_fp64(N, widths, variant):
     np.testing.assert_allclose(SS, SS.T)      # lower triangle mirrored
 
 
-@pytest.mark.parametrize("variant", [0, 4])
+@pytest.mark.parametrize("variant", [0, 4, 8])
 @pytest.mark.parametrize("N,widths", [(4096, (8, 3, 3)), (70001, (32, 32, 32)), (5003, (5, 7, 2)),
                                       (99999, (32, 1, 1)), (77777, (2,))])
 def test_gram_fp32(N, widths, variant):
@@ -177,6 +177,34 @@ def test_gram_fp32(N, widths, variant):
     assert np.all(np.abs(SAS - Sf.T @ ASf)[iu] <= bound[iu] + 1e-30)
     boundB = 64 * EPS32 * (np.abs(Sf).T @ np.abs(Sf))
     assert np.all(np.abs(SS - Sf.T @ Sf)[iu] <= boundB[iu] + 1e-30)
+
+
+@pytest.mark.parametrize("prec", [L.FP64, L.MIXED])
+@pytest.mark.parametrize("N,widths", [(4096, (8, 3, 3)), (70001, (32, 32, 32)), (5003, (5, 7, 2)),
+                                      (99999, (32, 1, 1)), (20000, (16, 5)), (3001, (7, 1))])
+def test_gram_paper_form(N, widths, prec):
+    """Steps 17-23 in the paper's form: S^T S off the block diagonal and S^T AS
+    outside the S_0-S_0 block are computed, every other entry is zero."""
+    ctx = ctx_for((N, 1, 1), 32, None, L.MIXED)
+    npdt, tdt = (np.float64, torch.float64) if prec == L.FP64 else (np.float32, torch.float32)
+    S = [synth.random_block(N, w, seed=120 + i).astype(npdt) for i, w in enumerate(widths)]
+    AS = [synth.random_block(N, w, seed=140 + i).astype(npdt) for i, w in enumerate(widths)]
+    SS, SAS = L.lobpcg_gram(ctx, [dev(s, tdt) for s in S], [dev(a, tdt) for a in AS], paper_form=True)
+    Sf, ASf = np.hstack(S).astype(np.float64), np.hstack(AS).astype(np.float64)
+    blk = np.concatenate([np.full(w, b) for b, w in enumerate(widths)])
+    wantB = blk[:, None] != blk[None, :]
+    wantA = ~((blk[:, None] == 0) & (blk[None, :] == 0))
+    if prec == L.FP64:
+        tolB = tolA = 1e-13 * N
+    else:
+        tolB = 64 * EPS32 * (np.abs(Sf).T @ np.abs(Sf)).max()
+        tolA = 64 * EPS32 * (np.abs(Sf).T @ np.abs(ASf)).max()
+    np.testing.assert_allclose(SS[wantB], (Sf.T @ Sf)[wantB], rtol=0, atol=tolB)
+    np.testing.assert_array_equal(SS[~wantB], 0.0)
+    iu = np.triu(np.ones_like(wantA), 0) & wantA
+    np.testing.assert_allclose(SAS[iu], (Sf.T @ ASf)[iu], rtol=0, atol=tolA)
+    np.testing.assert_array_equal(SAS[~wantA], 0.0)
+    np.testing.assert_array_equal(SAS, SAS.T)
 
 
 def test_gram_single_block_without_AS():

@@ -190,7 +190,7 @@ def test_error_paths():
         L.lobpcg_solve(ctx, dev(synth.x0_uniform(N, m)), -1.0, 10)
 
 
-@pytest.mark.parametrize("variant", [1, 2, 4])
+@pytest.mark.parametrize("variant", [1, 2, 4, 8])
 @pytest.mark.parametrize("m", [6, 12])
 def test_kernel_variants_give_the_same_solution(variant, m):
     """The default multivector / Gram kernels and the other variants agree."""
