@@ -52,6 +52,9 @@ def main():
     ap.add_argument("--spmm-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy a 1 GiB buffer three times (a plain copy kernel of known size, the "
+                         "reference for scaling hardware byte counters)")
     ap.add_argument("--no-profile-steps", action="store_true",
                     help="skip the extra solve with per-step HIP-event timing (then the roofline is the stencil's)")
     args = ap.parse_args()
@@ -67,6 +70,13 @@ def main():
 
     torch.cuda.init()
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     n, m, levels, tol = args.n, args.m, args.levels, args.tol
     dims = (n, n, n)
     N = n ** 3

@@ -1,0 +1,124 @@
+"""Parity at the full sizes of the benchmark configurations, in the launch
+configuration the benchmark uses.
+
+The oracle cannot run these sizes in seconds, so they are checked through
+what holds at any size: the closed-form spectrum of the Dirichlet 7-point
+Laplacian (Section 4.1), the explicit FP64 residual of every pair, the
+orthonormality of X, and for the eigenvalue adjoint the Euler identity and a
+central finite difference of warm-started solves along a seeded direction.
+"""
+import gc
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import closed_form
+
+L = pytest.importorskip("paper_0705_2626_amd")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def release():
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+def check_orthonormal(X, atol):
+    G = (X.T @ X).cpu().numpy()
+    np.testing.assert_allclose(G, np.eye(G.shape[0]), rtol=0, atol=atol)
+
+
+def test_n128_m16_fp64_multigrid():
+    """FP64, n=128 (N=2,097,152), m=16, V(2,2) with 5 levels, tol 1e-8.  The
+    block edge cuts the 6-fold group lambda_12..17: eigenvalues still agree
+    with the closed form; the cut group's vectors are checked by residual."""
+    n, m, tol = 128, 16, 1e-8
+    N = n ** 3
+    ctx = L.lobpcg_setup(L.Op(n, n, n), L.Precond(5), m, L.FP64)
+    r = L.lobpcg_solve(ctx, dev(synth.x0_uniform(N, m, seed=2)), tol, 300)
+    exact, _ = closed_form.smallest(n, n, n, m)
+    assert r.status == L.OK
+    assert r.resid.max() <= tol
+    # |lambda - theta| <= ||r||^2 / gap, ||r|| = tol * ||A|| = 1.2e-7, gap >= 4e-4
+    np.testing.assert_allclose(r.lam, exact, rtol=1e-8)
+    check_orthonormal(r.X, 1e-10)
+    del ctx, r
+    release()
+
+
+def test_n464_m8_mixed_multigrid():
+    """Mixed precision, n=464 (N=99,897,344), m=8, 7 levels, tol 1e-8 after the
+    FP64 finish: eigenvalues to 1e-6 of the closed form (the block edge cuts
+    the 3-fold group lambda_8..10), every explicit FP64 residual <= tol."""
+    n, m, tol = 464, 8, 1e-8
+    N = n ** 3
+    ctx = L.lobpcg_setup(L.Op(n, n, n), L.Precond(7), m, L.MIXED)
+    X0 = dev(synth.x0_uniform(N, m, seed=2))
+    r = L.lobpcg_solve(ctx, X0, tol, 300, hist=False)
+    st = L.lobpcg_get_stats(ctx)
+    exact, _ = closed_form.smallest(n, n, n, m)
+    assert r.status == L.OK
+    assert st["iters_fp32"] > 0 and st["iters_fp64"] > 0
+    assert r.resid.max() <= tol
+    np.testing.assert_allclose(r.lam, exact, rtol=1e-6)
+    check_orthonormal(r.X, 1e-9)
+    del ctx, r, X0
+    release()
+
+
+def test_n96_m8_adjoint_full_size():
+    """-div(k grad u) with lognormal k (sigma 0.5, correlation 8 cells), n=96
+    (N=884,736), m=8, FP64: the Euler identity sum_f k_f dlambda_i/dk_f =
+    lambda_i for every i, and the gradient against a central difference of
+    two warm-started solves along a seeded direction of all 3 n^2 (n+1)
+    faces (relative step 1e-6).  The difference is taken of the sum of the m
+    eigenvalues: it is smooth where single eigenvalues come close, and its
+    error at residual rho is bounded by the gap to lambda_{m+1}, not by the
+    gaps inside the block.  Each eigenvalue enters as the Rayleigh quotient
+    x^T (A x) / x^T x of the returned vector with an explicit A x: its error is
+    quadratic in the vector's error, far below the 1e-10 change that the step
+    makes, which the Ritz values carried through the AX recurrence (absolute
+    error of order eps ||A||) would not resolve."""
+    n, m = 96, 8
+    N = n ** 3
+    kx, ky, kz = synth.gaussian_field_faces(n, n, n, sigma=0.5, corr=8.0, seed=2)
+    K = [dev(a) for a in (kx, ky, kz)]
+    ctx = L.lobpcg_setup(L.Op(n, n, n, *K), L.Precond(5), m, L.FP64)
+    r = L.lobpcg_solve(ctx, dev(synth.x0_uniform(N, m, seed=2)), 1e-12, 500, hist=False)
+    assert r.status == L.OK
+    lam = r.lam
+    assert np.all(np.diff(lam) > 1e-8 * lam[-1])   # simple eigenvalues: gradients defined
+    for i in range(m):
+        e = np.zeros(m)
+        e[i] = 1.0
+        g = L.lobpcg_eig_grad_k(ctx, r.X, e)
+        s = sum(float((k * gi).sum()) for k, gi in zip(K, g))
+        assert s == pytest.approx(lam[i], rel=1e-10)
+    w = np.ones(m)
+    g = L.lobpcg_eig_grad_k(ctx, r.X, w)
+    rng = np.random.default_rng(4)
+    V = [dev(rng.uniform(-1, 1, a.shape)) * k for a, k in zip((kx, ky, kz), K)]   # relative direction
+    dirderiv = sum(float((gi * v).sum()) for gi, v in zip(g, V))
+    h = 1e-6
+    vals = []
+    for sgn in (1.0, -1.0):
+        Kp = [k + sgn * h * v for k, v in zip(K, V)]
+        Ap = L.Op(n, n, n, *Kp)
+        rp = L.lobpcg_solve(ctx, r.X, 1e-12, 500, A=Ap, hist=False)
+        assert rp.status == L.OK
+        AX = L.lobpcg_apply_A(ctx, rp.X, A=Ap)
+        rq = ((rp.X * AX).sum(0) / (rp.X * rp.X).sum(0)).cpu().numpy()
+        np.testing.assert_allclose(rq, rp.lam, rtol=1e-10)
+        vals.append(float(np.dot(rq, w)))
+    fd = (vals[0] - vals[1]) / (2 * h)
+    assert fd == pytest.approx(dirderiv, rel=1e-5), np.diff(lam) / lam[-1]
+    del ctx, r, K, g
+    release()
