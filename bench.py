@@ -38,6 +38,25 @@ sys.path.insert(0, ROOT)
 METRIC = "time-to-residual 1e-8, 256^3 Laplacian m=32, FP64 vs mixed; SpMM HBM GB/s"
 HBM_PEAK_GBPS = 8000.0
 
+# Measured HBM bytes per launch of a step's kernels in the mixed solve, from
+# two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy;
+# valid only while the kernel source is the one the counters were taken with.
+TRAFFIC = {
+    "update": {"bytes_per_launch": 17.050e9, "source": "paper_0705_2626_amd/csrc/k_update.hip",
+               "sha1": "48679fd94b862d215155e6a9d91e56cca76b5b13", "profile": "profiles/lobpcg_mixed_n256_m32_hbm_traffic.md"},
+}
+
+
+def measured_traffic(step):
+    t = TRAFFIC.get(step)
+    if not t:
+        return None
+    import hashlib
+    with open(os.path.join(ROOT, t["source"]), "rb") as f:
+        if hashlib.sha1(f.read()).hexdigest() != t["sha1"]:
+            return None
+    return t["bytes_per_launch"]
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -182,9 +201,11 @@ def main():
                 "apply_A": "stencil7 A*W (step 12)", "residual": "residual_kernel (step 7)"}
         name = max(kern, key=lambda k: steps_mixed[k]["ms"])
         d = steps_mixed[name]
+        tr = measured_traffic(name)
         out["roofline"] = {"bound": "hbm", "achieved": d["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                           "frac": d["GBps"] / HBM_PEAK_GBPS, "traffic": None, "step": name, "kernel": kern[name],
-                           "ms": d["ms"], "calls": d["calls"], "algorithmic_GB": d["GB"]}
+                           "frac": d["GBps"] / HBM_PEAK_GBPS, "traffic": tr, "step": name, "kernel": kern[name],
+                           "ms": d["ms"], "calls": d["calls"], "algorithmic_GB": d["GB"],
+                           "algorithmic_bytes_per_launch": d["GB"] * 1e9 / max(d["calls"], 1)}
     else:
         out["roofline"] = {"bound": "hbm", "achieved": spmm_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                            "frac": spmm_gbps / HBM_PEAK_GBPS, "traffic": None, "kernel": "stencil7 f32 N x 32"}
