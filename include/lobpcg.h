@@ -139,9 +139,14 @@ enum {
                                     /* multi-column-tile Gram kernel also for narrow   */
                                     /* single-block Grams; bit 3: up to four Gram      */
                                     /* tiles per wave (default two)                    */
-    LOBPCG_OPT_FP32_EXPLICIT_GRAM = 6 /* MIXED: 1 (default) FP32 iterations compute    */
+    LOBPCG_OPT_FP32_EXPLICIT_GRAM = 6,/* MIXED: 1 (default) FP32 iterations compute   */
                                     /* X^T X, X^T AX, W^T W, P^T P rather than taking  */
                                     /* I and Lambda for them as the paper's form does  */
+    LOBPCG_OPT_FOLD_CHOLQR = 7      /* 1 (default): the Cholesky-QR factors of steps   */
+                                    /* 11 and 14-15 are folded into the Gram matrices  */
+                                    /* and the update coefficients (W_J R^-1 and       */
+                                    /* P_J R^-1 are never formed; same algebra, fewer  */
+                                    /* passes); 0: applied to the blocks               */
 };
 int lobpcg_set_option(lobpcg_ctx *ctx, int key, double value);
 

@@ -457,11 +457,10 @@ __global__ void __launch_bounds__(256) mvf_kernel(MVDev<T> a)
 #pragma unroll
     for (int nt = 0; nt < NT; nt++) sr[nt] = sx[nt] = 0.0;
 
-    // one input into a fixed accumulator array
-    auto input = [&](accT(&tgt)[NT], int s, int b, i64 prow, bool pok) {
-        T av[KQ];
-        frag_load<T>(av, a.in[s][b] + prow * a.ld[b], a.ld[b], a.k[b], k4[b], sh.cmap + roffs[b],
-                     a.cols[b] != nullptr, pok, kq);
+    // the MFMAs of one input whose fragments are loaded, into a fixed
+    // accumulator array (a runtime choice of array would force the
+    // accumulators out of registers)
+    auto mma_in = [&](accT(&tgt)[NT], const T(&av)[KQ], int b) {
         const T *cf = sh.Cf + soff[b] * NT * 64 + lane;
 #pragma unroll
         for (int i = 0; i < KQ; i++) {
@@ -470,26 +469,85 @@ __global__ void __launch_bounds__(256) mvf_kernel(MVDev<T> a)
             for (int nt = 0; nt < NT; nt++) tgt[nt] = Mfma<T>::mma(av[i], cf[(i * NT + nt) * 64], tgt[nt]);
         }
     };
-
-    const i64 ngroups = (a.N + 15) / 16;
-    for (i64 g = (i64)blockIdx.x * 4 + wave; g < ngroups; g += (i64)gridDim.x * 4) {
-        const i64 p0w = g * 16, prow = p0w + (lane & 15);
-        const bool pok = prow < a.N;
-        accT keepX[NT];
-        for (int s = 0; s < a.nside; s++) {
-            accT acc[NT], acc2[NT];
+    auto load_in = [&](T(&av)[KQ], int s, int b, i64 prow, bool pok) {
+        frag_load<T>(av, a.in[s][b] + prow * a.ld[b], a.ld[b], a.k[b], k4[b], sh.cmap + roffs[b],
+                     a.cols[b] != nullptr, pok, kq);
+    };
+    const i64 ngroups = (a.N + 15) / 16, gstride = (i64)gridDim.x * 4;
+    i64 g = (i64)blockIdx.x * 4 + wave;
+    if constexpr (sizeof(T) == 4) {
+        // FP32: input 0 (X, the widest block, or the only input) is loaded for
+        // both sides one group ahead, so that its loads are in flight while the
+        // current group is multiplied
+        auto load0 = [&](T(&dst)[2][KQ], i64 gg) {
+            const i64 prow = gg * 16 + (lane & 15);
 #pragma unroll
-            for (int nt = 0; nt < NT; nt++) acc[nt] = acc_zero<T>(), acc2[nt] = acc_zero<T>();
-            for (int b = has2 ? 1 : 0; b < a.nin; b++) input(acc, s, b, prow, pok);
-            if (has2) {
+            for (int s = 0; s < 2; s++)
+                if (s < a.nside) load_in(dst[s], s, 0, prow, prow < a.N);
+        };
+        T x0[2][KQ];
+        if (g < ngroups) load0(x0, g);
+        for (; g < ngroups; g += gstride) {
+            const i64 p0w = g * 16, prow = p0w + (lane & 15);
+            const bool pok = prow < a.N;
+            T xn[2][KQ];
+            if (g + gstride < ngroups) load0(xn, g + gstride);
+            accT keepX[NT];
 #pragma unroll
-                for (int nt = 0; nt < NT; nt++) acc2[nt] = acc[nt];
-                input(acc2, s, 0, prow, pok);
+            for (int s = 0; s < 2; s++) {
+                if (s >= a.nside) break;
+                accT acc[NT], acc2[NT];
+#pragma unroll
+                for (int nt = 0; nt < NT; nt++) acc[nt] = acc_zero<T>(), acc2[nt] = acc_zero<T>();
+                if (!has2) mma_in(acc, x0[s], 0);
+                for (int b = 1; b < a.nin; b++) {
+                    T av[KQ];
+                    load_in(av, s, b, prow, pok);
+                    mma_in(acc, av, b);
+                }
+                if (has2) {
+#pragma unroll
+                    for (int nt = 0; nt < NT; nt++) acc2[nt] = acc[nt];
+                    mma_in(acc2, x0[s], 0);
+                }
+                mv_outputs<T, NT>(a, sh, s, p0w, acc, acc2, keepX, sr, sx, lane);
+                if (s == 0) {
+#pragma unroll
+                    for (int nt = 0; nt < NT; nt++) keepX[nt] = acc2[nt];
+                }
             }
-            mv_outputs<T, NT>(a, sh, s, p0w, acc, acc2, keepX, sr, sx, lane);
-            if (s == 0) {
 #pragma unroll
-                for (int nt = 0; nt < NT; nt++) keepX[nt] = acc2[nt];
+            for (int s = 0; s < 2; s++)
+#pragma unroll
+                for (int i = 0; i < KQ; i++) x0[s][i] = xn[s][i];
+        }
+    } else {
+        // FP64: each input loaded right before its products (the registers of
+        // a second group would cost occupancy)
+        auto input = [&](accT(&tgt)[NT], int s, int b, i64 prow, bool pok) {
+            T av[KQ];
+            load_in(av, s, b, prow, pok);
+            mma_in(tgt, av, b);
+        };
+        for (; g < ngroups; g += gstride) {
+            const i64 p0w = g * 16, prow = p0w + (lane & 15);
+            const bool pok = prow < a.N;
+            accT keepX[NT];
+            for (int s = 0; s < a.nside; s++) {
+                accT acc[NT], acc2[NT];
+#pragma unroll
+                for (int nt = 0; nt < NT; nt++) acc[nt] = acc_zero<T>(), acc2[nt] = acc_zero<T>();
+                for (int b = has2 ? 1 : 0; b < a.nin; b++) input(acc, s, b, prow, pok);
+                if (has2) {
+#pragma unroll
+                    for (int nt = 0; nt < NT; nt++) acc2[nt] = acc[nt];
+                    input(acc2, s, 0, prow, pok);
+                }
+                mv_outputs<T, NT>(a, sh, s, p0w, acc, acc2, keepX, sr, sx, lane);
+                if (s == 0) {
+#pragma unroll
+                    for (int nt = 0; nt < NT; nt++) keepX[nt] = acc2[nt];
+                }
             }
         }
     }

@@ -156,6 +156,7 @@ struct lobpcg_ctx {
     bool profile, reactivate;
     int mv_variant, gram_staged, gram_nt4;  // kernel variants (see LOBPCG_OPT_KERNELS)
     bool fp32_explicit;           // FP32 phase: Gram diagonal blocks computed, not assumed
+    bool fold;                    // Cholesky-QR factors of W_J, P_J folded into Gram and coefficients
     lobpcg_stats stats;
     // profiling: pending (step, start, end) event pairs
     std::vector<hipEvent_t> ev_pool;
@@ -288,17 +289,21 @@ int apply_A(lobpcg_ctx *c, const lobpcg_op *A, int dt, const void *in, void *out
 //    and the identities; other entries are zero).
 // Entries (i, j) with i <= j are computed and mirrored.
 int gram(lobpcg_ctx *c, int dt, int n, const void *const *S, const void *const *AS, const int *w,
-         std::vector<double> &SS, std::vector<double> *SAS, int step, bool paper = false)
+         std::vector<double> &SS, std::vector<double> *SAS, int step, bool paper = false,
+         const int *const *cols = nullptr, const int *ld = nullptr, bool diag_blocks = false)
 {
     int K = 0;
     std::vector<int> blk, col, off(n + 1, 0);
+    bool plain = true;   // every block read whole
     for (int b = 0; b < n; b++) {
-        for (int i = 0; i < w[b]; i++) blk.push_back(b), col.push_back(i);
+        const bool sel = cols && cols[b];
+        for (int i = 0; i < w[b]; i++) blk.push_back(b), col.push_back(sel ? cols[b][i] : i);
         K += w[b];
         off[b + 1] = K;
+        plain = plain && !sel && (!ld || ld[b] == w[b]);
     }
     double *h = (double *)(c->h_pin + c->h_gram_off);
-    if (!AS && n == 1 && w[0] <= 8 && !c->gram_staged) {
+    if (!AS && n == 1 && w[0] <= 8 && plain && !c->gram_staged) {
         // one narrow block: one grid row per thread
         prof_begin(c, step);
         hipError_t e = launch_gram_rows(dt, S[0], w[0], c->N, c->d_gram_part, c->d_gram_out, w[0], c->st);
@@ -317,8 +322,9 @@ int gram(lobpcg_ctx *c, int dt, int n, const void *const *S, const void *const *
     GramXArgs a;
     for (int b = 0; b < GX_MAX_ARR; b++) a.arr[b] = nullptr, a.ld[b] = 1;
     for (int b = 0; b < n; b++) {
-        a.arr[b] = S[b], a.ld[b] = w[b];
-        if (AS) a.arr[3 + b] = AS[b], a.ld[3 + b] = w[b];
+        const int l = ld ? ld[b] : w[b];
+        a.arr[b] = S[b], a.ld[b] = l;
+        if (AS) a.arr[3 + b] = AS[b], a.ld[3 + b] = l;
     }
     // Lm = S; Rm as above.  rs[j] / ra[j]: column of Rm holding S_j / AS_j (-1: none)
     a.KL = K;
@@ -344,7 +350,8 @@ int gram(lobpcg_ctx *c, int dt, int n, const void *const *S, const void *const *
     std::vector<Want> want;
     for (int i = 0; i < K; i++)
         for (int j = i; j < K; j++) {
-            if (!pform || blk[i] < blk[j]) want.push_back({i, j, 0, rs[j]});
+            if (!pform || blk[i] < blk[j] || (diag_blocks && blk[i] == blk[j] && blk[i] > 0))
+                want.push_back({i, j, 0, rs[j]});
             if (AS && (!pform || !(blk[i] == 0 && blk[j] == 0))) want.push_back({i, j, 1, ra[j]});
         }
     std::vector<int> tiles;   // (ta << 8) | tb, sorted
@@ -362,16 +369,16 @@ int gram(lobpcg_ctx *c, int dt, int n, const void *const *S, const void *const *
     if (launch_gramx(dt, a, c->st) != hipSuccess) return LOBPCG_ERR_HIP;
     prof_end(c);
     {
-        // each array some tile reads, once
+        // the columns of each array that some tile reads, once
         std::vector<char> used(GX_MAX_ARR, 0);
         for (int t = 0; t < a.ntiles; t++) {
             for (int i = 16 * a.ta[t]; i < std::min(K, 16 * a.ta[t] + 16); i++) used[a.lmap[i] >> 8] = 1;
             for (int j = 16 * a.tb[t]; j < std::min(KR, 16 * a.tb[t] + 16); j++) used[a.rmap[j] >> 8] = 1;
         }
-        double cols = 0.0;
+        double ncols = 0.0;
         for (int b = 0; b < GX_MAX_ARR; b++)
-            if (used[b]) cols += a.ld[b];
-        add_bytes(c, step, cols * c->N * esize(dt));
+            if (used[b]) ncols += w[b % 3];
+        add_bytes(c, step, ncols * c->N * esize(dt));
     }
     HIPCHK(hipMemcpyAsync(h, c->d_gram_out, (size_t)a.ntiles * 256 * 8, hipMemcpyDeviceToHost, c->st));
     int s = sync(c);
@@ -662,6 +669,209 @@ std::vector<int> positions(const std::vector<int> &sub, const std::vector<int> &
     return pos;
 }
 
+// Steps 11-33 with the Cholesky-QR factors of W_J and P_J (steps 11 and 14-15)
+// folded into the Gram matrices and the update coefficients instead of being
+// applied to the blocks.  With W_J = Wn R_W and P_J = Pn R_P, the Gram blocks of
+// the orthonormal Wn, Pn are R^-T (.) R^-1 of those of W_J, P_J, and
+// Wn C_W = W_J (R_W^-1 C_W): the same algebra, with one pass over the blocks
+// (the Gram products, which then include W_J^T W_J and P_J^T P_J) instead of
+// three (Gram, R^-1 applied to W_J; Gram, R^-1 applied to P_J and AP_J).  A W_J
+// is formed from the unnormalised W_J.  On entry W_J = T(residual) is in Wt.
+// Sets `switched` when the FP32 phase of the mixed solver must end.
+int folded_step(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &ps, void *Wt, int nJ,
+                bool explicit_gram, bool allow_switch, bool &switched)
+{
+    const int m = c->m;
+    int s;
+    switched = false;
+    if (Wt == B.AW)
+        std::swap(B.W, B.AW);
+    else if (Wt == B.T0)
+        std::swap(B.W, B.T0);
+    // step 12: A W_J
+    s = apply_A(c, A, dt, B.W, B.AW, nJ);
+    if (s) return s;
+    // P_J: the active columns that have a direction, read in place from B.P
+    std::vector<int> ppos;
+    for (int j : ps.J) {
+        auto it = std::find(ps.Pcols.begin(), ps.Pcols.end(), j);
+        if (it != ps.Pcols.end()) ppos.push_back((int)(it - ps.Pcols.begin()));
+    }
+    int nP = (int)ppos.size();
+    const int np = (int)ps.Pcols.size();
+    // steps 17-23, with the Gram matrices of steps 11 and 14 in the same pass
+    std::vector<double> SS, SAS;
+    {
+        const void *Sb[3] = {B.X[ps.cur], B.W, B.P};
+        const void *ASb[3] = {B.AX[ps.cur], B.AW, B.AP};
+        int wb[3] = {m, nJ, nP}, ldb[3] = {m, nJ, np};
+        const int *cl[3] = {nullptr, nullptr, nP ? ppos.data() : nullptr};
+        s = gram(c, dt, nP ? 3 : 2, Sb, ASb, wb, SS, &SAS, LOBPCG_STEP_GRAM, !explicit_gram, cl, ldb, true);
+        if (s) return s;
+        if (!all_finite(SS) || !all_finite(SAS)) return LOBPCG_ERR_NONFINITE;
+    }
+    const int K0 = m + nJ + nP;
+    auto block = [&](int i0, int n0) {
+        std::vector<double> G((size_t)n0 * n0);
+        for (int i = 0; i < n0; i++)
+            for (int j = 0; j < n0; j++) G[(size_t)i * n0 + j] = SS[(size_t)(i0 + i) * K0 + i0 + j];
+        return G;
+    };
+    // step 11: R_W (failure: the error of step 11, or the end of the FP32 phase)
+    std::vector<double> RiW, RiP;
+    if (!chol_inv(nJ, block(m, nJ), RiW)) {
+        if (allow_switch) {
+            switched = true;
+            return LOBPCG_OK;
+        }
+        return LOBPCG_ERR_CHOL;
+    }
+    // step 14: R_P (failure: this iteration runs without P)
+    if (nP && !chol_inv(nP, block(m + nJ, nP), RiP)) {
+        nP = 0;
+        c->stats.restarts++;
+    }
+    const int nPr = nP;   // order of R_P^-1
+    // (D^T M D) for D = diag(I, R_W^-1, R_P^-1) over the leading K x K part;
+    // the R^-1 are upper triangular
+    auto congruence = [&](const std::vector<double> &M, int K, int nPk) {
+        auto dcol = [&](int j, int &b0, int &jj) {   // block start and index within the block
+            if (j < m) { b0 = -1, jj = j; }
+            else if (j < m + nJ) { b0 = m, jj = j - m; }
+            else { b0 = m + nJ, jj = j - m - nJ; }
+        };
+        std::vector<double> T1((size_t)K * K), out((size_t)K * K);
+        for (int i = 0; i < K; i++)
+            for (int j = 0; j < K; j++) {
+                int b0, jj;
+                dcol(j, b0, jj);
+                double v = 0.0;
+                if (b0 < 0) v = M[(size_t)i * K0 + j];
+                else if (b0 == m)
+                    for (int l = 0; l <= jj; l++) v += M[(size_t)i * K0 + m + l] * RiW[(size_t)l * nJ + jj];
+                else
+                    for (int l = 0; l <= jj; l++) v += M[(size_t)i * K0 + m + nJ + l] * RiP[(size_t)l * nPk + jj];
+                T1[(size_t)i * K + j] = v;
+            }
+        for (int i = 0; i < K; i++)
+            for (int j = 0; j < K; j++) {
+                int b0, ii;
+                dcol(i, b0, ii);
+                double v = 0.0;
+                if (b0 < 0) v = T1[(size_t)i * K + j];
+                else if (b0 == m)
+                    for (int l = 0; l <= ii; l++) v += RiW[(size_t)l * nJ + ii] * T1[(size_t)(m + l) * K + j];
+                else
+                    for (int l = 0; l <= ii; l++) v += RiP[(size_t)l * nPk + ii] * T1[(size_t)(m + nJ + l) * K + j];
+                out[(size_t)i * K + j] = v;
+            }
+        for (int i = 0; i < K; i++)
+            for (int j = i + 1; j < K; j++) {
+                const double v = 0.5 * (out[(size_t)i * K + j] + out[(size_t)j * K + i]);
+                out[(size_t)i * K + j] = out[(size_t)j * K + i] = v;
+            }
+        return out;
+    };
+    // step 24 on the orthonormalised basis [X, Wn, Pn] (on failure with P,
+    // retry without it)
+    std::vector<double> theta(m), C;
+    int Kused = 0;
+    bool ok = false;
+    for (int attempt = 0; attempt < 2 && !ok; attempt++) {
+        if (attempt == 1) {
+            if (!nP) break;
+            nP = 0;
+            c->stats.restarts++;
+        }
+        Kused = m + nJ + nP;
+        std::vector<double> gA = congruence(SAS, Kused, nPr);
+        std::vector<double> gB = congruence(SS, Kused, nPr);
+        if (!explicit_gram) {
+            // the paper's form: Lambda and identities on the block diagonal
+            auto blk = [&](int i0, int n0, std::vector<double> &M, bool lam) {
+                for (int i = 0; i < n0; i++)
+                    for (int j = 0; j < n0; j++)
+                        M[(size_t)(i0 + i) * Kused + i0 + j] = (i == j) ? (lam ? ps.lam[i] : 1.0) : 0.0;
+            };
+            blk(0, m, gA, true);
+            blk(0, m, gB, false);
+            blk(m, nJ, gB, false);
+            if (nP) blk(m + nJ, nP, gB, false);
+        }
+        C.assign((size_t)Kused * m, 0.0);
+        auto t0 = std::chrono::steady_clock::now();
+        ok = rayleigh_ritz(Kused, m, gA.data(), gB.data(), theta.data(), C.data());
+        auto t1 = std::chrono::steady_clock::now();
+        c->stats.step_ms[LOBPCG_STEP_RR] += std::chrono::duration<double, std::milli>(t1 - t0).count();
+        c->stats.step_calls[LOBPCG_STEP_RR] += 1;
+    }
+    if (!ok) {
+        if (allow_switch) {
+            switched = true;
+            return LOBPCG_OK;
+        }
+        return LOBPCG_ERR_RR;
+    }
+    // coefficients for the unnormalised blocks: rows of W_J and P_J times R^-1
+    {
+        std::vector<double> Cd(C);
+        for (int ii = 0; ii < nJ; ii++)
+            for (int j = 0; j < m; j++) {
+                double v = 0.0;
+                for (int l = ii; l < nJ; l++) v += RiW[(size_t)ii * nJ + l] * C[(size_t)(m + l) * m + j];
+                Cd[(size_t)(m + ii) * m + j] = v;
+            }
+        for (int ii = 0; ii < nP; ii++)
+            for (int j = 0; j < m; j++) {
+                double v = 0.0;
+                for (int l = ii; l < nP; l++) v += RiP[(size_t)ii * nPr + l] * C[(size_t)(m + nJ + l) * m + j];
+                Cd[(size_t)(m + nJ + ii) * m + j] = v;
+            }
+        C.swap(Cd);
+    }
+    // steps 25-33 fused with step 7 of the next iteration; the new P, AP go to
+    // the spare pair of blocks (the old P_J is read in place)
+    std::vector<int> jpos(m, -1);
+    for (int i = 0; i < nJ; i++) jpos[ps.J[i]] = i;
+    const int *djpos, *dppos = nullptr;
+    const double *dtheta;
+    s = upload_cols(c, jpos, &djpos);
+    if (s) return s;
+    if (nP) {
+        s = upload_cols(c, ppos, &dppos);
+        if (s) return s;
+    }
+    s = upload_doubles(c, theta, &dtheta);
+    if (s) return s;
+    MV q;
+    q.nside = 2;
+    q.input(0, B.X[ps.cur], B.AX[ps.cur], m, m);
+    q.input(1, B.W, B.AW, nJ, nJ);
+    if (nP) q.input(2, B.P, B.AP, np, nP, dppos);
+    q.kout = m;
+    q.out[0] = B.PJ;
+    q.out[1] = B.APJ;
+    q.opos = djpos;
+    q.nout = nJ;
+    q.out2[0] = B.X[1 - ps.cur];
+    q.out2[1] = B.AX[1 - ps.cur];
+    q.resid = true;
+    q.theta = dtheta;
+    q.wpos = djpos;
+    q.Wout = B.T0;
+    q.nW = nJ;
+    s = mv(c, dt, q, C.data(), LOBPCG_STEP_UPDATE);
+    if (s) return s;
+    std::swap(B.P, B.PJ);
+    std::swap(B.AP, B.APJ);
+    std::swap(B.W, B.T0);
+    ps.Pcols = ps.J;
+    ps.cur = 1 - ps.cur;
+    ps.lam = theta;
+    ps.have_res = true;
+    return LOBPCG_OK;
+}
+
 int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &ps, double tol, double normA,
               int maxit, int &iters, double *h_hist, bool explicit_gram, bool allow_switch, int &outcome)
 {
@@ -741,6 +951,16 @@ int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &
         if (c->mg) {
             s = apply_T(c, dt, B.W, B.AW, B.T0, nJ, &Wt);
             if (s) return s;
+        }
+        if (c->fold) {
+            bool switched;
+            s = folded_step(c, A, dt, B, ps, Wt, nJ, explicit_gram, allow_switch, switched);
+            if (s) return s;
+            if (switched) {
+                outcome = PH_SWITCH;
+                return LOBPCG_OK;
+            }
+            continue;
         }
         // step 11: W_J = W_J R^-1 with R = chol(W_J^T W_J); the result goes to
         // whichever of W / T0 does not hold the input
@@ -1053,6 +1273,7 @@ int lobpcg_setup(lobpcg_ctx **out, const lobpcg_op *A, const lobpcg_op *B, const
     c->gram_staged = 0;
     c->gram_nt4 = 0;
     c->fp32_explicit = true;
+    c->fold = true;
     memset(&c->stats, 0, sizeof(c->stats));
     c->ev_used = 0;
     *out = c;
@@ -1094,6 +1315,7 @@ int lobpcg_set_option(lobpcg_ctx *c, int key, double v)
         return LOBPCG_OK;
     case LOBPCG_OPT_REACTIVATE: c->reactivate = v != 0; return LOBPCG_OK;
     case LOBPCG_OPT_FP32_EXPLICIT_GRAM: c->fp32_explicit = v != 0; return LOBPCG_OK;
+    case LOBPCG_OPT_FOLD_CHOLQR: c->fold = v != 0; return LOBPCG_OK;
     case LOBPCG_OPT_KERNELS:
         if (v < 0 || v > 15 || ((int)v & 3) == 3) return LOBPCG_ERR_ARG;
         c->mv_variant = (int)v & 3;

@@ -23,6 +23,7 @@ FP64, MIXED = 0, 1
 F64, F32 = 0, 1
 OPT_SWITCH_TOL, OPT_STALL_WINDOW, OPT_STALL_FACTOR, OPT_PROFILE, OPT_REACTIVATE, OPT_KERNELS = 0, 1, 2, 3, 4, 5
 OPT_FP32_EXPLICIT_GRAM = 6
+OPT_FOLD_CHOLQR = 7
 STEP_NAMES = ["residual", "precond", "ortho", "apply_A", "gram", "rr_host", "update", "other"]
 
 

@@ -207,6 +207,26 @@ def test_kernel_variants_give_the_same_solution(variant, m):
     assert abs(res[0].iters - res[1].iters) <= 1
 
 
+@pytest.mark.parametrize("prec", [L.FP64, L.MIXED])
+def test_folded_and_applied_cholqr_agree(prec):
+    """Steps 11 and 14-15 with R^-1 applied to W_J, P_J (as printed) and folded
+    into the Gram matrices and coefficients (the default) give the same
+    eigenpairs."""
+    dims, m, levels = (24, 20, 18), 8, 3
+    N = int(np.prod(dims))
+    X0 = dev(synth.x0_uniform(N, m))
+    res = []
+    for fold in (0, 1):
+        ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(levels), m, prec)
+        L.lobpcg_set_option(ctx, L.OPT_FOLD_CHOLQR, fold)
+        res.append(L.lobpcg_solve(ctx, X0, 1e-9, 200))
+    exact, _ = closed_form.smallest(*dims, m)
+    for r in res:
+        assert r.status == L.OK and r.resid.max() <= 1e-9
+        np.testing.assert_allclose(r.lam, exact, rtol=5e-9)
+    assert abs(res[0].iters - res[1].iters) <= 2
+
+
 def test_solver_is_deterministic():
     dims, m = (20, 20, 20), 6
     _, r1, _ = solve(dims, m, 3, L.MIXED, 1e-8, 100)
