@@ -35,6 +35,18 @@ __device__ __forceinline__ void vstore(T *p, const vec<T, V> &x)
     *reinterpret_cast<vec<T, V> *>(p) = x;
 }
 
+// The same store marked non-temporal: streamed results that should not
+// displace operands still to be re-read from the caches.
+template <typename T, int V>
+__device__ __forceinline__ void vstore_nt(T *p, const vec<T, V> &x)
+{
+    typedef T vt __attribute__((ext_vector_type(V)));
+    vt v;
+#pragma unroll
+    for (int i = 0; i < V; i++) v[i] = x.v[i];
+    __builtin_nontemporal_store(v, reinterpret_cast<vt *>(p));
+}
+
 // Workgroup -> tile remap so that consecutive tiles run on one XCD.  The
 // hardware deals workgroups round-robin over the 8 XCDs (workgroup b lands on
 // XCD b % 8); giving each XCD a contiguous range of tiles keeps neighbouring

@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(256) stencil7_kernel(int nx, int ny, int nz, i
                 o.v[q] = (EPI == EPI_JACOBI) ? cur.v[q] + c1 * r : r;
             }
         }
-        vstore<T, V>(out + i, o);
+        vstore_nt<T, V>(out + i, o);
         prev = cur;
         cur = next;
     }
@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(256) varcoef7_kernel(int nx, int ny, int nz, i
             o.v[q] = kxm * (up - xm.v[q]) + kxp * (up - xp.v[q]) + kym * (up - ym.v[q]) +
                      kyp * (up - yp.v[q]) + kzm * (up - prev.v[q]) + kzp * (up - next.v[q]);
         }
-        vstore<T, V>(out + i, o);
+        vstore_nt<T, V>(out + i, o);
         prev = cur;
         cur = next;
     }
