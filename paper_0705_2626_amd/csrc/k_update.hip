@@ -187,7 +187,7 @@ __device__ __forceinline__ void mv_setup(const MVShared<T, NT> &sh, const MVDev<
 }
 
 // write the outputs of side s for the 16 points of this wave
-template <typename T, int NT, typename SH>
+template <typename T, int NT, typename SH, bool SKIP2 = false>
 __device__ __forceinline__ void mv_outputs(const MVDev<T> &a, const SH &sh, int s, i64 p0w,
                                            const typename Mfma<T>::acc (&acc)[NT],
                                            const typename Mfma<T>::acc (&acc2)[NT],
@@ -208,7 +208,7 @@ __device__ __forceinline__ void mv_outputs(const MVDev<T> &a, const SH &sh, int 
             if (a.add && s == 0) v += a.add[p * a.kout + c];
             const int q = sh.opos[c];
             if (out && q >= 0) out[p * a.nout + q] = v;
-            if (has2) out2[p * a.kout + c] = acc2[nt][r];
+            if (has2 && !SKIP2) out2[p * a.kout + c] = acc2[nt][r];
             if (resid && s == 1) {
                 const double x = (double)keepX[nt][r];
                 const double rv = (double)acc2[nt][r] - sh.theta[c] * x;
@@ -374,11 +374,14 @@ __global__ void __launch_bounds__(256) mvd_kernel(MVDev<T> a)
 // after the set-up.
 static const int KQ = MAXW / 4;    // most k-steps of one input
 
+__host__ __device__ inline size_t mvf_stage_offset(int nsteps, int NT, int K, size_t esz);
+
 template <typename T, int NT>
 struct MVFShared {
     T *Cf;                 // [sum k4][NT][64]
     double *theta, *red;
     int *cmap, *opos, *wpos;
+    T *stage;              // [4 waves][16][NC + 4]: one output tile of each wave
     __device__ MVFShared(unsigned char *smem, const MVDev<T> &a, int nsteps)
     {
         const int NC = NT * 16;
@@ -388,8 +391,20 @@ struct MVFShared {
         cmap = reinterpret_cast<int *>(red + 16 * 2 * NC);
         opos = cmap + a.K + 4;
         wpos = opos + NC;
+        stage = reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(smem) +
+                                      mvf_stage_offset(nsteps, NT, a.K, sizeof(T)));
     }
 };
+
+// the output staging area of MVFShared: after the other arrays, 16-byte aligned
+__host__ __device__ inline size_t mvf_stage_offset(int nsteps, int NT, int K, size_t esz)
+{
+    const int NC = NT * 16;
+    size_t off = (size_t)nsteps * NT * 64 * esz;
+    off = (off + 7) / 8 * 8 + (size_t)NC * 8 + (size_t)16 * 2 * NC * 8 + (size_t)(K + 4 + 2 * NC) * sizeof(int);
+    return (off + 15) / 16 * 16;
+}
+__host__ __device__ inline size_t mvf_stage_bytes(int NT, size_t esz) { return (size_t)4 * 16 * (NT * 16 + 4) * esz; }
 
 // av[i] = column (l/16)*k4 + i of this lane's row (zero past k or the grid)
 template <typename T>
@@ -476,6 +491,7 @@ __global__ void __launch_bounds__(256) mvf_kernel(MVDev<T> a)
     const i64 ngroups = (a.N + 15) / 16, gstride = (i64)gridDim.x * 4;
     i64 g = (i64)blockIdx.x * 4 + wave;
     if constexpr (sizeof(T) == 4) {
+        const bool stage2 = has2 && (a.kout % 4) == 0;
         // FP32: input 0 (X, the widest block, or the only input) is loaded for
         // both sides one group ahead, so that its loads are in flight while the
         // current group is multiplied
@@ -510,7 +526,32 @@ __global__ void __launch_bounds__(256) mvf_kernel(MVDev<T> a)
                     for (int nt = 0; nt < NT; nt++) acc2[nt] = acc[nt];
                     mma_in(acc2, x0[s], 0);
                 }
-                mv_outputs<T, NT>(a, sh, s, p0w, acc, acc2, keepX, sr, sx, lane);
+                if (stage2) {
+                    // out2 through LDS: the MFMA layout gives each lane one
+                    // column of four rows; after the transpose each lane holds
+                    // four consecutive columns of one row and stores 16 bytes.
+                    // The tile is private to this wave and LDS operations of
+                    // one wave complete in order.
+                    mv_outputs<T, NT, MVFShared<T, NT>, true>(a, sh, s, p0w, acc, acc2, keepX, sr, sx, lane);
+                    T *st = sh.stage + wave * 16 * (NC + 4);
+#pragma unroll
+                    for (int r = 0; r < 4; r++)
+#pragma unroll
+                        for (int nt = 0; nt < NT; nt++)
+                            st[Mfma<T>::row(lane, r) * (NC + 4) + 16 * nt + (lane & 15)] = acc2[nt][r];
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    const int row = lane >> 2;
+                    const i64 p = p0w + row;
+#pragma unroll
+                    for (int h = 0; h < NT * 4 / 4; h++) {
+                        const int c0 = 4 * ((lane & 3) + 4 * h);
+                        const vec<T, 4> v = *reinterpret_cast<const vec<T, 4> *>(st + row * (NC + 4) + c0);
+                        if (p < a.N && c0 < a.kout) vstore<T, 4>(a.out2[s] + p * a.kout + c0, v);
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                } else {
+                    mv_outputs<T, NT>(a, sh, s, p0w, acc, acc2, keepX, sr, sx, lane);
+                }
                 if (s == 0) {
 #pragma unroll
                     for (int nt = 0; nt < NT; nt++) keepX[nt] = acc2[nt];
@@ -729,7 +770,7 @@ static hipError_t run_mv(const MVArgs &h, hipStream_t st)
     } else if (h.variant == 0) {
         int nsteps = 0;
         for (int b = 0; b < h.nin; b++) nsteps += (h.k[b] + 3) / 4;
-        const size_t shm = (size_t)nsteps * NT * 64 * sizeof(T) + tail;
+        const size_t shm = mvf_stage_offset(nsteps, NT, a.K, sizeof(T)) + mvf_stage_bytes(NT, sizeof(T));
         hipLaunchKernelGGL((mvf_kernel<T, NT>), dim3(nb), dim3(256), shm, st, a);
     } else {
         const bool staged = any_wide && h.variant == 2;

@@ -282,7 +282,7 @@ int apply_A(lobpcg_ctx *c, const lobpcg_op *A, int dt, const void *in, void *out
 // when AS is given, AS = [AS_0 .. AS_{n-1}]; returns K x K host matrices
 // (row-major, symmetric).  They are entries of Lm^T Rm with Lm = S and
 //  - no AS: Rm = S (S^T S, the Cholesky Gram matrices of steps 3, 11, 14);
-//  - AS, explicit form: Rm = [S AS], all of S^T S and S^T AS;
+//  - AS, explicit form: Rm = [S_0 AS_0 S_1.. AS_1..], all of S^T S and S^T AS;
 //  - AS, the paper's form (steps 17-23): Rm = [S_1.. AS_1..] (W, P, AW, AP)
 //    and only the entries the paper does not take as known: gramB off the
 //    block diagonal, gramA outside the X-X block (the caller fills Lambda
@@ -336,6 +336,12 @@ int gram(lobpcg_ctx *c, int dt, int n, const void *const *S, const void *const *
         a.rmap[KR++] = (unsigned short)((arr << 8) | col[i]);
     };
     if (pform) {
+        for (int i = w[0]; i < K; i++) addr(blk[i], i, rs);
+        for (int i = w[0]; i < K; i++) addr(3 + blk[i], i, ra);
+    } else if (AS && n > 1) {
+        // [S_0 AS_0 | S_1.. AS_1..]: the thin blocks share 16-column tiles
+        for (int i = 0; i < w[0]; i++) addr(0, i, rs);
+        for (int i = 0; i < w[0]; i++) addr(3, i, ra);
         for (int i = w[0]; i < K; i++) addr(blk[i], i, rs);
         for (int i = w[0]; i < K; i++) addr(3 + blk[i], i, ra);
     } else {
