@@ -1,7 +1,7 @@
 """Block LOBPCG oracle, FP64 (test infrastructure only).
 
-Follows the algorithm of Section 2.2 (steps 1-37) for B = I and no
-constraints Y (steps 2 and 10 are then empty), with soft locking as described
+Follows the algorithm of Section 2.2 (steps 1-37) for B = I, with optional
+constraints Y (steps 2 and 10: hard locking) and soft locking as described
 in Section 2.3: only the active columns J get residuals, preconditioned
 residuals W_J and directions P_J, while all m columns of X take part in every
 Rayleigh-Ritz procedure.
@@ -75,10 +75,14 @@ class Result:
         self.__dict__.update(kw)
 
 
-def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactivate=True):
+def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactivate=True, Y=None):
     """Smallest eigenpairs of A x = lambda x (Section 2.1.1, B = I).
 
     apply_A, apply_T: functions on (N, k) blocks.  X0: (N, m) start block.
+    Y: optional (N, l) constraint vectors of full column rank: the
+    eigenvectors are sought in the orthogonal complement of span(Y), which
+    steps 2 and 10 impose on X0 and on every preconditioned residual block
+    (hard locking, Section 2.3).
     Returns Result(status, lam, X, hist, iters, resid) where hist[k] holds
     rho_j of every column at iteration k and resid the explicit final rho_j.
     """
@@ -87,6 +91,16 @@ def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactiva
     if not np.all(np.isfinite(X0)):
         return Result(status=ERR_NONFINITE, lam=None, X=None, hist=np.zeros((0, m)), iters=0, resid=None)
     T = apply_T if apply_T is not None else (lambda V: V)
+    if Y is not None:
+        Y = np.asfortranarray(np.asarray(Y, dtype=np.float64))
+        YtY = Y.T @ Y
+
+        def constrain(V):
+            # steps 2 and 10 with B = I: V - Y (Y^T Y)^-1 (Y^T V)
+            return V - Y @ np.linalg.solve(YtY, Y.T @ V)
+        X0 = np.asfortranarray(constrain(X0))                  # step 2
+    else:
+        constrain = None
 
     def rho_of(X, AX, lam):
         Rr = AX - X * lam[None, :]
@@ -121,6 +135,8 @@ def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactiva
             status = OK
             break
         W = T(np.asfortranarray(Rr[:, J]))                     # step 9
+        if constrain is not None:                              # step 10
+            W = np.asfortranarray(constrain(W))
         try:                                                   # step 11
             (W,) = orthonormalize(W)
         except CholeskyFailure:
@@ -181,14 +197,15 @@ def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactiva
 
 
 def laplace7_solver(dims, m, X0, tol, maxit, levels=None, nu_pre=2, nu_post=2, coarse_sweeps=20,
-                    omega=2.0 / 3.0, callback=None):
-    """LOBPCG on the 7-point Laplacian with optional V-cycle preconditioning."""
+                    omega=2.0 / 3.0, callback=None, Y=None):
+    """LOBPCG on the 7-point Laplacian with optional V-cycle preconditioning
+    and optional constraints Y."""
     from . import grid, mg
     A = lambda V: grid.laplace7(dims, V)
     T = None
     if levels:
         T = mg.VCycle(dims, levels, nu_pre, nu_post, coarse_sweeps, omega)
-    return lobpcg(A, X0, tol, maxit, grid.gershgorin_laplace7(), apply_T=T, callback=callback)
+    return lobpcg(A, X0, tol, maxit, grid.gershgorin_laplace7(), apply_T=T, callback=callback, Y=Y)
 
 
 def varcoef_solver(dims, kx, ky, kz, m, X0, tol, maxit, levels=None, callback=None):

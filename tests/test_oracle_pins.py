@@ -436,3 +436,42 @@ def test_laplace7_rows_matches_full_operator():
     U = synth.random_block(210, 3, seed=21)
     pts = np.array([0, 1, 6, 34, 35, 100, 209])
     np.testing.assert_allclose(grid.laplace7_rows(dims, U, pts), grid.laplace7(dims, U)[pts], rtol=0, atol=1e-14)
+
+
+# ---------------------------------------------------------------- constraints Y (steps 2 and 10)
+
+def test_constraints_give_the_next_eigenpairs():
+    """Hard locking: with Y = the exact eigenvectors of the m smallest
+    eigenvalues, LOBPCG in span(Y)^perp finds eigenvalues m+1 .. 2m (closed
+    form, Section 4.1) and its vectors stay orthogonal to Y."""
+    dims, m = (12, 10, 8), 4
+    N = int(np.prod(dims))
+    lam, ijk = closed_form.smallest(*dims, 2 * m)
+    assert np.all(np.diff(lam) > 1e-6)            # simple spectrum here
+    Y = np.stack([closed_form.mode(*dims, *t) for t in ijk[:m]], axis=1)
+    Y /= np.linalg.norm(Y, axis=0)
+    X0 = synth.x0_uniform(N, m, seed=3)
+    r = lobpcg.laplace7_solver(dims, m, X0, 1e-10, 300, levels=2, Y=Y)
+    assert r.status == lobpcg.OK
+    np.testing.assert_allclose(r.lam, lam[m:], rtol=1e-9)
+    assert np.abs(Y.T @ r.X).max() < 1e-9
+    # without the constraints the same start finds the m smallest instead
+    r0 = lobpcg.laplace7_solver(dims, m, X0, 1e-10, 300, levels=2)
+    np.testing.assert_allclose(r0.lam, lam[:m], rtol=1e-9)
+
+
+def test_constraints_match_dense_projected_eigenproblem():
+    """Y spanning an invariant subspace that is not the lowest one, given by a
+    non-orthonormal basis (a random mix of the exact eigenvectors 0, 2 and 5
+    of a dense solve, N = 72): the constrained problem's m smallest eigenvalues
+    are those of indices 1, 3, 4 (brute force), and the vectors stay orthogonal
+    to Y.  The mix makes the (Y^T Y)^-1 of steps 2 and 10 matter."""
+    dims, m = (6, 4, 3), 3
+    N = int(np.prod(dims))
+    lam, V = np.linalg.eigh(dense_laplace7(*dims))
+    assert np.all(np.diff(lam[:6]) > 1e-8)
+    Y = V[:, [0, 2, 5]] @ np.random.default_rng(12).standard_normal((3, 3))
+    r = lobpcg.laplace7_solver(dims, m, synth.x0_uniform(N, m, seed=4), 1e-11, 500, Y=Y)
+    assert r.status == lobpcg.OK
+    np.testing.assert_allclose(r.lam, lam[[1, 3, 4]], rtol=1e-10)
+    assert np.abs(Y.T @ r.X).max() < 1e-10
