@@ -96,7 +96,7 @@ int lobpcg_setup(lobpcg_ctx **ctx, const lobpcg_op *A, const lobpcg_op *B, const
                  int m, int precision, void *d_workspace, size_t ws_bytes, void *stream);
 
 /* Solve for the m smallest eigenpairs (Section 2.2, steps 1-37, B = I, no
- * constraints).  A must have the dimensions and kind given to setup (its
+ * constraints; see lobpcg_solve_constrained for steps 2 and 10).  A must have the dimensions and kind given to setup (its
  * face arrays may differ between calls); T must equal setup's.
  *   d_X0         N x m FP64 start block (linearly independent columns)
  *   tol          stop when every rho_j = ||A x_j - lambda_j x_j|| / (||A|| ||x_j||)
@@ -112,6 +112,23 @@ int lobpcg_setup(lobpcg_ctx **ctx, const lobpcg_op *A, const lobpcg_op *B, const
 int lobpcg_solve(lobpcg_ctx *ctx, const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T,
                  const double *d_X0, int m, double tol, int maxit, double *h_lambda, double *d_X,
                  double *h_hist, int *h_iters, double *h_final_resid);
+
+/* lobpcg_solve with constraints (hard locking, Section 2.3): the eigenpairs
+ * are sought in the orthogonal complement of span(Y), imposed on X0 (step 2)
+ * and on every preconditioned residual block (step 10) as
+ * V - Y (Y^T Y)^-1 (Y^T V).
+ *   d_Y   N x ny FP64, point-major, full column rank, 1 <= ny <= 32,
+ *         3m + ny <= N; caller-owned, read during the call only
+ * As printed, step 7 does not project the residual: it goes to zero only when
+ * span(Y) is invariant under A, as for previously computed eigenvectors (the
+ * intended use: repeated calls with the converged X appended to Y give the
+ * next eigenpairs).  FP64 contexts only (MIXED: ERR_UNSUPPORTED); a
+ * rank-deficient Y (Cholesky of Y^T Y fails) gives ERR_ARG.  Other arguments
+ * and outputs as lobpcg_solve. */
+int lobpcg_solve_constrained(lobpcg_ctx *ctx, const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T,
+                             const double *d_Y, int ny, const double *d_X0, int m, double tol, int maxit,
+                             double *h_lambda, double *d_X, double *h_hist, int *h_iters,
+                             double *h_final_resid);
 
 /* Hellmann-Feynman eigenvalue adjoint for VARCOEF7: for
  * lambda_i = (x_i, A x_i) / (x_i, x_i) and A = sum_f k_f (e_p - e_q)(e_p - e_q)^T,

@@ -157,6 +157,9 @@ struct lobpcg_ctx {
     int mv_variant, gram_staged, gram_nt4;  // kernel variants (see LOBPCG_OPT_KERNELS)
     bool fp32_explicit;           // FP32 phase: Gram diagonal blocks computed, not assumed
     bool fold;                    // Cholesky-QR factors of W_J, P_J folded into Gram and coefficients
+    const double *Y;              // constraints of the current solve (FP64, N x ny) or null
+    int ny;
+    std::vector<double> RY;       // Y^T Y = RY^T RY (upper, ny x ny)
     lobpcg_stats stats;
     // profiling: pending (step, start, end) event pairs
     std::vector<hipEvent_t> ev_pool;
@@ -675,6 +678,72 @@ std::vector<int> positions(const std::vector<int> &sub, const std::vector<int> &
     return pos;
 }
 
+// Steps 2 and 10 with B = I: dst = V - Y (Y^T Y)^-1 (Y^T V) for the N x k
+// block V (FP64).  Y^T V comes from the Gram kernel (Lm = Y, Rm = V), the
+// small solve runs on the host with the Cholesky factor of Y^T Y, and the
+// update is one multivector product [V Y] [I; -C].
+int constrain(lobpcg_ctx *c, const void *V, int k, void *dst, int step)
+{
+    const int ny = c->ny;
+    GramXArgs a;
+    for (int b = 0; b < GX_MAX_ARR; b++) a.arr[b] = nullptr, a.ld[b] = 1;
+    a.arr[0] = c->Y, a.ld[0] = ny;
+    a.arr[1] = V, a.ld[1] = k;
+    a.KL = ny;
+    a.KR = k;
+    for (int i = 0; i < ny; i++) a.lmap[i] = (unsigned short)i;
+    for (int j = 0; j < k; j++) a.rmap[j] = (unsigned short)((1 << 8) | j);
+    const int TL = (ny + 15) / 16, TR = (k + 15) / 16;
+    a.ntiles = TL * TR;
+    for (int t = 0; t < a.ntiles; t++) a.ta[t] = t / TR, a.tb[t] = t % TR;
+    a.N = c->N;
+    a.partials = c->d_gram_part;
+    a.out = c->d_gram_out;
+    a.max_nt = 2;
+    prof_begin(c, step);
+    if (launch_gramx(DT_F64, a, c->st) != hipSuccess) return LOBPCG_ERR_HIP;
+    prof_end(c);
+    add_bytes(c, step, (double)(ny + k) * c->N * 8.0);
+    double *h = (double *)(c->h_pin + c->h_gram_off);
+    HIPCHK(hipMemcpyAsync(h, c->d_gram_out, (size_t)a.ntiles * 256 * 8, hipMemcpyDeviceToHost, c->st));
+    int s = sync(c);
+    if (s) return s;
+    // Y^T V (ny x k) from the tiles (FP64 accumulator layout: row l/16 + 4r)
+    std::vector<double> G((size_t)ny * k);
+    for (int t = 0; t < a.ntiles; t++)
+        for (int e = 0; e < 256; e++) {
+            const int r = e / 64, lane = e % 64;
+            const int i = 16 * a.ta[t] + lane / 16 + 4 * r, j = 16 * a.tb[t] + lane % 16;
+            if (i < ny && j < k) G[(size_t)i * k + j] = h[(size_t)t * 256 + e];
+        }
+    if (!all_finite(G)) return LOBPCG_ERR_NONFINITE;
+    // C = (RY^T RY)^-1 G: forward then back substitution, column by column
+    std::vector<double> C(G);
+    for (int j = 0; j < k; j++) {
+        for (int i = 0; i < ny; i++) {
+            double v = C[(size_t)i * k + j];
+            for (int l = 0; l < i; l++) v -= c->RY[(size_t)l * ny + i] * C[(size_t)l * k + j];
+            C[(size_t)i * k + j] = v / c->RY[(size_t)i * ny + i];
+        }
+        for (int i = ny - 1; i >= 0; i--) {
+            double v = C[(size_t)i * k + j];
+            for (int l = i + 1; l < ny; l++) v -= c->RY[(size_t)i * ny + l] * C[(size_t)l * k + j];
+            C[(size_t)i * k + j] = v / c->RY[(size_t)i * ny + i];
+        }
+    }
+    // [V Y] [I; -C]
+    std::vector<double> coef((size_t)(k + ny) * k, 0.0);
+    for (int i = 0; i < k; i++) coef[(size_t)i * k + i] = 1.0;
+    for (int i = 0; i < ny; i++)
+        for (int j = 0; j < k; j++) coef[(size_t)(k + i) * k + j] = -C[(size_t)i * k + j];
+    MV q;
+    q.input(0, V, nullptr, k, k);
+    q.input(1, c->Y, nullptr, ny, ny);
+    q.kout = k;
+    q.out[0] = dst;
+    return mv(c, DT_F64, q, coef.data(), step);
+}
+
 // Steps 11-33 with the Cholesky-QR factors of W_J and P_J (steps 11 and 14-15)
 // folded into the Gram matrices and the update coefficients instead of being
 // applied to the blocks.  With W_J = Wn R_W and P_J = Pn R_P, the Gram blocks of
@@ -957,6 +1026,13 @@ int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &
         if (c->mg) {
             s = apply_T(c, dt, B.W, B.AW, B.T0, nJ, &Wt);
             if (s) return s;
+        }
+        // step 10: W_J = W_J - Y (Y^T Y)^-1 (Y^T W_J)
+        if (c->ny) {
+            void *dst = (Wt == B.T0) ? B.AW : B.T0;
+            s = constrain(c, Wt, nJ, dst, LOBPCG_STEP_PRECOND);
+            if (s) return s;
+            Wt = dst;
         }
         if (c->fold) {
             bool switched;
@@ -1280,6 +1356,8 @@ int lobpcg_setup(lobpcg_ctx **out, const lobpcg_op *A, const lobpcg_op *B, const
     c->gram_nt4 = 0;
     c->fp32_explicit = true;
     c->fold = true;
+    c->Y = nullptr;
+    c->ny = 0;
     memset(&c->stats, 0, sizeof(c->stats));
     c->ev_used = 0;
     *out = c;
@@ -1351,20 +1429,35 @@ static int same_precond(const lobpcg_ctx *c, const lobpcg_precond *T)
            T->nu_post == c->T.nu_post && T->coarse_sweeps == c->T.coarse_sweeps && T->omega == c->T.omega;
 }
 
-int lobpcg_solve(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T, const double *d_X0,
-                 int m, double tol, int maxit, double *h_lambda, double *d_X, double *h_hist, int *h_iters,
-                 double *h_final_resid)
+static int solve_impl(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T,
+                      const double *d_Y, int ny, const double *d_X0, int m, double tol, int maxit, double *h_lambda,
+                      double *d_X, double *h_hist, int *h_iters, double *h_final_resid)
 {
     if (!c) return LOBPCG_ERR_ARG;
     if (B) return LOBPCG_ERR_UNSUPPORTED;
     if (!same_op(c, A) || !same_precond(c, T) || m != c->m || !d_X0 || !d_X || !h_lambda || !h_iters ||
         !(tol > 0) || maxit < 0)
         return LOBPCG_ERR_ARG;
+    if (ny < 0 || ny > LOBPCG_MAX_M || (ny > 0 && !d_Y) || 3LL * m + ny > c->N) return LOBPCG_ERR_ARG;
+    if (ny > 0 && c->precision != LOBPCG_FP64) return LOBPCG_ERR_UNSUPPORTED;
     auto t0 = std::chrono::steady_clock::now();
     memset(&c->stats, 0, sizeof(c->stats));
     c->ev_used = 0;
     c->coef_slot = 0;
     *h_iters = 0;
+    c->Y = ny ? d_Y : nullptr;
+    c->ny = ny;
+    if (ny) {
+        // the Cholesky factor of Y^T Y (Y must have full column rank)
+        std::vector<double> G;
+        const void *Sb[1] = {d_Y};
+        int w1[1] = {ny};
+        int s0 = gram(c, DT_F64, 1, Sb, nullptr, w1, G, nullptr, LOBPCG_STEP_OTHER);
+        if (s0) return s0;
+        if (!all_finite(G)) return LOBPCG_ERR_NONFINITE;
+        c->RY.assign((size_t)ny * ny, 0.0);
+        if (!chol_scaled(ny, G.data(), c->RY.data())) return LOBPCG_ERR_ARG;
+    }
     const double normA = op_norm(c, A);
     if (!(normA > 0)) return LOBPCG_ERR_HIP;
     const size_t nm = (size_t)c->N * m;
@@ -1404,7 +1497,13 @@ int lobpcg_solve(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, const lo
                 s = run_phase(c, A, DT_F64, c->b64, ps, tol, normA, maxit, iters, h_hist, false, false, outcome);
         }
     } else {
-        HIPCHK(hipMemcpyAsync(c->b64.X[0], d_X0, nm * 8, hipMemcpyDeviceToDevice, c->st));
+        if (ny) {
+            // step 2: X0 - Y (Y^T Y)^-1 (Y^T X0)
+            s = constrain(c, d_X0, m, c->b64.X[0], LOBPCG_STEP_OTHER);
+            if (s) return s;
+        } else {
+            HIPCHK(hipMemcpyAsync(c->b64.X[0], d_X0, nm * 8, hipMemcpyDeviceToDevice, c->st));
+        }
         s = init_phase(c, A, DT_F64, c->b64, ps, true, false);
         if (s == LOBPCG_OK)
             s = run_phase(c, A, DT_F64, c->b64, ps, tol, normA, maxit, iters, h_hist, false, false, outcome);
@@ -1432,6 +1531,21 @@ int lobpcg_solve(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, const lo
     c->stats.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     c->stats.status = outcome == PH_CONVERGED ? LOBPCG_OK : LOBPCG_NOT_CONVERGED;
     return c->stats.status;
+}
+
+int lobpcg_solve(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T, const double *d_X0,
+                 int m, double tol, int maxit, double *h_lambda, double *d_X, double *h_hist, int *h_iters,
+                 double *h_final_resid)
+{
+    return solve_impl(c, A, B, T, nullptr, 0, d_X0, m, tol, maxit, h_lambda, d_X, h_hist, h_iters, h_final_resid);
+}
+
+int lobpcg_solve_constrained(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T,
+                             const double *d_Y, int ny, const double *d_X0, int m, double tol, int maxit,
+                             double *h_lambda, double *d_X, double *h_hist, int *h_iters, double *h_final_resid)
+{
+    if (ny < 1 || !d_Y) return LOBPCG_ERR_ARG;
+    return solve_impl(c, A, B, T, d_Y, ny, d_X0, m, tol, maxit, h_lambda, d_X, h_hist, h_iters, h_final_resid);
 }
 
 int lobpcg_eig_grad_k(lobpcg_ctx *c, const double *d_X, const double *h_gbar, int m, double *gkx, double *gky,

@@ -70,6 +70,7 @@ def lib():
             "lobpcg_workspace_bytes": (i, [P(_Op), P(_Op), P(_Precond), i, i, P(sz)]),
             "lobpcg_setup": (i, [P(p), P(_Op), P(_Op), P(_Precond), i, i, p, sz, p]),
             "lobpcg_solve": (i, [p, P(_Op), P(_Op), P(_Precond), p, i, d, i, p, p, p, p, p]),
+            "lobpcg_solve_constrained": (i, [p, P(_Op), P(_Op), P(_Precond), p, i, p, i, d, i, p, p, p, p, p]),
             "lobpcg_eig_grad_k": (i, [p, p, p, i, p, p, p]),
             "lobpcg_destroy": (None, [p]),
             "lobpcg_status_string": (ctypes.c_char_p, [i]),
@@ -205,9 +206,10 @@ class SolveResult:
         self.__dict__.update(kw)
 
 
-def lobpcg_solve(ctx, X0, tol, maxit, A=None, hist=True, raise_on_error=True):
-    """Smallest eigenpairs.  X0: (N, m) float64 device tensor.  Returns a
-    SolveResult(status, lam, X, hist, iters, resid)."""
+def lobpcg_solve(ctx, X0, tol, maxit, A=None, hist=True, raise_on_error=True, Y=None):
+    """Smallest eigenpairs.  X0: (N, m) float64 device tensor; Y: optional
+    (N, l) float64 device tensor of constraints (lobpcg_solve_constrained).
+    Returns a SolveResult(status, lam, X, hist, iters, resid)."""
     A = A if A is not None else ctx.A
     N, m = ctx.N, ctx.m
     X0 = _blk(ctx, X0, "X0", m, torch.float64)
@@ -216,9 +218,14 @@ def lobpcg_solve(ctx, X0, tol, maxit, A=None, hist=True, raise_on_error=True):
     H = np.zeros((max(maxit, 1), m)) if hist else None
     iters = ctypes.c_int(0)
     res = np.zeros(m)
-    s = lib().lobpcg_solve(ctx.h, ctypes.byref(A.c()), None, ctypes.byref(ctx.T.c()), _ptr(X0), m, float(tol),
-                           int(maxit), _np_ptr(lam), _ptr(X), _np_ptr(H) if hist else None, ctypes.byref(iters),
-                           _np_ptr(res))
+    tail = (m, float(tol), int(maxit), _np_ptr(lam), _ptr(X), _np_ptr(H) if hist else None, ctypes.byref(iters),
+            _np_ptr(res))
+    if Y is None:
+        s = lib().lobpcg_solve(ctx.h, ctypes.byref(A.c()), None, ctypes.byref(ctx.T.c()), _ptr(X0), *tail)
+    else:
+        Y = _blk(ctx, Y, "Y", dtype=torch.float64)
+        s = lib().lobpcg_solve_constrained(ctx.h, ctypes.byref(A.c()), None, ctypes.byref(ctx.T.c()), _ptr(Y),
+                                           int(Y.shape[1]), _ptr(X0), *tail)
     if raise_on_error:
         _check(s, "lobpcg_solve", allow=(OK, NOT_CONVERGED))
     return SolveResult(status=s, lam=lam, X=X, hist=H[:iters.value] if hist else None, iters=iters.value,

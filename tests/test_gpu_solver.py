@@ -246,3 +246,67 @@ def test_soft_locking_reduces_active_work():
     # some column dropped below tol before the last iteration
     first_below = [int(np.argmax(H[:, j] <= 1e-9)) if np.any(H[:, j] <= 1e-9) else H.shape[0] for j in range(m)]
     assert min(first_below) < H.shape[0] - 1
+
+
+# ---------------------------------------------------------------- constraints Y (steps 2 and 10)
+
+def sine_block(dims, ijk):
+    V = np.stack([closed_form.mode(*dims, *t) for t in ijk], axis=1)
+    return V / np.linalg.norm(V, axis=0)
+
+
+@pytest.mark.parametrize("mix", [False, True])
+def test_constraints_match_oracle(mix):
+    """Y = the exact eigenvectors of the 6 smallest eigenvalues (or a random,
+    non-orthonormal basis of their span): GPU and oracle find eigenvalues
+    7..12, with vectors orthogonal to Y."""
+    dims, m, levels, tol = (24, 20, 16), 6, 3, 1e-9
+    N = int(np.prod(dims))
+    lam, ijk = closed_form.smallest(*dims, 2 * m)
+    Y = sine_block(dims, ijk[:m])
+    if mix:
+        Y = Y @ np.random.default_rng(7).standard_normal((m, m))
+    X0 = synth.x0_uniform(N, m, seed=5)
+    ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(levels), m, L.FP64)
+    r = L.lobpcg_solve(ctx, dev(X0), tol, 200, Y=dev(Y))
+    ref = olob.laplace7_solver(dims, m, X0, tol, 200, levels=levels, Y=Y)
+    assert r.status == L.OK and ref.status == olob.OK
+    np.testing.assert_allclose(r.lam, lam[m:], rtol=5e-9)
+    np.testing.assert_allclose(r.lam, ref.lam, rtol=5e-9)
+    assert r.resid.max() <= tol
+    assert np.abs(Y.T @ r.X.cpu().numpy()).max() < 1e-8 * np.abs(Y).max() * np.sqrt(N)
+    assert abs(r.iters - ref.iters) <= 2, (r.iters, ref.iters)
+
+
+def test_constraints_repeated_calls_give_successive_eigenpairs():
+    """Hard locking as intended: each call appends its converged vectors to Y
+    and the next call finds the next block of the spectrum."""
+    dims, m, tol = (20, 18, 16), 4, 1e-10
+    N = int(np.prod(dims))
+    lam, _ = closed_form.smallest(*dims, 3 * m)
+    ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(3), m, L.FP64)
+    Y = None
+    found = []
+    for call in range(3):
+        r = L.lobpcg_solve(ctx, dev(synth.x0_uniform(N, m, seed=20 + call)), tol, 300, Y=Y)
+        assert r.status == L.OK
+        found.append(r.lam)
+        Y = r.X.clone() if Y is None else torch.cat([Y, r.X], dim=1).contiguous()
+    np.testing.assert_allclose(np.concatenate(found), lam, rtol=1e-9)
+    G = (Y.T @ Y).cpu().numpy()
+    np.testing.assert_allclose(G, np.eye(3 * m), atol=1e-9)
+
+
+def test_constraints_error_paths():
+    dims, m = (12, 10, 8), 3
+    N = int(np.prod(dims))
+    X0 = dev(synth.x0_uniform(N, m))
+    Y = synth.random_block(N, 2, seed=1)
+    ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(None), m, L.MIXED)
+    r = L.lobpcg_solve(ctx, X0, 1e-8, 10, Y=dev(Y), raise_on_error=False)
+    assert r.status == L.ERR_UNSUPPORTED
+    ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(None), m, L.FP64)
+    r = L.lobpcg_solve(ctx, X0, 1e-8, 10, Y=dev(np.hstack([Y, Y[:, :1]])), raise_on_error=False)
+    assert r.status == L.ERR_ARG          # rank-deficient constraints
+    r = L.lobpcg_solve(ctx, X0, 1e-8, 10, Y=dev(synth.random_block(N, 33, seed=2)), raise_on_error=False)
+    assert r.status == L.ERR_ARG          # more than 32 constraint vectors
