@@ -1,7 +1,8 @@
 """Block LOBPCG oracle, FP64 (test infrastructure only).
 
-Follows the algorithm of Section 2.2 (steps 1-37) for B = I, with optional
-constraints Y (steps 2 and 10: hard locking) and soft locking as described
+Follows the algorithm of Section 2.2 (steps 1-37), for B = I or a given SPD
+B, with optional constraints Y (steps 2 and 10: hard locking) and soft
+locking as described
 in Section 2.3: only the active columns J get residuals, preconditioned
 residuals W_J and directions P_J, while all m columns of X take part in every
 Rayleigh-Ritz procedure.
@@ -75,53 +76,64 @@ class Result:
         self.__dict__.update(kw)
 
 
-def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactivate=True, Y=None):
-    """Smallest eigenpairs of A x = lambda x (Section 2.1.1, B = I).
+def b_orthonormalize(V, BV, *others):
+    """B-orthonormalisation (steps 3, 11, 14-15): R = chol(V^T BV);
+    V R^-1, BV R^-1 (and others R^-1)."""
+    R = chol_scaled(V.T @ BV)
+    return (right_solve_upper(V, R), right_solve_upper(BV, R)) + tuple(right_solve_upper(O, R) for O in others)
 
-    apply_A, apply_T: functions on (N, k) blocks.  X0: (N, m) start block.
+
+def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactivate=True, Y=None, apply_B=None):
+    """Smallest eigenpairs of A x = lambda B x (Section 2.1.1).
+
+    apply_A, apply_T, apply_B: functions on (N, k) blocks (apply_B None: B = I).
+    X0: (N, m) start block.
     Y: optional (N, l) constraint vectors of full column rank: the
-    eigenvectors are sought in the orthogonal complement of span(Y), which
+    eigenvectors are sought in the B-orthogonal complement of span(Y), which
     steps 2 and 10 impose on X0 and on every preconditioned residual block
     (hard locking, Section 2.3).
     Returns Result(status, lam, X, hist, iters, resid) where hist[k] holds
-    rho_j of every column at iteration k and resid the explicit final rho_j.
+    rho_j = ||A x_j - lambda_j B x_j|| / (||A|| ||B x_j||) of every column at
+    iteration k and resid the explicit final rho_j.
     """
     X0 = np.asfortranarray(np.asarray(X0, dtype=np.float64))
     N, m = X0.shape
     if not np.all(np.isfinite(X0)):
         return Result(status=ERR_NONFINITE, lam=None, X=None, hist=np.zeros((0, m)), iters=0, resid=None)
     T = apply_T if apply_T is not None else (lambda V: V)
+    Bop = apply_B if apply_B is not None else (lambda V: V)
     if Y is not None:
         Y = np.asfortranarray(np.asarray(Y, dtype=np.float64))
-        YtY = Y.T @ Y
+        BY = Bop(Y)
+        YtBY = Y.T @ BY
 
         def constrain(V):
-            # steps 2 and 10 with B = I: V - Y (Y^T Y)^-1 (Y^T V)
-            return V - Y @ np.linalg.solve(YtY, Y.T @ V)
+            # steps 2 and 10: V - Y (Y^T BY)^-1 ((BY)^T V)
+            return V - Y @ np.linalg.solve(YtBY, BY.T @ V)
         X0 = np.asfortranarray(constrain(X0))                  # step 2
     else:
         constrain = None
 
-    def rho_of(X, AX, lam):
-        Rr = AX - X * lam[None, :]
-        return np.linalg.norm(Rr, axis=0) / (normA * np.linalg.norm(X, axis=0)), Rr
+    def rho_of(X, AX, BX, lam):
+        Rr = AX - BX * lam[None, :]
+        return np.linalg.norm(Rr, axis=0) / (normA * np.linalg.norm(BX, axis=0)), Rr
 
-    # step 3: orthonormalise X, then AX = A X
+    # step 3: B-orthonormalise X, then AX = A X
     try:
-        (X,) = orthonormalize(X0)
+        X, BX = b_orthonormalize(X0, Bop(X0))
     except CholeskyFailure:
         return Result(status=ERR_CHOL, lam=None, X=None, hist=np.zeros((0, m)), iters=0, resid=None)
     AX = apply_A(X)
     # step 4: initial Ritz vectors from X^T A X
     H = X.T @ AX
     lam, Z = np.linalg.eigh(0.5 * (H + H.T))
-    X, AX = X @ Z, AX @ Z
+    X, AX, BX = X @ Z, AX @ Z, BX @ Z
     # step 5
     J = np.arange(m)
-    P = AP = None
+    P = AP = BP = None
     hist, status, k = [], NOT_CONVERGED, 0
     for k in range(maxit):                                     # step 6
-        rho, Rr = rho_of(X, AX, lam)                           # step 7 (all columns)
+        rho, Rr = rho_of(X, AX, BX, lam)                       # step 7 (all columns)
         hist.append(rho)
         if not np.all(np.isfinite(rho)):
             status = ERR_NONFINITE
@@ -138,7 +150,7 @@ def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactiva
         if constrain is not None:                              # step 10
             W = np.asfortranarray(constrain(W))
         try:                                                   # step 11
-            (W,) = orthonormalize(W)
+            W, BW = b_orthonormalize(W, Bop(W))
         except CholeskyFailure:
             status = ERR_CHOL
             break
@@ -146,7 +158,7 @@ def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactiva
         use_p = False
         if P is not None:                                      # steps 13-16
             try:
-                PJ, APJ = orthonormalize(P[:, J], AP[:, J])
+                PJ, BPJ, APJ = b_orthonormalize(P[:, J], BP[:, J], AP[:, J])
                 use_p = True
             except CholeskyFailure:
                 use_p = False
@@ -156,12 +168,12 @@ def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactiva
                 gramA = np.block([[np.diag(lam), X.T @ AW, X.T @ APJ],
                                   [AW.T @ X, W.T @ AW, W.T @ APJ],
                                   [APJ.T @ X, APJ.T @ W, PJ.T @ APJ]])
-                gramB = np.block([[np.eye(m), X.T @ W, X.T @ PJ],
-                                  [W.T @ X, np.eye(J.size), W.T @ PJ],
-                                  [PJ.T @ X, PJ.T @ W, np.eye(J.size)]])
+                gramB = np.block([[np.eye(m), X.T @ BW, X.T @ BPJ],
+                                  [BW.T @ X, np.eye(J.size), W.T @ BPJ],
+                                  [BPJ.T @ X, BPJ.T @ W, np.eye(J.size)]])
             else:                                              # steps 21-22
                 gramA = np.block([[np.diag(lam), X.T @ AW], [AW.T @ X, W.T @ AW]])
-                gramB = np.block([[np.eye(m), X.T @ W], [W.T @ X, np.eye(J.size)]])
+                gramB = np.block([[np.eye(m), X.T @ BW], [BW.T @ X, np.eye(J.size)]])
             # the lower blocks are the transposes of the upper ones
             gramA = np.triu(gramA) + np.triu(gramA, 1).T
             gramB = np.triu(gramB) + np.triu(gramB, 1).T
@@ -180,32 +192,38 @@ def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactiva
             CP = C[m + j:]
             P = W @ CW + PJ @ CP
             AP = AW @ CW + APJ @ CP
+            BP = BW @ CW + BPJ @ CP
         else:                                                  # steps 30-32
             P = W @ CW
             AP = AW @ CW
+            BP = BW @ CW
         X = X @ CX + P
         AX = AX @ CX + AP
+        BX = BX @ CX + BP
         lam = theta
     else:
         k = maxit
     iters = len(hist)
-    # explicit final residuals with a fresh A X
-    AXt = apply_A(X)
-    resid, _ = rho_of(X, AXt, lam)
+    # explicit final residuals with a fresh A X and B X
+    resid, _ = rho_of(X, apply_A(X), Bop(X), lam)
     return Result(status=status, lam=lam, X=X, hist=np.array(hist).reshape(-1, m), iters=iters,
                   resid=resid, J=J)
 
 
 def laplace7_solver(dims, m, X0, tol, maxit, levels=None, nu_pre=2, nu_post=2, coarse_sweeps=20,
-                    omega=2.0 / 3.0, callback=None, Y=None):
-    """LOBPCG on the 7-point Laplacian with optional V-cycle preconditioning
-    and optional constraints Y."""
+                    omega=2.0 / 3.0, callback=None, Y=None, bdiag=None):
+    """LOBPCG on the 7-point Laplacian with optional V-cycle preconditioning,
+    constraints Y and a positive diagonal B = diag(bdiag) (a lumped mass)."""
     from . import grid, mg
     A = lambda V: grid.laplace7(dims, V)
     T = None
     if levels:
         T = mg.VCycle(dims, levels, nu_pre, nu_post, coarse_sweeps, omega)
-    return lobpcg(A, X0, tol, maxit, grid.gershgorin_laplace7(), apply_T=T, callback=callback, Y=Y)
+    Bop = None
+    if bdiag is not None:
+        d = np.asarray(bdiag, dtype=np.float64).reshape(-1)
+        Bop = lambda V: d[:, None] * V
+    return lobpcg(A, X0, tol, maxit, grid.gershgorin_laplace7(), apply_T=T, callback=callback, Y=Y, apply_B=Bop)
 
 
 def varcoef_solver(dims, kx, ky, kz, m, X0, tol, maxit, levels=None, callback=None):

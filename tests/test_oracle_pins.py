@@ -475,3 +475,42 @@ def test_constraints_match_dense_projected_eigenproblem():
     assert r.status == lobpcg.OK
     np.testing.assert_allclose(r.lam, lam[[1, 3, 4]], rtol=1e-10)
     assert np.abs(Y.T @ r.X).max() < 1e-10
+
+
+# ---------------------------------------------------------------- B != I (general SPD B)
+
+def test_scalar_B_scales_the_spectrum():
+    """A x = lambda (c I) x: the eigenvalues are the closed form divided by c,
+    and X is B-orthonormal (X^T B X = I)."""
+    dims, m, c = (12, 10, 8), 4, 2.5
+    N = int(np.prod(dims))
+    lam, _ = closed_form.smallest(*dims, m)
+    r = lobpcg.laplace7_solver(dims, m, synth.x0_uniform(N, m, seed=3), 1e-10, 300, levels=2,
+                               bdiag=np.full(N, c))
+    assert r.status == lobpcg.OK
+    np.testing.assert_allclose(r.lam, lam / c, rtol=1e-9)
+    np.testing.assert_allclose(c * r.X.T @ r.X, np.eye(m), atol=1e-10)
+
+
+def test_diagonal_B_matches_dense_generalized_eigenproblem():
+    """Lumped-mass-like B = diag(d), d in [0.5, 2] (seeded): the eigenvalues of
+    the pencil (A, B) by brute force through the congruent standard problem
+    D^-1/2 A D^-1/2 (N = 72); X is B-orthonormal; with constraints Y spanning
+    B-eigenvectors 0 and 2 (randomly mixed) the next ones are 1, 3, 4."""
+    dims, m = (6, 4, 3), 3
+    N = int(np.prod(dims))
+    d = np.random.default_rng(13).uniform(0.5, 2.0, N)
+    A = dense_laplace7(*dims)
+    s = 1.0 / np.sqrt(d)
+    mu, Z = np.linalg.eigh(s[:, None] * A * s[None, :])
+    V = s[:, None] * Z                                  # B-orthonormal eigenvectors
+    assert np.all(np.diff(mu[:6]) > 1e-6)
+    r = lobpcg.laplace7_solver(dims, m, synth.x0_uniform(N, m, seed=5), 1e-11, 500, bdiag=d)
+    assert r.status == lobpcg.OK
+    np.testing.assert_allclose(r.lam, mu[:m], rtol=1e-10)
+    np.testing.assert_allclose(r.X.T @ (d[:, None] * r.X), np.eye(m), atol=1e-10)
+    Y = V[:, [0, 2]] @ np.random.default_rng(14).standard_normal((2, 2))
+    r = lobpcg.laplace7_solver(dims, m, synth.x0_uniform(N, m, seed=6), 1e-11, 500, bdiag=d, Y=Y)
+    assert r.status == lobpcg.OK
+    np.testing.assert_allclose(r.lam, mu[[1, 3, 4]], rtol=1e-10)
+    assert np.abs(Y.T @ (d[:, None] * r.X)).max() < 1e-10
