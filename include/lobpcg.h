@@ -38,7 +38,7 @@ enum {
     LOBPCG_OK = 0,              /* converged: every residual norm <= tol            */
     LOBPCG_NOT_CONVERGED = 1,   /* maxit reached; outputs hold the last iterate     */
     LOBPCG_ERR_ARG = -1,        /* bad dimension, pointer, tolerance or mismatch    */
-    LOBPCG_ERR_UNSUPPORTED = -2,/* B other than the identity                        */
+    LOBPCG_ERR_UNSUPPORTED = -2,/* a combination this version does not provide      */
     LOBPCG_ERR_WORKSPACE = -3,  /* workspace too small or misaligned               */
     LOBPCG_ERR_CHOL = -4,       /* Cholesky of X0^T X0 or W^T W failed (steps 3, 11)*/
     LOBPCG_ERR_RR = -5,         /* Rayleigh-Ritz failed even without P (step 24)    */
@@ -47,7 +47,7 @@ enum {
 };
 
 /* ---------------------------------------------------------------- descriptors */
-enum { LOBPCG_OP_LAPLACE7 = 0, LOBPCG_OP_VARCOEF7 = 1 };
+enum { LOBPCG_OP_LAPLACE7 = 0, LOBPCG_OP_VARCOEF7 = 1, LOBPCG_OP_DIAG = 2 };
 enum { LOBPCG_PC_NONE = 0, LOBPCG_PC_GMG_V = 1 };
 enum { LOBPCG_FP64 = 0, LOBPCG_MIXED = 1 };     /* solver precision           */
 enum { LOBPCG_F64 = 0, LOBPCG_F32 = 1 };        /* element type of one block  */
@@ -63,6 +63,8 @@ typedef struct lobpcg_op {
     int nx, ny, nz;
     int kind;
     const double *kx, *ky, *kz;     /* VARCOEF7 only, else NULL */
+    const double *diag;             /* DIAG only: N positive FP64 entries (device), */
+                                    /* B = diag(diag), e.g. a lumped mass matrix    */
 } lobpcg_op;
 
 /* Preconditioner T (Section 2.1.1 requires it linear, symmetric, positive
@@ -84,8 +86,9 @@ typedef struct lobpcg_ctx lobpcg_ctx;   /* opaque */
 /* ---------------------------------------------------------------- solver */
 
 /* Device workspace needed by lobpcg_setup for this problem, in bytes.
- * B must be NULL (B = I).  m: block size, 1 <= m and 3m <= N.  Pure host
- * code: callable without a GPU. */
+ * B: NULL (B = I) or a DIAG operator of A's dimensions (A x = lambda B x,
+ * Section 2.1.1; FP64 precision only, else ERR_UNSUPPORTED).  m: block
+ * size, 1 <= m and 3m <= N.  Pure host code: callable without a GPU. */
 int lobpcg_workspace_bytes(const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T,
                            int m, int precision, size_t *bytes);
 
@@ -95,8 +98,11 @@ int lobpcg_workspace_bytes(const lobpcg_op *A, const lobpcg_op *B, const lobpcg_
 int lobpcg_setup(lobpcg_ctx **ctx, const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T,
                  int m, int precision, void *d_workspace, size_t ws_bytes, void *stream);
 
-/* Solve for the m smallest eigenpairs (Section 2.2, steps 1-37, B = I, no
- * constraints; see lobpcg_solve_constrained for steps 2 and 10).  A must have the dimensions and kind given to setup (its
+/* Solve for the m smallest eigenpairs (Section 2.2, steps 1-37, no
+ * constraints; see lobpcg_solve_constrained for steps 2 and 10).  B must be
+ * NULL or the DIAG operator given to setup (its array may differ between
+ * calls); with B, X is B-orthonormal and rho_j = ||A x_j - lambda_j B x_j|| /
+ * (||A|| ||B x_j||) (for B = I the definition below).  A must have the dimensions and kind given to setup (its
  * face arrays may differ between calls); T must equal setup's.
  *   d_X0         N x m FP64 start block (linearly independent columns)
  *   tol          stop when every rho_j = ||A x_j - lambda_j x_j|| / (||A|| ||x_j||)

@@ -190,6 +190,33 @@ hipError_t launch_cast(int from, int to, long long n, const void *src, void *dst
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- diagonal B
+
+// one thread per row: the row's k entries scaled by d[p]
+template <typename T>
+__global__ void __launch_bounds__(256) diag_scale_kernel(i64 N, int k, const double *__restrict__ d,
+                                                         const T *__restrict__ in, T *__restrict__ out)
+{
+    for (i64 p = (i64)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (i64)gridDim.x * blockDim.x) {
+        const double s = d[p];
+        for (int j = 0; j < k; j++) out[p * k + j] = (T)(s * (double)in[p * k + j]);
+    }
+}
+
+hipError_t launch_diag_scale(int dtype, long long N, int k, const double *d, const void *in, void *out,
+                             hipStream_t st)
+{
+    if (N == 0) return hipSuccess;
+    const unsigned nb = stride_blocks(N, 16384);
+    if (dtype == DT_F32)
+        hipLaunchKernelGGL(diag_scale_kernel<float>, dim3(nb), dim3(256), 0, st, (i64)N, k, d, (const float *)in,
+                           (float *)out);
+    else
+        hipLaunchKernelGGL(diag_scale_kernel<double>, dim3(nb), dim3(256), 0, st, (i64)N, k, d, (const double *)in,
+                           (double *)out);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- eigenvalue adjoint
 
 // For each face f between grid points p and q (q beyond the boundary counts

@@ -101,6 +101,10 @@ hipError_t launch_residual(int dtype, const ResidualArgs &a, hipStream_t st);
 
 hipError_t launch_cast(int from, int to, long long n, const void *src, void *dst, hipStream_t st);
 
+// out[p][j] = d[p] in[p][j] for an N x k block (B = diag(d) applied to a block)
+hipError_t launch_diag_scale(int dtype, long long N, int k, const double *d, const void *in, void *out,
+                             hipStream_t st);
+
 // d lambda_i / d k_f accumulation over faces (FP64), w[i] = gbar_i / (x_i, x_i)
 hipError_t launch_eig_grad(const Grid3 &g, int m, const double *X, const double *w, double *gkx, double *gky,
                            double *gkz, hipStream_t st);
@@ -112,7 +116,7 @@ hipError_t launch_eig_grad(const Grid3 &g, int m, const double *X, const double 
 // (rows 16 ta..16 ta+15 of Lm^T Rm, columns 16 tb..16 tb+15; sorted by ta)
 // are written to out[t][e], e = r*64 + lane of the MFMA accumulator layout
 // (row 16 ta + Mfma<T>::row(lane, r), column 16 tb + lane % 16).
-static const int GX_MAX_ARR = 6;
+static const int GX_MAX_ARR = 9;
 static const int GX_MAX_L = 96;
 static const int GX_MAX_R = 192;
 static const int GX_MAX_TILES = 64;

@@ -39,10 +39,12 @@ struct Blocks {
     void *P, *AP;         // directions of all m columns, as produced by steps 27/31
     void *PJ, *APJ;       // orthonormalised active directions (packed)
     void *T0;             // multigrid fine-level scratch
+    void *BX[2], *BW, *BP, *BPJ;   // B X, B W, B P and a spare, when B is not the identity
 };
 
 struct Layout {
     size_t blocks64, blocks32;          // offsets (or SIZE_MAX if absent)
+    size_t blocksB;                     // the five FP64 B-blocks (or SIZE_MAX)
     std::vector<size_t> mg;             // per level l >= 1: x, b, t (3 entries each)
     size_t lambda, jpos, cols, coef, gram_out, gram_part, res_part, mv_part, res_out, wvec;
     size_t total;
@@ -62,8 +64,13 @@ bool op_ok(const lobpcg_op *A)
 int check_common(const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T, int m, int precision)
 {
     if (!op_ok(A)) return LOBPCG_ERR_ARG;
-    if (B) return LOBPCG_ERR_UNSUPPORTED;
     if (precision != LOBPCG_FP64 && precision != LOBPCG_MIXED) return LOBPCG_ERR_ARG;
+    if (B) {
+        // B = diag(d): a positive diagonal of A's grid, FP64 solver only
+        if (B->kind != LOBPCG_OP_DIAG || !B->diag || B->nx != A->nx || B->ny != A->ny || B->nz != A->nz)
+            return LOBPCG_ERR_ARG;
+        if (precision != LOBPCG_FP64) return LOBPCG_ERR_UNSUPPORTED;
+    }
     const long long N = (long long)A->nx * A->ny * A->nz;
     if (m < 1 || m > LOBPCG_MAX_M || 3LL * m > N) return LOBPCG_ERR_ARG;
     if (T) {
@@ -85,7 +92,7 @@ int check_common(const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T
 
 bool has_mg(const lobpcg_precond *T) { return T && T->kind == LOBPCG_PC_GMG_V; }
 
-Layout make_layout(const lobpcg_op *A, const lobpcg_precond *T, int m, int precision)
+Layout make_layout(const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T, int m, int precision)
 {
     Layout L;
     const long long N = (long long)A->nx * A->ny * A->nz;
@@ -97,6 +104,7 @@ Layout make_layout(const lobpcg_op *A, const lobpcg_precond *T, int m, int preci
     };
     L.blocks64 = take(11 * (size_t)N * m * 8);
     L.blocks32 = precision == LOBPCG_MIXED ? take(11 * (size_t)N * m * 4) : (size_t)-1;
+    L.blocksB = B ? take(5 * (size_t)N * m * 8) : (size_t)-1;
     L.mg_dtype = precision == LOBPCG_MIXED ? DT_F32 : DT_F64;
     L.levels.push_back(Grid3{A->nx, A->ny, A->nz});
     if (has_mg(T)) {
@@ -157,6 +165,8 @@ struct lobpcg_ctx {
     int mv_variant, gram_staged, gram_nt4;  // kernel variants (see LOBPCG_OPT_KERNELS)
     bool fp32_explicit;           // FP32 phase: Gram diagonal blocks computed, not assumed
     bool fold;                    // Cholesky-QR factors of W_J, P_J folded into Gram and coefficients
+    bool hasB;                    // A x = lambda B x with B = diag (FP64 only)
+    lobpcg_op Bop;
     const double *Y;              // constraints of the current solve (FP64, N x ny) or null
     int ny;
     std::vector<double> RY;       // Y^T Y = RY^T RY (upper, ny x ny)
@@ -180,6 +190,7 @@ Blocks carve_blocks(char *base, long long N, int m, int dt)
     const size_t bs = (size_t)N * m * esize(dt);
     void **slots[11] = {&b.X[0], &b.X[1], &b.AX[0], &b.AX[1], &b.W, &b.AW, &b.P, &b.AP, &b.PJ, &b.APJ, &b.T0};
     for (int i = 0; i < 11; i++) *slots[i] = base + i * bs;
+    b.BX[0] = b.BX[1] = b.BW = b.BP = b.BPJ = nullptr;
     return b;
 }
 
@@ -265,6 +276,16 @@ int upload_cols(lobpcg_ctx *c, const std::vector<int> &cols, const int **dptr)
 
 // ---- kernel-level building blocks (asynchronous unless they return host data)
 
+// B applied to an N x k FP64 block (B = diag(d))
+int apply_B(lobpcg_ctx *c, const void *in, void *out, int k, int step)
+{
+    prof_begin(c, step);
+    hipError_t e = launch_diag_scale(DT_F64, c->N, k, c->Bop.diag, in, out, c->st);
+    prof_end(c);
+    add_bytes(c, step, (2.0 * k + 1.0) * c->N * 8.0);
+    return e == hipSuccess ? LOBPCG_OK : LOBPCG_ERR_HIP;
+}
+
 int apply_A(lobpcg_ctx *c, const lobpcg_op *A, int dt, const void *in, void *out, int k)
 {
     prof_begin(c, LOBPCG_STEP_APPLY_A);
@@ -293,7 +314,8 @@ int apply_A(lobpcg_ctx *c, const lobpcg_op *A, int dt, const void *in, void *out
 // Entries (i, j) with i <= j are computed and mirrored.
 int gram(lobpcg_ctx *c, int dt, int n, const void *const *S, const void *const *AS, const int *w,
          std::vector<double> &SS, std::vector<double> *SAS, int step, bool paper = false,
-         const int *const *cols = nullptr, const int *ld = nullptr, bool diag_blocks = false)
+         const int *const *cols = nullptr, const int *ld = nullptr, bool diag_blocks = false,
+         const void *const *BS = nullptr)
 {
     int K = 0;
     std::vector<int> blk, col, off(n + 1, 0);
@@ -306,7 +328,7 @@ int gram(lobpcg_ctx *c, int dt, int n, const void *const *S, const void *const *
         plain = plain && !sel && (!ld || ld[b] == w[b]);
     }
     double *h = (double *)(c->h_pin + c->h_gram_off);
-    if (!AS && n == 1 && w[0] <= 8 && plain && !c->gram_staged) {
+    if (!AS && !BS && n == 1 && w[0] <= 8 && plain && !c->gram_staged) {
         // one narrow block: one grid row per thread
         prof_begin(c, step);
         hipError_t e = launch_gram_rows(dt, S[0], w[0], c->N, c->d_gram_part, c->d_gram_out, w[0], c->st);
@@ -328,7 +350,10 @@ int gram(lobpcg_ctx *c, int dt, int n, const void *const *S, const void *const *
         const int l = ld ? ld[b] : w[b];
         a.arr[b] = S[b], a.ld[b] = l;
         if (AS) a.arr[3 + b] = AS[b], a.ld[3 + b] = l;
+        if (BS) a.arr[6 + b] = BS[b], a.ld[6 + b] = l;
     }
+    // with BS the "S^T S" products are S^T BS: Rm takes those columns from BS
+    const int sb = BS ? 6 : 0;
     // Lm = S; Rm as above.  rs[j] / ra[j]: column of Rm holding S_j / AS_j (-1: none)
     a.KL = K;
     for (int i = 0; i < K; i++) a.lmap[i] = (unsigned short)((blk[i] << 8) | col[i]);
@@ -339,16 +364,16 @@ int gram(lobpcg_ctx *c, int dt, int n, const void *const *S, const void *const *
         a.rmap[KR++] = (unsigned short)((arr << 8) | col[i]);
     };
     if (pform) {
-        for (int i = w[0]; i < K; i++) addr(blk[i], i, rs);
+        for (int i = w[0]; i < K; i++) addr(sb + blk[i], i, rs);
         for (int i = w[0]; i < K; i++) addr(3 + blk[i], i, ra);
     } else if (AS && n > 1) {
         // [S_0 AS_0 | S_1.. AS_1..]: the thin blocks share 16-column tiles
-        for (int i = 0; i < w[0]; i++) addr(0, i, rs);
+        for (int i = 0; i < w[0]; i++) addr(sb, i, rs);
         for (int i = 0; i < w[0]; i++) addr(3, i, ra);
-        for (int i = w[0]; i < K; i++) addr(blk[i], i, rs);
+        for (int i = w[0]; i < K; i++) addr(sb + blk[i], i, rs);
         for (int i = w[0]; i < K; i++) addr(3 + blk[i], i, ra);
     } else {
-        for (int i = 0; i < K; i++) addr(blk[i], i, rs);
+        for (int i = 0; i < K; i++) addr(sb + blk[i], i, rs);
         if (AS)
             for (int i = 0; i < K; i++) addr(3 + blk[i], i, ra);
     }
@@ -763,9 +788,14 @@ int folded_step(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState
         std::swap(B.W, B.AW);
     else if (Wt == B.T0)
         std::swap(B.W, B.T0);
-    // step 12: A W_J
+    // step 12: A W_J (and B W_J)
     s = apply_A(c, A, dt, B.W, B.AW, nJ);
     if (s) return s;
+    const bool hb = c->hasB;
+    if (hb) {
+        s = apply_B(c, B.W, B.BW, nJ, LOBPCG_STEP_APPLY_A);
+        if (s) return s;
+    }
     // P_J: the active columns that have a direction, read in place from B.P
     std::vector<int> ppos;
     for (int j : ps.J) {
@@ -779,9 +809,11 @@ int folded_step(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState
     {
         const void *Sb[3] = {B.X[ps.cur], B.W, B.P};
         const void *ASb[3] = {B.AX[ps.cur], B.AW, B.AP};
+        const void *BSb[3] = {B.BX[ps.cur], B.BW, B.BP};
         int wb[3] = {m, nJ, nP}, ldb[3] = {m, nJ, np};
         const int *cl[3] = {nullptr, nullptr, nP ? ppos.data() : nullptr};
-        s = gram(c, dt, nP ? 3 : 2, Sb, ASb, wb, SS, &SAS, LOBPCG_STEP_GRAM, !explicit_gram, cl, ldb, true);
+        s = gram(c, dt, nP ? 3 : 2, Sb, ASb, wb, SS, &SAS, LOBPCG_STEP_GRAM, !explicit_gram, cl, ldb, true,
+                 hb ? BSb : nullptr);
         if (s) return s;
         if (!all_finite(SS) || !all_finite(SAS)) return LOBPCG_ERR_NONFINITE;
     }
@@ -920,15 +952,35 @@ int folded_step(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState
     if (s) return s;
     MV q;
     q.nside = 2;
-    q.input(0, B.X[ps.cur], B.AX[ps.cur], m, m);
-    q.input(1, B.W, B.AW, nJ, nJ);
-    if (nP) q.input(2, B.P, B.AP, np, nP, dppos);
+    if (hb) {
+        // three sides: X alone, then B X and A X with the residual W = AX' - BX' Theta
+        MV qx;
+        qx.input(0, B.X[ps.cur], nullptr, m, m);
+        qx.input(1, B.W, nullptr, nJ, nJ);
+        if (nP) qx.input(2, B.P, nullptr, np, nP, dppos);
+        qx.kout = m;
+        qx.out[0] = B.PJ;
+        qx.opos = djpos;
+        qx.nout = nJ;
+        qx.out2[0] = B.X[1 - ps.cur];
+        s = mv(c, dt, qx, C.data(), LOBPCG_STEP_UPDATE);
+        if (s) return s;
+        q.input(0, B.BX[ps.cur], B.AX[ps.cur], m, m);
+        q.input(1, B.BW, B.AW, nJ, nJ);
+        if (nP) q.input(2, B.BP, B.AP, np, nP, dppos);
+        q.out[0] = B.BPJ;
+        q.out2[0] = B.BX[1 - ps.cur];
+    } else {
+        q.input(0, B.X[ps.cur], B.AX[ps.cur], m, m);
+        q.input(1, B.W, B.AW, nJ, nJ);
+        if (nP) q.input(2, B.P, B.AP, np, nP, dppos);
+        q.out[0] = B.PJ;
+        q.out2[0] = B.X[1 - ps.cur];
+    }
     q.kout = m;
-    q.out[0] = B.PJ;
     q.out[1] = B.APJ;
     q.opos = djpos;
     q.nout = nJ;
-    q.out2[0] = B.X[1 - ps.cur];
     q.out2[1] = B.AX[1 - ps.cur];
     q.resid = true;
     q.theta = dtheta;
@@ -939,6 +991,7 @@ int folded_step(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState
     if (s) return s;
     std::swap(B.P, B.PJ);
     std::swap(B.AP, B.APJ);
+    if (hb) std::swap(B.BP, B.BPJ);
     std::swap(B.W, B.T0);
     ps.Pcols = ps.J;
     ps.cur = 1 - ps.cur;
@@ -966,7 +1019,7 @@ int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &
             rr.assign(h, h + m);
             xx.assign(h + m, h + 2 * m);
         } else {
-            s = residual(c, dt, B.X[ps.cur], B.AX[ps.cur], ps.lam, ps.J, B.W, rr, xx);
+            s = residual(c, dt, c->hasB ? B.BX[ps.cur] : B.X[ps.cur], B.AX[ps.cur], ps.lam, ps.J, B.W, rr, xx);
             if (s) return s;
         }
         ps.have_res = false;
@@ -1016,7 +1069,7 @@ int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &
             } else {
                 // columns made active again: form W for the new set
                 ps.J = Jn;
-                s = residual(c, dt, B.X[ps.cur], B.AX[ps.cur], ps.lam, ps.J, B.W, rr, xx);
+                s = residual(c, dt, c->hasB ? B.BX[ps.cur] : B.X[ps.cur], B.AX[ps.cur], ps.lam, ps.J, B.W, rr, xx);
                 if (s) return s;
             }
         }
@@ -1209,16 +1262,30 @@ int init_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState 
     const int m = c->m;
     std::vector<double> SS, SAS;
     int s;
+    const bool hb = c->hasB;
     if (ortho) {
+        // step 3: R = chol(X^T B X), X = X R^-1 (and B X = B X R^-1)
         const void *Sb[1] = {B.X[ps.cur]};
+        const void *BSb[1] = {hb ? B.BX[ps.cur] : nullptr};
         int w1[1] = {m};
-        s = gram(c, dt, 1, Sb, nullptr, w1, SS, nullptr, LOBPCG_STEP_ORTHO);
+        if (hb) {
+            s = apply_B(c, B.X[ps.cur], B.BX[ps.cur], m, LOBPCG_STEP_ORTHO);
+            if (s) return s;
+        }
+        s = gram(c, dt, 1, Sb, nullptr, w1, SS, nullptr, LOBPCG_STEP_ORTHO, false, nullptr, nullptr, false,
+                 hb ? BSb : nullptr);
         if (s) return s;
         if (!all_finite(SS)) return LOBPCG_ERR_NONFINITE;
         std::vector<double> Ri;
         if (!chol_inv(m, SS, Ri)) return LOBPCG_ERR_CHOL;
         MV q;
-        q.input(0, B.X[ps.cur], nullptr, m, m);
+        if (hb) {
+            q.nside = 2;
+            q.input(0, B.X[ps.cur], B.BX[ps.cur], m, m);
+            q.out[1] = B.BX[1 - ps.cur];
+        } else {
+            q.input(0, B.X[ps.cur], nullptr, m, m);
+        }
         q.kout = m;
         q.out[0] = B.X[1 - ps.cur];
         s = mv(c, dt, q, Ri.data(), LOBPCG_STEP_ORTHO);
@@ -1246,6 +1313,14 @@ int init_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState 
     q.out[1] = B.AX[1 - ps.cur];
     s = mv(c, dt, q, Z.data(), LOBPCG_STEP_OTHER);
     if (s) return s;
+    if (hb) {
+        MV qb;
+        qb.input(0, B.BX[ps.cur], nullptr, m, m);
+        qb.kout = m;
+        qb.out[0] = B.BX[1 - ps.cur];
+        s = mv(c, dt, qb, Z.data(), LOBPCG_STEP_OTHER);
+        if (s) return s;
+    }
     ps.cur = 1 - ps.cur;
     ps.lam = theta;
     ps.J.clear();
@@ -1282,7 +1357,7 @@ int lobpcg_workspace_bytes(const lobpcg_op *A, const lobpcg_op *B, const lobpcg_
     if (!bytes) return LOBPCG_ERR_ARG;
     int s = check_common(A, B, T, m, precision);
     if (s) return s;
-    *bytes = make_layout(A, T, m, precision).total;
+    *bytes = make_layout(A, B, T, m, precision).total;
     return LOBPCG_OK;
 }
 
@@ -1293,7 +1368,7 @@ int lobpcg_setup(lobpcg_ctx **out, const lobpcg_op *A, const lobpcg_op *B, const
     *out = nullptr;
     int s = check_common(A, B, T, m, precision);
     if (s) return s;
-    Layout L = make_layout(A, T, m, precision);
+    Layout L = make_layout(A, B, T, m, precision);
     if (!d_workspace || ws_bytes < L.total || ((uintptr_t)d_workspace % ALIGN)) return LOBPCG_ERR_WORKSPACE;
     lobpcg_ctx *c = new lobpcg_ctx();
     c->g = Grid3{A->nx, A->ny, A->nz};
@@ -1308,6 +1383,14 @@ int lobpcg_setup(lobpcg_ctx **out, const lobpcg_op *A, const lobpcg_op *B, const
     c->ws = (char *)d_workspace;
     c->L = L;
     c->b64 = carve_blocks(c->ws + L.blocks64, c->N, m, DT_F64);
+    c->hasB = B != nullptr;
+    if (B) {
+        c->Bop = *B;
+        const size_t bs = (size_t)c->N * m * 8;
+        char *bb = c->ws + L.blocksB;
+        c->b64.BX[0] = bb, c->b64.BX[1] = bb + bs, c->b64.BW = bb + 2 * bs, c->b64.BP = bb + 3 * bs;
+        c->b64.BPJ = bb + 4 * bs;
+    }
     if (precision == LOBPCG_MIXED) c->b32 = carve_blocks(c->ws + L.blocks32, c->N, m, DT_F32);
     else memset(&c->b32, 0, sizeof(c->b32));
     c->mgx.assign(L.levels.size(), nullptr);
@@ -1434,12 +1517,19 @@ static int solve_impl(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, con
                       double *d_X, double *h_hist, int *h_iters, double *h_final_resid)
 {
     if (!c) return LOBPCG_ERR_ARG;
-    if (B) return LOBPCG_ERR_UNSUPPORTED;
     if (!same_op(c, A) || !same_precond(c, T) || m != c->m || !d_X0 || !d_X || !h_lambda || !h_iters ||
         !(tol > 0) || maxit < 0)
         return LOBPCG_ERR_ARG;
+    if ((B != nullptr) != c->hasB) return LOBPCG_ERR_ARG;
+    if (B) {
+        if (B->kind != LOBPCG_OP_DIAG || !B->diag || B->nx != c->g.nx || B->ny != c->g.ny || B->nz != c->g.nz)
+            return LOBPCG_ERR_ARG;
+        c->Bop = *B;
+    }
     if (ny < 0 || ny > LOBPCG_MAX_M || (ny > 0 && !d_Y) || 3LL * m + ny > c->N) return LOBPCG_ERR_ARG;
     if (ny > 0 && c->precision != LOBPCG_FP64) return LOBPCG_ERR_UNSUPPORTED;
+    // B != I: the folded form only, without constraints
+    if (B && (ny > 0 || !c->fold)) return LOBPCG_ERR_UNSUPPORTED;
     auto t0 = std::chrono::steady_clock::now();
     memset(&c->stats, 0, sizeof(c->stats));
     c->ev_used = 0;
@@ -1520,9 +1610,15 @@ static int solve_impl(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, con
     if (h_final_resid) {
         s = apply_A(c, A, DT_F64, c->b64.X[ps.cur], c->b64.AW, m);
         if (s) return s;
+        const void *BXf = c->b64.X[ps.cur];
+        if (c->hasB) {
+            s = apply_B(c, c->b64.X[ps.cur], c->b64.BW, m, LOBPCG_STEP_OTHER);
+            if (s) return s;
+            BXf = c->b64.BW;
+        }
         std::vector<double> rr, xx;
         std::vector<int> none;
-        s = residual(c, DT_F64, c->b64.X[ps.cur], c->b64.AW, ps.lam, none, nullptr, rr, xx);
+        s = residual(c, DT_F64, BXf, c->b64.AW, ps.lam, none, nullptr, rr, xx);
         if (s) return s;
         for (int j = 0; j < m; j++) h_final_resid[j] = std::sqrt(rr[j]) / (normA * std::sqrt(xx[j]));
     }
@@ -1552,6 +1648,7 @@ int lobpcg_eig_grad_k(lobpcg_ctx *c, const double *d_X, const double *h_gbar, in
                       double *gkz)
 {
     if (!c || !d_X || !h_gbar || !gkx || !gky || !gkz || m < 1 || m > c->m) return LOBPCG_ERR_ARG;
+    if (c->hasB) return LOBPCG_ERR_UNSUPPORTED;
     // column norms (x_i, x_i) through the residual kernel with AX = X and
     // lambda = 0; it works on blocks of the context's width, so a narrower X
     // is first copied into zero-padded scratch

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "liblobpcg.so")
 
 OK, NOT_CONVERGED = 0, 1
 ERR_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_CHOL, ERR_RR, ERR_NONFINITE, ERR_HIP = -1, -2, -3, -4, -5, -6, -7
-OP_LAPLACE7, OP_VARCOEF7 = 0, 1
+OP_LAPLACE7, OP_VARCOEF7, OP_DIAG = 0, 1, 2
 PC_NONE, PC_GMG_V = 0, 1
 FP64, MIXED = 0, 1
 F64, F32 = 0, 1
@@ -35,7 +35,8 @@ class LobpcgError(RuntimeError):
 
 class _Op(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("kind", ctypes.c_int),
-                ("kx", ctypes.c_void_p), ("ky", ctypes.c_void_p), ("kz", ctypes.c_void_p)]
+                ("kx", ctypes.c_void_p), ("ky", ctypes.c_void_p), ("kz", ctypes.c_void_p),
+                ("diag", ctypes.c_void_p)]
 
 
 class _Precond(ctypes.Structure):
@@ -131,10 +132,26 @@ class Op:
         return self.dims[0] * self.dims[1] * self.dims[2]
 
     def c(self):
-        o = _Op(*self.dims, OP_LAPLACE7 if self.k is None else OP_VARCOEF7, None, None, None)
+        o = _Op(*self.dims, OP_LAPLACE7 if self.k is None else OP_VARCOEF7, None, None, None, None)
         if self.k is not None:
             o.kx, o.ky, o.kz = (t.data_ptr() for t in self.k)
         return o
+
+
+class Diag:
+    """B = diag(d) for A x = lambda B x: d an (N,) positive float64 device
+    tensor on the grid of A (e.g. a lumped mass matrix)."""
+
+    def __init__(self, nx, ny, nz, d):
+        self.dims = (int(nx), int(ny), int(nz))
+        if not isinstance(d, torch.Tensor) or d.dtype != torch.float64 or not d.is_cuda:
+            raise ValueError("the diagonal must be a float64 device tensor")
+        if d.numel() != self.dims[0] * self.dims[1] * self.dims[2]:
+            raise ValueError("the diagonal must have N entries")
+        self.d = d.contiguous()
+
+    def c(self):
+        return _Op(*self.dims, OP_DIAG, None, None, None, self.d.data_ptr())
 
 
 class Precond:
@@ -150,25 +167,29 @@ class Precond:
         return _Precond(PC_GMG_V, self.levels, self.nu_pre, self.nu_post, self.coarse_sweeps, self.omega)
 
 
-def lobpcg_workspace_bytes(A, T, m, precision):
+def _bref(B):
+    return ctypes.byref(B.c()) if B is not None else None
+
+
+def lobpcg_workspace_bytes(A, T, m, precision, B=None):
     n = ctypes.c_size_t(0)
-    _check(lib().lobpcg_workspace_bytes(ctypes.byref(A.c()), None, ctypes.byref(T.c()), int(m), int(precision),
-                                        ctypes.byref(n)), "lobpcg_workspace_bytes")
+    _check(lib().lobpcg_workspace_bytes(ctypes.byref(A.c()), _bref(B), ctypes.byref(T.c()), int(m),
+                                        int(precision), ctypes.byref(n)), "lobpcg_workspace_bytes")
     return n.value
 
 
 class Context:
     """A solver context with its device workspace (a uint8 tensor it owns)."""
 
-    def __init__(self, A, T, m, precision, device="cuda", stream=None):
-        self.A, self.T, self.m, self.precision = A, T, int(m), int(precision)
-        nbytes = lobpcg_workspace_bytes(A, T, m, precision)
+    def __init__(self, A, T, m, precision, device="cuda", stream=None, B=None):
+        self.A, self.T, self.m, self.precision, self.B = A, T, int(m), int(precision), B
+        nbytes = lobpcg_workspace_bytes(A, T, m, precision, B)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         base = self.workspace.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         self.h = ctypes.c_void_p()
-        _check(lib().lobpcg_setup(ctypes.byref(self.h), ctypes.byref(A.c()), None, ctypes.byref(T.c()), self.m,
+        _check(lib().lobpcg_setup(ctypes.byref(self.h), ctypes.byref(A.c()), _bref(B), ctypes.byref(T.c()), self.m,
                                   self.precision, ctypes.c_void_p(self._ws_ptr), ctypes.c_size_t(nbytes),
                                   ctypes.c_void_p(self.stream.cuda_stream)), "lobpcg_setup")
 
@@ -183,8 +204,9 @@ class Context:
         return self.A.N
 
 
-def lobpcg_setup(A, T, m, precision=FP64, device="cuda", stream=None):
-    return Context(A, T, m, precision, device, stream)
+def lobpcg_setup(A, T, m, precision=FP64, device="cuda", stream=None, B=None):
+    """Context for A x = lambda x, or A x = lambda B x with B a Diag (FP64)."""
+    return Context(A, T, m, precision, device, stream, B)
 
 
 def lobpcg_set_option(ctx, key, value):
@@ -221,11 +243,11 @@ def lobpcg_solve(ctx, X0, tol, maxit, A=None, hist=True, raise_on_error=True, Y=
     tail = (m, float(tol), int(maxit), _np_ptr(lam), _ptr(X), _np_ptr(H) if hist else None, ctypes.byref(iters),
             _np_ptr(res))
     if Y is None:
-        s = lib().lobpcg_solve(ctx.h, ctypes.byref(A.c()), None, ctypes.byref(ctx.T.c()), _ptr(X0), *tail)
+        s = lib().lobpcg_solve(ctx.h, ctypes.byref(A.c()), _bref(ctx.B), ctypes.byref(ctx.T.c()), _ptr(X0), *tail)
     else:
         Y = _blk(ctx, Y, "Y", dtype=torch.float64)
-        s = lib().lobpcg_solve_constrained(ctx.h, ctypes.byref(A.c()), None, ctypes.byref(ctx.T.c()), _ptr(Y),
-                                           int(Y.shape[1]), _ptr(X0), *tail)
+        s = lib().lobpcg_solve_constrained(ctx.h, ctypes.byref(A.c()), _bref(ctx.B), ctypes.byref(ctx.T.c()),
+                                           _ptr(Y), int(Y.shape[1]), _ptr(X0), *tail)
     if raise_on_error:
         _check(s, "lobpcg_solve", allow=(OK, NOT_CONVERGED))
     return SolveResult(status=s, lam=lam, X=X, hist=H[:iters.value] if hist else None, iters=iters.value,

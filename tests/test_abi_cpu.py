@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "lobpcg.h")
 
 L = pytest.importorskip("paper_0705_2626_amd")
-from paper_0705_2626_amd.lobpcg import _Precond as PC  # noqa: E402
+from paper_0705_2626_amd.lobpcg import _Op, _Precond as PC  # noqa: E402
 
 
 def declared_functions():
@@ -70,10 +70,19 @@ def test_workspace_bytes_rejects_bad_arguments(dims, levels, m, prec, want):
     assert s == want
 
 
-def test_general_B_is_unsupported():
-    B = L.Op(8, 8, 8).c()
-    s, _ = ws((8, 8, 8), None, 2, 0, B=B)
-    assert s == L.ERR_UNSUPPORTED
+def test_B_must_be_a_positive_diagonal_of_the_grid():
+    """B: a DIAG descriptor of A's grid (FP64 solver); its array is not read
+    by the workspace query, so a placeholder address is enough here."""
+    fake = 256
+    diag = _Op(8, 8, 8, L.OP_DIAG, None, None, None, fake)
+    s0, n0 = ws((8, 8, 8), None, 2, L.FP64)
+    s, n = ws((8, 8, 8), None, 2, L.FP64, B=diag)
+    assert s == s0 == L.OK
+    assert n - n0 >= 5 * 512 * 2 * 8                 # B X (twice), B W, B P and a spare
+    assert ws((8, 8, 8), None, 2, L.MIXED, B=diag)[0] == L.ERR_UNSUPPORTED
+    assert ws((8, 8, 8), None, 2, L.FP64, B=L.Op(8, 8, 8).c())[0] == L.ERR_ARG          # not a diagonal
+    assert ws((8, 8, 8), None, 2, L.FP64, B=_Op(8, 8, 4, L.OP_DIAG, None, None, None, fake))[0] == L.ERR_ARG
+    assert ws((8, 8, 8), None, 2, L.FP64, B=_Op(8, 8, 8, L.OP_DIAG, None, None, None, None))[0] == L.ERR_ARG
 
 
 def test_setup_rejects_small_or_missing_workspace():

@@ -310,3 +310,51 @@ def test_constraints_error_paths():
     assert r.status == L.ERR_ARG          # rank-deficient constraints
     r = L.lobpcg_solve(ctx, X0, 1e-8, 10, Y=dev(synth.random_block(N, 33, seed=2)), raise_on_error=False)
     assert r.status == L.ERR_ARG          # more than 32 constraint vectors
+
+
+# ---------------------------------------------------------------- B != I (a positive diagonal)
+
+def lumped_mass(N, seed):
+    return np.random.default_rng(seed).uniform(0.5, 2.0, N)
+
+
+def test_diagonal_B_matches_oracle():
+    """A x = lambda B x with a seeded lumped-mass-like B = diag(d): GPU and
+    oracle agree, X is B-orthonormal, every explicit residual <= tol."""
+    dims, m, levels, tol = (20, 18, 16), 6, 3, 1e-9
+    N = int(np.prod(dims))
+    d = lumped_mass(N, 21)
+    X0 = synth.x0_uniform(N, m, seed=8)
+    ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(levels), m, L.FP64, B=L.Diag(*dims, dev(d)))
+    r = L.lobpcg_solve(ctx, dev(X0), tol, 300)
+    ref = olob.laplace7_solver(dims, m, X0, tol, 300, levels=levels, bdiag=d)
+    assert r.status == L.OK and ref.status == olob.OK
+    np.testing.assert_allclose(r.lam, ref.lam, rtol=5e-9)
+    assert r.resid.max() <= tol
+    X = r.X.cpu().numpy()
+    np.testing.assert_allclose(X.T @ (d[:, None] * X), np.eye(m), atol=1e-10)
+    assert abs(r.iters - ref.iters) <= 2, (r.iters, ref.iters)
+
+
+def test_scalar_B_scales_the_closed_form():
+    dims, m, c = (24, 20, 16), 6, 2.5
+    N = int(np.prod(dims))
+    ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(3), m, L.FP64, B=L.Diag(*dims, dev(np.full(N, c))))
+    r = L.lobpcg_solve(ctx, dev(synth.x0_uniform(N, m)), 1e-10, 300)
+    exact, _ = closed_form.smallest(*dims, m)
+    assert r.status == L.OK
+    np.testing.assert_allclose(r.lam, exact / c, rtol=1e-9)
+
+
+def test_diagonal_B_unsupported_combinations():
+    dims, m = (12, 10, 8), 3
+    N = int(np.prod(dims))
+    Bd = L.Diag(*dims, dev(lumped_mass(N, 1)))
+    with pytest.raises(L.LobpcgError):
+        L.lobpcg_setup(L.Op(*dims), L.Precond(None), m, L.MIXED, B=Bd)
+    ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(None), m, L.FP64, B=Bd)
+    X0 = dev(synth.x0_uniform(N, m))
+    r = L.lobpcg_solve(ctx, X0, 1e-8, 10, Y=dev(synth.random_block(N, 2, seed=3)), raise_on_error=False)
+    assert r.status == L.ERR_UNSUPPORTED
+    L.lobpcg_set_option(ctx, L.OPT_FOLD_CHOLQR, 0)
+    assert L.lobpcg_solve(ctx, X0, 1e-8, 10, raise_on_error=False).status == L.ERR_UNSUPPORTED
