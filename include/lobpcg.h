@@ -161,7 +161,8 @@ enum {
                                     /* staged through LDS (3 is invalid); bit 2: the   */
                                     /* multi-column-tile Gram kernel also for narrow   */
                                     /* single-block Grams; bit 3: up to four Gram      */
-                                    /* tiles per wave (default two)                    */
+                                    /* tiles per wave (default two); bit 4: the same   */
+                                    /* for FP32 blocks only                            */
     LOBPCG_OPT_FP32_EXPLICIT_GRAM = 6,/* MIXED: 1 (default) FP32 iterations compute   */
                                     /* X^T X, X^T AX, W^T W, P^T P rather than taking  */
                                     /* I and Lambda for them as the paper's form does  */

@@ -87,13 +87,15 @@ __global__ void __launch_bounds__(256) gramx_kernel(GXDev<T> a)
         }
     }
 
+    // FP32 blocks: the FP64 running sums live in this lane's own entries of
+    // red[wave] (registers are kept for the MFMA accumulators)
     accT acc[NT];
-    double acc64[NT][4];
 #pragma unroll
     for (int j = 0; j < NT; j++) {
         acc[j] = acc_zero<T>();
+        if (sizeof(T) == 4)
 #pragma unroll
-        for (int r = 0; r < 4; r++) acc64[j][r] = 0.0;
+            for (int r = 0; r < 4; r++) red[wave][j][r * 64 + lane] = 0.0;
     }
     // the wave's share of a chunk: k-steps s0 .. s0+ksteps-1 (4 rows each),
     // taken UNR at a time; the loads of the next UNR k-steps (of this chunk or
@@ -149,7 +151,7 @@ __global__ void __launch_bounds__(256) gramx_kernel(GXDev<T> a)
 #pragma unroll
             for (int j = 0; j < NT; j++) {
 #pragma unroll
-                for (int r = 0; r < 4; r++) acc64[j][r] += (double)acc[j][r];
+                for (int r = 0; r < 4; r++) red[wave][j][r * 64 + lane] += (double)acc[j][r];
                 acc[j] = acc_zero<T>();
             }
         }
@@ -166,7 +168,8 @@ __global__ void __launch_bounds__(256) gramx_kernel(GXDev<T> a)
 #pragma unroll
     for (int j = 0; j < NT; j++)
 #pragma unroll
-        for (int r = 0; r < 4; r++) red[wave][j][r * 64 + lane] = sizeof(T) == 4 ? acc64[j][r] : (double)acc[j][r];
+        for (int r = 0; r < 4; r++)
+            if (sizeof(T) == 8) red[wave][j][r * 64 + lane] = (double)acc[j][r];
     __syncthreads();
     for (int e = tid; e < NT * 256; e += blockDim.x) {
         const int j = e / 256, q = e % 256;
@@ -313,7 +316,7 @@ static hipError_t run_gramx(const GramXArgs &h, hipStream_t st)
     for (int t = 0; t < h.ntiles;) {
         int n = 0;
         while (t + n < h.ntiles && h.ta[t + n] == h.ta[t]) n++;
-        NT = std::max(NT, std::min(n, std::max(1, std::min(h.max_nt, GX_MAXB))));
+        NT = std::max(NT, std::min(n, std::max(1, std::min(sizeof(T) == 4 ? h.max_nt32 : h.max_nt, GX_MAXB))));
         t += n;
     }
     if (NT == 3) NT = 4;

@@ -131,7 +131,8 @@ struct GramXArgs {
     long long N;
     double *partials;   // scratch, gram_partials_bytes(N)
     double *out;        // device [ntiles][256]
-    int max_nt;         // most tiles per wave (1, 2 or GX_MAXB)
+    int max_nt;         // most tiles per wave for FP64 blocks (1, 2 or GX_MAXB)
+    int max_nt32;       // the same for FP32 blocks
 };
 size_t gram_partials_bytes(long long N);
 hipError_t launch_gramx(int dtype, const GramXArgs &a, hipStream_t st);

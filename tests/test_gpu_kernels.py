@@ -161,7 +161,7 @@ def test_gram_fp64(N, widths, variant):
     np.testing.assert_allclose(SS, SS.T)      # lower triangle mirrored
 
 
-@pytest.mark.parametrize("variant", [0, 4, 8])
+@pytest.mark.parametrize("variant", [0, 4, 8, 16])
 @pytest.mark.parametrize("N,widths", [(4096, (8, 3, 3)), (70001, (32, 32, 32)), (5003, (5, 7, 2)),
                                       (99999, (32, 1, 1)), (77777, (2,))])
 def test_gram_fp32(N, widths, variant):
