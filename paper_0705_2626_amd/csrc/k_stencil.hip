@@ -7,10 +7,12 @@
 //
 // Mapping: one thread owns V consecutive columns of one (x, y) grid column and
 // marches in z, so the z-1 / z / z+1 values stay in registers and every
-// element is fetched from HBM once; the four in-plane neighbours are the
-// centre values of the adjacent threads of the same or a nearby workgroup,
-// fetched through L1/L2.  Workgroups are remapped so that each XCD owns a
-// contiguous range of (x, y) tiles.
+// element is fetched from HBM once.  The x-1 / x+1 neighbours are the centre
+// values of lanes -L / +L of the same wave and are exchanged by cross-lane
+// shuffles (only lanes at a wave edge load them); the y neighbours are the
+// centre values of threads of the same or a nearby workgroup, fetched through
+// L1/L2.  Workgroups are remapped so that each XCD owns a contiguous range of
+// (x, y) tiles.
 #include "common.h"
 #include "kernels.h"
 
@@ -43,8 +45,11 @@ __global__ void __launch_bounds__(256) stencil7_kernel(int nx, int ny, int nz, i
     const unsigned nbx = gridDim.x;
     const unsigned bx = xcd_remap(blockIdx.x, nbx);
     const i64 plane = (i64)nx * ny * L;   // threads per z-plane
-    const i64 t = (i64)bx * blockDim.x + threadIdx.x;
-    if (t >= plane) return;
+    const i64 t0 = (i64)bx * blockDim.x + threadIdx.x;
+    // lanes past the plane stay (on the plane's last item, without storing):
+    // every lane of a wave takes part in the x-neighbour exchange
+    const bool active = t0 < plane;
+    const i64 t = active ? t0 : plane - 1;
     const int c = (int)(t % L);
     const i64 pxy = t / L;
     const int x = (int)(pxy % nx);
@@ -54,13 +59,26 @@ __global__ void __launch_bounds__(256) stencil7_kernel(int nx, int ny, int nz, i
     const i64 sx = (i64)L * V, sy = (i64)nx * L * V, sz = (i64)nx * ny * L * V;   // element strides
     const i64 base = (pxy * L + c) * V;
     const vec<T, V> zero = vzero<T, V>();
+    // consecutive lanes hold consecutive (point, chunk) items, so the centre
+    // of x-1 / x+1 (same row) is in lane -L / +L of this wave unless that lane
+    // is outside it; only those edge lanes load the neighbour
+    const int lane = threadIdx.x & 63;
+    const bool in_m = lane >= L, in_p = lane + L < 64;
     vec<T, V> prev = z0 > 0 ? vload<T, V>(u + base + (z0 - 1) * sz) : zero;
     vec<T, V> cur = vload<T, V>(u + base + z0 * sz);
     for (int z = z0; z < z1; z++) {
         const i64 i = base + z * sz;
         vec<T, V> next = (z + 1 < nz) ? vload<T, V>(u + i + sz) : zero;
-        vec<T, V> xm = x > 0 ? vload<T, V>(u + i - sx) : zero;
-        vec<T, V> xp = x + 1 < nx ? vload<T, V>(u + i + sx) : zero;
+        vec<T, V> xm, xp;
+#pragma unroll
+        for (int q = 0; q < V; q++) {
+            xm.v[q] = __shfl(cur.v[q], in_m ? lane - L : lane, 64);
+            xp.v[q] = __shfl(cur.v[q], in_p ? lane + L : lane, 64);
+        }
+        if (x == 0) xm = zero;
+        else if (!in_m) xm = vload<T, V>(u + i - sx);
+        if (x + 1 == nx) xp = zero;
+        else if (!in_p) xp = vload<T, V>(u + i + sx);
         vec<T, V> ym = y > 0 ? vload<T, V>(u + i - sy) : zero;
         vec<T, V> yp = y + 1 < ny ? vload<T, V>(u + i + sy) : zero;
         vec<T, V> au = lap<T, V>(cur, prev, next, xm, xp, ym, yp);
@@ -79,7 +97,7 @@ __global__ void __launch_bounds__(256) stencil7_kernel(int nx, int ny, int nz, i
                 o.v[q] = (EPI == EPI_JACOBI) ? cur.v[q] + c1 * r : r;
             }
         }
-        vstore_nt<T, V>(out + i, o);
+        if (active) vstore_nt<T, V>(out + i, o);
         prev = cur;
         cur = next;
     }
