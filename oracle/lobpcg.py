@@ -83,7 +83,8 @@ def b_orthonormalize(V, BV, *others):
     return (right_solve_upper(V, R), right_solve_upper(BV, R)) + tuple(right_solve_upper(O, R) for O in others)
 
 
-def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactivate=True, Y=None, apply_B=None):
+def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactivate=True, Y=None, apply_B=None,
+           explicit_gram=False):
     """Smallest eigenpairs of A x = lambda B x (Section 2.1.1).
 
     apply_A, apply_T, apply_B: functions on (N, k) blocks (apply_B None: B = I).
@@ -95,6 +96,10 @@ def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactiva
     Returns Result(status, lam, X, hist, iters, resid) where hist[k] holds
     rho_j = ||A x_j - lambda_j B x_j|| / (||A|| ||B x_j||) of every column at
     iteration k and resid the explicit final rho_j.
+    explicit_gram: the variant of Section 2.2 that computes the block diagonal
+    of gramB (X^T B X, W^T B W, P_J^T B P_J) instead of taking identities, and
+    with it the X block of gramA (X^T A X instead of Lambda), so that the
+    Rayleigh-Ritz procedure sees the basis as it is after rounding.
     """
     X0 = np.asfortranarray(np.asarray(X0, dtype=np.float64))
     N, m = X0.shape
@@ -163,17 +168,23 @@ def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactiva
             except CholeskyFailure:
                 use_p = False
         C = None
+        if explicit_gram:
+            gXX, gXA, gWW = X.T @ BX, X.T @ AX, W.T @ BW
+            gPP = PJ.T @ BPJ if use_p else None
+        else:
+            gXX, gXA, gWW = np.eye(m), np.diag(lam), np.eye(J.size)
+            gPP = np.eye(J.size)
         for with_p in ([True, False] if use_p else [False]):
             if with_p:                                         # steps 18-19
-                gramA = np.block([[np.diag(lam), X.T @ AW, X.T @ APJ],
+                gramA = np.block([[gXA, X.T @ AW, X.T @ APJ],
                                   [AW.T @ X, W.T @ AW, W.T @ APJ],
                                   [APJ.T @ X, APJ.T @ W, PJ.T @ APJ]])
-                gramB = np.block([[np.eye(m), X.T @ BW, X.T @ BPJ],
-                                  [BW.T @ X, np.eye(J.size), W.T @ BPJ],
-                                  [BPJ.T @ X, BPJ.T @ W, np.eye(J.size)]])
+                gramB = np.block([[gXX, X.T @ BW, X.T @ BPJ],
+                                  [BW.T @ X, gWW, W.T @ BPJ],
+                                  [BPJ.T @ X, BPJ.T @ W, gPP]])
             else:                                              # steps 21-22
-                gramA = np.block([[np.diag(lam), X.T @ AW], [AW.T @ X, W.T @ AW]])
-                gramB = np.block([[np.eye(m), X.T @ BW], [BW.T @ X, np.eye(J.size)]])
+                gramA = np.block([[gXA, X.T @ AW], [AW.T @ X, W.T @ AW]])
+                gramB = np.block([[gXX, X.T @ BW], [BW.T @ X, gWW]])
             # the lower blocks are the transposes of the upper ones
             gramA = np.triu(gramA) + np.triu(gramA, 1).T
             gramB = np.triu(gramB) + np.triu(gramB, 1).T
@@ -211,7 +222,7 @@ def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactiva
 
 
 def laplace7_solver(dims, m, X0, tol, maxit, levels=None, nu_pre=2, nu_post=2, coarse_sweeps=20,
-                    omega=2.0 / 3.0, callback=None, Y=None, bdiag=None):
+                    omega=2.0 / 3.0, callback=None, Y=None, bdiag=None, explicit_gram=False):
     """LOBPCG on the 7-point Laplacian with optional V-cycle preconditioning,
     constraints Y and a positive diagonal B = diag(bdiag) (a lumped mass)."""
     from . import grid, mg
@@ -223,7 +234,8 @@ def laplace7_solver(dims, m, X0, tol, maxit, levels=None, nu_pre=2, nu_post=2, c
     if bdiag is not None:
         d = np.asarray(bdiag, dtype=np.float64).reshape(-1)
         Bop = lambda V: d[:, None] * V
-    return lobpcg(A, X0, tol, maxit, grid.gershgorin_laplace7(), apply_T=T, callback=callback, Y=Y, apply_B=Bop)
+    return lobpcg(A, X0, tol, maxit, grid.gershgorin_laplace7(), apply_T=T, callback=callback, Y=Y, apply_B=Bop,
+                  explicit_gram=explicit_gram)
 
 
 def varcoef_solver(dims, kx, ky, kz, m, X0, tol, maxit, levels=None, callback=None):

@@ -364,6 +364,29 @@ def test_lobpcg_soft_locked_pairs_keep_improving():
     assert np.all(np.diff(e0) <= 1e-15) and e0[-1] < e0[0]
 
 
+def test_lobpcg_explicit_gram_variant():
+    """Section 2.2's variant with the block diagonal of gramB computed: on a
+    short run it gives the paper's form's eigenvalues (closed form) in the same
+    number of iterations; on a long run with m=40 where the paper's form loses
+    orthogonality (a spurious Ritz value below lambda_1), it converges to the
+    closed form."""
+    dims, m = (12, 10, 8), 6
+    X0 = synth.x0_uniform(960, m)
+    exact, _ = closed_form.smallest(*dims, m)
+    a = lobpcg.laplace7_solver(dims, m, X0, 1e-10, 200, levels=2)
+    b = lobpcg.laplace7_solver(dims, m, X0, 1e-10, 200, levels=2, explicit_gram=True)
+    assert a.status == b.status == lobpcg.OK
+    np.testing.assert_allclose(b.lam, exact, rtol=1e-12)
+    assert abs(a.iters - b.iters) <= 1
+    dims, m = (20, 18, 16), 40
+    X0 = synth.x0_uniform(5760, m)
+    exact, _ = closed_form.smallest(*dims, m)
+    c = lobpcg.laplace7_solver(dims, m, X0, 1e-9, 120, levels=3, explicit_gram=True)
+    assert c.status == lobpcg.OK and c.iters < 60
+    np.testing.assert_allclose(c.lam, exact, rtol=1e-11)
+    assert c.resid.max() <= 1e-9
+
+
 def test_lobpcg_error_paths():
     dims, m = (6, 6, 6), 3
     X0 = synth.x0_uniform(216, m)
