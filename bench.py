@@ -23,6 +23,11 @@ Also reported:
                 LOBPCG iteration at the same size, extrapolated to the
                 iteration count of the FP64 GPU solve
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Block-size study (Section 4, LOBPCG performance vs block size, m = 1..98 on
+the 128^3 Laplacian to tol 1e-8): python bench.py --sweep-m 1,2,4,...,98
+prints one JSON line per (m, precision) with the solve time, the iteration
+counts and the time of each step class; the headline line is not printed.
 """
 import argparse
 import json
@@ -76,6 +81,8 @@ def main():
                          "reference for scaling hardware byte counters)")
     ap.add_argument("--no-profile-steps", action="store_true",
                     help="skip the extra solve with per-step HIP-event timing (then the roofline is the stencil's)")
+    ap.add_argument("--sweep-m", default=None,
+                    help="comma-separated block sizes: the block-size study instead of the headline run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see the design notes on how "
@@ -96,6 +103,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.sweep_m:
+        sweep_block_size(args, L, synth, torch, dev)
+        return
     n, m, levels, tol = args.n, args.m, args.levels, args.tol
     dims = (n, n, n)
     N = n ** 3
@@ -214,6 +224,43 @@ def main():
         out["cpu_baseline"] = cpu_baseline(dims, m, levels, X0.cpu().numpy(),
                                            fp64["iters"] if fp64 else acc_mixed["iters"])
     print(json.dumps(out), flush=True)
+
+
+def sweep_block_size(args, L, synth, torch, dev):
+    """Solve time vs block size on the 128^3 Laplacian (5-level V-cycle), FP64
+    and mixed, one solve per (m, precision) after an untimed short solve."""
+    from oracle import closed_form  # closed form of the spectrum, used only to report accuracy
+    n = 128 if args.n == 256 else args.n
+    levels = 5 if args.levels == 6 else args.levels
+    dims = (n, n, n)
+    N = n ** 3
+    A, T = L.Op(*dims), L.Precond(levels)
+    for m in [int(v) for v in args.sweep_m.split(",")]:
+        X0 = torch.from_numpy(synth.x0_uniform(N, m, seed=2)).to(dev)
+        exact, _ = closed_form.smallest(*dims, m)
+        for prec, name in ((L.FP64, "fp64"), (L.MIXED, "mixed")):
+            ctx = L.lobpcg_setup(A, T, m, prec, device=dev)
+            L.lobpcg_solve(ctx, X0, args.tol, 2, hist=False, raise_on_error=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = L.lobpcg_solve(ctx, X0, args.tol, 1000, hist=False, raise_on_error=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            st = L.lobpcg_get_stats(ctx)
+            L.lobpcg_set_option(ctx, L.OPT_PROFILE, 1)
+            L.lobpcg_solve(ctx, X0, args.tol, 1000, hist=False, raise_on_error=False)
+            sp = L.lobpcg_get_stats(ctx)
+            ok = r.status in (L.OK, L.NOT_CONVERGED)
+            line = {"sweep": "block_size", "n": n, "m": m, "precision": name, "status": L.status_string(r.status),
+                    "time_s": dt, "iters": r.iters, "iters_fp32": st["iters_fp32"], "iters_fp64": st["iters_fp64"],
+                    "ms_per_iter": dt * 1e3 / max(r.iters, 1),
+                    "max_rel_err_closed_form": float(np.max(np.abs(r.lam - exact) / exact)) if ok else None,
+                    "max_resid": float(r.resid.max()) if ok else None,
+                    "step_ms": {k: round(v, 3) for k, v in sp["step_ms"].items()}}
+            print(json.dumps(line), flush=True)
+            del ctx, r
+            torch.cuda.empty_cache()
+        del X0
 
 
 def cpu_baseline(dims, m, levels, X0, iters):

@@ -88,7 +88,9 @@ typedef struct lobpcg_ctx lobpcg_ctx;   /* opaque */
 /* Device workspace needed by lobpcg_setup for this problem, in bytes.
  * B: NULL (B = I) or a DIAG operator of A's dimensions (A x = lambda B x,
  * Section 2.1.1; FP64 precision only, else ERR_UNSUPPORTED).  m: block
- * size, 1 <= m and 3m <= N.  Pure host code: callable without a GPU. */
+ * size, 1 <= m <= 128 and 3m <= N (blocks of more than 32 columns run through
+ * a general path of the block kernels: slower per column).  Pure host code:
+ * callable without a GPU. */
 int lobpcg_workspace_bytes(const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T,
                            int m, int precision, size_t *bytes);
 
@@ -123,7 +125,7 @@ int lobpcg_solve(lobpcg_ctx *ctx, const lobpcg_op *A, const lobpcg_op *B, const 
  * are sought in the orthogonal complement of span(Y), imposed on X0 (step 2)
  * and on every preconditioned residual block (step 10) as
  * V - Y (Y^T Y)^-1 (Y^T V).
- *   d_Y   N x ny FP64, point-major, full column rank, 1 <= ny <= 32,
+ *   d_Y   N x ny FP64, point-major, full column rank, 1 <= ny <= 128,
  *         3m + ny <= N; caller-owned, read during the call only
  * As printed, step 7 does not project the residual: it goes to zero only when
  * span(Y) is invariant under A, as for previously computed eigenvectors (the
@@ -166,11 +168,17 @@ enum {
     LOBPCG_OPT_FP32_EXPLICIT_GRAM = 6,/* MIXED: 1 (default) FP32 iterations compute   */
                                     /* X^T X, X^T AX, W^T W, P^T P rather than taking  */
                                     /* I and Lambda for them as the paper's form does  */
-    LOBPCG_OPT_FOLD_CHOLQR = 7      /* 1 (default): the Cholesky-QR factors of steps   */
+    LOBPCG_OPT_FOLD_CHOLQR = 7,     /* 1 (default): the Cholesky-QR factors of steps   */
                                     /* 11 and 14-15 are folded into the Gram matrices  */
                                     /* and the update coefficients (W_J R^-1 and       */
                                     /* P_J R^-1 are never formed; same algebra, fewer  */
                                     /* passes); 0: applied to the blocks               */
+    LOBPCG_OPT_FP64_EXPLICIT_GRAM = 8 /* 1: FP64 iterations compute the block diagonal */
+                                    /* of gramB and X^T AX too (the variant Section    */
+                                    /* 2.2 reports testing in MATLAB: better           */
+                                    /* attainable accuracy; it keeps long runs on      */
+                                    /* clustered spectra from losing orthogonality);   */
+                                    /* 0 (default): the paper's form                   */
 };
 int lobpcg_set_option(lobpcg_ctx *ctx, int key, double value);
 

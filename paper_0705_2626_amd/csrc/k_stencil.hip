@@ -32,6 +32,28 @@ __device__ __forceinline__ vec<T, V> lap(const vec<T, V> &c, const vec<T, V> &zm
     return r;
 }
 
+// x-1 / x+1 neighbours of the centre values cur (element offset i): lanes
+// -L / +L of the wave hold them when they exist (consecutive lanes hold
+// consecutive (point, chunk) items of one row); lanes at a wave edge load
+// them, lanes at the grid's x faces take the Dirichlet zero.  Every lane of
+// the wave must call this (the shuffles are wave-wide).
+template <typename T, int V>
+__device__ __forceinline__ void x_neighbours(const vec<T, V> &cur, const T *__restrict__ u, i64 i, i64 sx,
+                                             int x, int nx, int L, vec<T, V> &xm, vec<T, V> &xp)
+{
+    const int lane = threadIdx.x & 63;
+    const bool in_m = lane >= L, in_p = lane + L < 64;
+#pragma unroll
+    for (int q = 0; q < V; q++) {
+        xm.v[q] = __shfl(cur.v[q], in_m ? lane - L : lane, 64);
+        xp.v[q] = __shfl(cur.v[q], in_p ? lane + L : lane, 64);
+    }
+    if (x == 0) xm = vzero<T, V>();
+    else if (!in_m) xm = vload<T, V>(u + i - sx);
+    if (x + 1 == nx) xp = vzero<T, V>();
+    else if (!in_p) xp = vload<T, V>(u + i + sx);
+}
+
 // EPI_APPLY : out = s * L7 u
 // EPI_JACOBI: out = u + c1 * (b - s * L7 u)
 // EPI_RESID : out = b - s * L7 u
@@ -59,26 +81,13 @@ __global__ void __launch_bounds__(256) stencil7_kernel(int nx, int ny, int nz, i
     const i64 sx = (i64)L * V, sy = (i64)nx * L * V, sz = (i64)nx * ny * L * V;   // element strides
     const i64 base = (pxy * L + c) * V;
     const vec<T, V> zero = vzero<T, V>();
-    // consecutive lanes hold consecutive (point, chunk) items, so the centre
-    // of x-1 / x+1 (same row) is in lane -L / +L of this wave unless that lane
-    // is outside it; only those edge lanes load the neighbour
-    const int lane = threadIdx.x & 63;
-    const bool in_m = lane >= L, in_p = lane + L < 64;
     vec<T, V> prev = z0 > 0 ? vload<T, V>(u + base + (z0 - 1) * sz) : zero;
     vec<T, V> cur = vload<T, V>(u + base + z0 * sz);
     for (int z = z0; z < z1; z++) {
         const i64 i = base + z * sz;
         vec<T, V> next = (z + 1 < nz) ? vload<T, V>(u + i + sz) : zero;
         vec<T, V> xm, xp;
-#pragma unroll
-        for (int q = 0; q < V; q++) {
-            xm.v[q] = __shfl(cur.v[q], in_m ? lane - L : lane, 64);
-            xp.v[q] = __shfl(cur.v[q], in_p ? lane + L : lane, 64);
-        }
-        if (x == 0) xm = zero;
-        else if (!in_m) xm = vload<T, V>(u + i - sx);
-        if (x + 1 == nx) xp = zero;
-        else if (!in_p) xp = vload<T, V>(u + i + sx);
+        x_neighbours<T, V>(cur, u, i, sx, x, nx, L, xm, xp);
         vec<T, V> ym = y > 0 ? vload<T, V>(u + i - sy) : zero;
         vec<T, V> yp = y + 1 < ny ? vload<T, V>(u + i + sy) : zero;
         vec<T, V> au = lap<T, V>(cur, prev, next, xm, xp, ym, yp);
@@ -114,8 +123,9 @@ __global__ void __launch_bounds__(256) varcoef7_kernel(int nx, int ny, int nz, i
 {
     const unsigned bx = xcd_remap(blockIdx.x, gridDim.x);
     const i64 plane = (i64)nx * ny * L;
-    const i64 t = (i64)bx * blockDim.x + threadIdx.x;
-    if (t >= plane) return;
+    const i64 t0 = (i64)bx * blockDim.x + threadIdx.x;
+    const bool active = t0 < plane;   // idle lanes stay for the shuffles
+    const i64 t = active ? t0 : plane - 1;
     const int c = (int)(t % L);
     const i64 pxy = t / L;
     const int x = (int)(pxy % nx);
@@ -130,8 +140,8 @@ __global__ void __launch_bounds__(256) varcoef7_kernel(int nx, int ny, int nz, i
     for (int z = z0; z < z1; z++) {
         const i64 i = base + z * sz;
         vec<T, V> next = (z + 1 < nz) ? vload<T, V>(u + i + sz) : zero;
-        vec<T, V> xm = x > 0 ? vload<T, V>(u + i - sx) : zero;
-        vec<T, V> xp = x + 1 < nx ? vload<T, V>(u + i + sx) : zero;
+        vec<T, V> xm, xp;
+        x_neighbours<T, V>(cur, u, i, sx, x, nx, L, xm, xp);
         vec<T, V> ym = y > 0 ? vload<T, V>(u + i - sy) : zero;
         vec<T, V> yp = y + 1 < ny ? vload<T, V>(u + i + sy) : zero;
         const i64 fxi = ((i64)z * ny + y) * (nx + 1) + x;
@@ -147,7 +157,7 @@ __global__ void __launch_bounds__(256) varcoef7_kernel(int nx, int ny, int nz, i
             o.v[q] = kxm * (up - xm.v[q]) + kxp * (up - xp.v[q]) + kym * (up - ym.v[q]) +
                      kyp * (up - yp.v[q]) + kzm * (up - prev.v[q]) + kzp * (up - next.v[q]);
         }
-        vstore_nt<T, V>(out + i, o);
+        if (active) vstore_nt<T, V>(out + i, o);
         prev = cur;
         cur = next;
     }

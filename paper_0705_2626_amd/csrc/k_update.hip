@@ -36,10 +36,12 @@ static const int MV_MAX_BLOCKS = 4096;
 
 template <typename T>
 struct MVDev {
-    const T *in[2][3];
-    int ld[3], k[3];
-    const int *cols[3];
+    const T *in[2][MV_MAX_IN];
+    int ld[MV_MAX_IN], k[MV_MAX_IN];
+    const int *cols[MV_MAX_IN];
+    int coff[MV_MAX_IN];
     int nin, nside, kout, K, Kp;
+    int n0, ld2;
     const T *C;
     const T *add;
     T *out[2];
@@ -205,10 +207,10 @@ __device__ __forceinline__ void mv_outputs(const MVDev<T> &a, const SH &sh, int 
             const int c = 16 * nt + (lane & 15);
             if (c >= a.kout) continue;
             T v = acc[nt][r];
-            if (a.add && s == 0) v += a.add[p * a.kout + c];
+            if (a.add && s == 0) v += a.add[p * a.ld2 + c];
             const int q = sh.opos[c];
             if (out && q >= 0) out[p * a.nout + q] = v;
-            if (has2 && !SKIP2) out2[p * a.kout + c] = acc2[nt][r];
+            if (has2 && !SKIP2) out2[p * a.ld2 + c] = acc2[nt][r];
             if (resid && s == 1) {
                 const double x = (double)keepX[nt][r];
                 const double rv = (double)acc2[nt][r] - sh.theta[c] * x;
@@ -406,14 +408,16 @@ __host__ __device__ inline size_t mvf_stage_offset(int nsteps, int NT, int K, si
 }
 __host__ __device__ inline size_t mvf_stage_bytes(int NT, size_t esz) { return (size_t)4 * 16 * (NT * 16 + 4) * esz; }
 
-// av[i] = column (l/16)*k4 + i of this lane's row (zero past k or the grid)
+// av[i] = column (l/16)*k4 + i of this lane's row (zero past k or the grid);
+// rowlen: columns of the row from base on, aligned: base is 16-byte aligned
+// for every row
 template <typename T>
-__device__ __forceinline__ void frag_load(T (&av)[KQ], const T *__restrict__ base, int ld, int k, int k4,
-                                          const int *__restrict__ cmap, bool mapped, bool pok, int kq)
+__device__ __forceinline__ void frag_load(T (&av)[KQ], const T *__restrict__ base, int rowlen, bool aligned, int k,
+                                          int k4, const int *__restrict__ cmap, bool mapped, bool pok, int kq)
 {
     const int VE = 16 / sizeof(T);
     const int j0 = kq * k4;
-    const bool vec_ok = !mapped && (k4 % VE) == 0 && (ld % VE) == 0 && j0 + k4 <= ld;
+    const bool vec_ok = !mapped && aligned && (k4 % VE) == 0 && j0 + k4 <= rowlen;
     if (vec_ok) {
 #pragma unroll
         for (int i = 0; i < KQ; i += VE) {
@@ -485,13 +489,13 @@ __global__ void __launch_bounds__(256) mvf_kernel(MVDev<T> a)
         }
     };
     auto load_in = [&](T(&av)[KQ], int s, int b, i64 prow, bool pok) {
-        frag_load<T>(av, a.in[s][b] + prow * a.ld[b], a.ld[b], a.k[b], k4[b], sh.cmap + roffs[b],
-                     a.cols[b] != nullptr, pok, kq);
+        frag_load<T>(av, a.in[s][b] + prow * a.ld[b], a.ld[b], (a.ld[b] % (16 / (int)sizeof(T))) == 0, a.k[b],
+                     k4[b], sh.cmap + roffs[b], a.cols[b] != nullptr, pok, kq);
     };
     const i64 ngroups = (a.N + 15) / 16, gstride = (i64)gridDim.x * 4;
     i64 g = (i64)blockIdx.x * 4 + wave;
     if constexpr (sizeof(T) == 4) {
-        const bool stage2 = has2 && (a.kout % 4) == 0;
+        const bool stage2 = has2 && (a.kout % 4) == 0 && (a.ld2 % 4) == 0;
         // FP32: input 0 (X, the widest block, or the only input) is loaded for
         // both sides one group ahead, so that its loads are in flight while the
         // current group is multiplied
@@ -546,7 +550,7 @@ __global__ void __launch_bounds__(256) mvf_kernel(MVDev<T> a)
                     for (int h = 0; h < NT * 4 / 4; h++) {
                         const int c0 = 4 * ((lane & 3) + 4 * h);
                         const vec<T, 4> v = *reinterpret_cast<const vec<T, 4> *>(st + row * (NC + 4) + c0);
-                        if (p < a.N && c0 < a.kout) vstore<T, 4>(a.out2[s] + p * a.kout + c0, v);
+                        if (p < a.N && c0 < a.kout) vstore<T, 4>(a.out2[s] + p * a.ld2 + c0, v);
                     }
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 } else {
@@ -589,6 +593,94 @@ __global__ void __launch_bounds__(256) mvf_kernel(MVDev<T> a)
 #pragma unroll
                     for (int nt = 0; nt < NT; nt++) keepX[nt] = acc2[nt];
                 }
+            }
+        }
+    }
+    if (a.partials) mv_norms<T, NT>(a, sh, sr, sx, wave, lane);
+}
+
+// Wide kernel: blocks of more than MAXW columns, given as up to MV_MAX_IN
+// pieces of at most MAXW columns each (a piece is a column range or a column
+// list of one block).  The products are those of the fragment kernel's FP64
+// branch, one piece after another; the per-piece tables live in LDS so that
+// the piece loop can run over a runtime count without private arrays.  With
+// out2 the first n0 pieces form the X part: acc = the sum over the pieces
+// from n0 on, acc2 = acc + the X pieces.
+template <typename T, int NT>
+__global__ void __launch_bounds__(256) mvw_kernel(MVDev<T> a)
+{
+    typedef typename Mfma<T>::acc accT;
+    extern __shared__ unsigned char smem[];
+    __shared__ int tk4[MV_MAX_IN], tsoff[MV_MAX_IN], troff[MV_MAX_IN];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, kq = lane >> 4;
+    const int NC = NT * 16;
+    int nsteps = 0;
+    for (int b = 0; b < a.nin; b++) nsteps += (a.k[b] + 3) / 4;
+    if (tid == 0) {
+        int st = 0, ro = 0;
+        for (int b = 0; b < a.nin; b++) {
+            tk4[b] = (a.k[b] + 3) / 4;
+            tsoff[b] = st;
+            troff[b] = ro;
+            st += tk4[b];
+            ro += a.k[b];
+        }
+    }
+    __syncthreads();
+    MVFShared<T, NT> sh(smem, a, nsteps);
+    for (int e = tid; e < nsteps * NT * 64; e += blockDim.x) {
+        const int l = e & 63, nt = (e >> 6) % NT, st = (e >> 6) / NT;
+        int b = 0;
+        while (b + 1 < a.nin && st >= tsoff[b + 1]) b++;
+        const int i = st - tsoff[b];
+        const int j = (l >> 4) * tk4[b] + i, c = 16 * nt + (l & 15);
+        sh.Cf[e] = (j < a.k[b] && c < a.kout) ? a.C[(troff[b] + j) * a.kout + c] : T(0);
+    }
+    for (int b = 0; b < a.nin; b++)
+        for (int r = tid; r < a.k[b]; r += blockDim.x) sh.cmap[troff[b] + r] = a.cols[b] ? a.cols[b][r] : r;
+    for (int c = tid; c < NC; c += blockDim.x) {
+        sh.opos[c] = c < a.kout ? (a.opos ? a.opos[c] : c) : -1;
+        sh.wpos[c] = (c < a.kout && a.wpos) ? a.wpos[c] : -1;
+        sh.theta[c] = (c < a.kout && a.theta) ? a.theta[c] : 0.0;
+    }
+    __syncthreads();
+
+    const bool has2 = a.out2[0] != nullptr;
+    double sr[NT], sx[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; nt++) sr[nt] = sx[nt] = 0.0;
+    auto input = [&](accT(&tgt)[NT], int s, int b, i64 prow, bool pok) {
+        const int k4 = tk4[b], ld = a.ld[b], co = a.coff[b];
+        T av[KQ];
+        frag_load<T>(av, a.in[s][b] + prow * ld + co, ld - co, ((ld | co) % (16 / (int)sizeof(T))) == 0, a.k[b], k4,
+                     sh.cmap + troff[b], a.cols[b] != nullptr, pok, kq);
+        const T *cf = sh.Cf + tsoff[b] * NT * 64 + lane;
+#pragma unroll
+        for (int i = 0; i < KQ; i++) {
+            if (i >= k4) break;
+#pragma unroll
+            for (int nt = 0; nt < NT; nt++) tgt[nt] = Mfma<T>::mma(av[i], cf[(i * NT + nt) * 64], tgt[nt]);
+        }
+    };
+    const i64 ngroups = (a.N + 15) / 16, gstride = (i64)gridDim.x * 4;
+    for (i64 g = (i64)blockIdx.x * 4 + wave; g < ngroups; g += gstride) {
+        const i64 p0w = g * 16, prow = p0w + (lane & 15);
+        const bool pok = prow < a.N;
+        accT keepX[NT];
+        for (int s = 0; s < a.nside; s++) {
+            accT acc[NT], acc2[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; nt++) acc[nt] = acc_zero<T>(), acc2[nt] = acc_zero<T>();
+            for (int b = has2 ? a.n0 : 0; b < a.nin; b++) input(acc, s, b, prow, pok);
+            if (has2) {
+#pragma unroll
+                for (int nt = 0; nt < NT; nt++) acc2[nt] = acc[nt];
+                for (int b = 0; b < a.n0; b++) input(acc2, s, b, prow, pok);
+            }
+            mv_outputs<T, NT>(a, sh, s, p0w, acc, acc2, keepX, sr, sx, lane);
+            if (s == 0) {
+#pragma unroll
+                for (int nt = 0; nt < NT; nt++) keepX[nt] = acc2[nt];
             }
         }
     }
@@ -663,9 +755,9 @@ __global__ void __launch_bounds__(256) mvn_kernel(MVDev<T> a)
             for (int c = 0; c < NARROW; c++) {
                 if (c >= a.kout) break;
                 T v = acc[c];
-                if (a.add && s == 0) v += a.add[p * a.kout + c];
+                if (a.add && s == 0) v += a.add[p * a.ld2 + c];
                 if (out && opos[c] >= 0) out[p * a.nout + opos[c]] = v;
-                if (has2) out2[p * a.kout + c] = acc2[c];
+                if (has2) out2[p * a.ld2 + c] = acc2[c];
                 if (resid && s == 1) {
                     const double x = (double)keepX[c];
                     const double rv = (double)acc2[c] - theta[c] * x;
@@ -701,10 +793,11 @@ __global__ void __launch_bounds__(256) mvn_kernel(MVDev<T> a)
     }
 }
 
-// sums[e] = sum over workgroups of partials[b][e]: one workgroup per entry,
-// strided partial sums then a fixed-shape tree, so the order never changes.
+// sums over workgroups of partials[b][e], e = which * kc + c, written to
+// out[which * ld + c]: one workgroup per entry, strided partial sums then a
+// fixed-shape tree, so the order never changes.
 __global__ void __launch_bounds__(256) mv_reduce_kernel(const double *__restrict__ partials, int nb, int width,
-                                                        double *__restrict__ out)
+                                                        int kc, int ld, double *__restrict__ out)
 {
     __shared__ double red[256];
     const int e = blockIdx.x;
@@ -716,7 +809,7 @@ __global__ void __launch_bounds__(256) mv_reduce_kernel(const double *__restrict
         if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[e] = red[0];
+    if (threadIdx.x == 0) out[(e / kc) * ld + e % kc] = red[0];
 }
 
 // both kernels cover 64 grid points per workgroup pass (4 waves x 16 points)
@@ -726,21 +819,42 @@ int mv_blocks(long long N)
     return (int)(nt < MV_MAX_BLOCKS ? (nt > 0 ? nt : 1) : MV_MAX_BLOCKS);
 }
 
+// dynamic LDS of the wide kernel for pieces of widths k[0..nin)
+static size_t mvw_lds(int NT, size_t esz, int nin, const int *k)
+{
+    int nsteps = 0, K = 0;
+    for (int b = 0; b < nin; b++) nsteps += (k[b] + 3) / 4, K += k[b];
+    return mvf_stage_offset(nsteps, NT, K, esz);
+}
+static const size_t MVW_MAX_LDS = 64 * 1024 - 256;   // with the kernel's static tables
+
+int mv_wide_chunk(int dtype, int nin, const int *k)
+{
+    const size_t esz = dtype == DT_F32 ? 4 : 8;
+    if (mvw_lds(2, esz, nin, k) <= MVW_MAX_LDS) return 32;
+    if (mvw_lds(1, esz, nin, k) <= MVW_MAX_LDS) return 16;
+    return 0;
+}
+
 template <typename T, int NT>
-static hipError_t run_mv(const MVArgs &h, hipStream_t st)
+static hipError_t run_mv(const MVArgs &h, bool wide, hipStream_t st)
 {
     MVDev<T> a;
     a.K = 0;
     bool any_wide = false;
-    for (int b = 0; b < 3; b++) {
-        for (int s = 0; s < 2; s++) a.in[s][b] = (const T *)h.in[s][b];
-        a.ld[b] = h.ld[b];
-        a.k[b] = b < h.nin ? h.k[b] : 0;
-        a.cols[b] = h.cols[b];
+    for (int b = 0; b < MV_MAX_IN; b++) {
+        const bool used = b < h.nin;
+        for (int s = 0; s < 2; s++) a.in[s][b] = used ? (const T *)h.in[s][b] : nullptr;
+        a.ld[b] = used ? h.ld[b] : 1;
+        a.k[b] = used ? h.k[b] : 0;
+        a.cols[b] = used ? h.cols[b] : nullptr;
+        a.coff[b] = used ? h.coff[b] : 0;
         a.K += a.k[b];
-        if (b < h.nin && h.ld[b] > NARROW) any_wide = true;
+        if (used && h.ld[b] > NARROW) any_wide = true;
     }
     a.nin = h.nin;
+    a.n0 = h.n0;
+    a.ld2 = h.ld2 > 0 ? h.ld2 : h.kout;
     a.nside = h.nside;
     a.kout = h.kout;
     a.Kp = (a.K + 3) / 4 * 4;
@@ -763,7 +877,12 @@ static hipError_t run_mv(const MVArgs &h, hipStream_t st)
     bool narrow = h.kout <= NARROW;
     for (int b = 0; b < h.nin; b++) narrow = narrow && h.ld[b] <= NARROW;
     const size_t tail = (size_t)NC * 8 + (size_t)16 * 2 * NC * 8 + (size_t)(a.K + 4 + 2 * NC) * sizeof(int);
-    if (h.variant == 0 && narrow) {
+    if (wide) {
+        int nsteps = 0;
+        for (int b = 0; b < h.nin; b++) nsteps += (h.k[b] + 3) / 4;
+        const size_t shm = mvf_stage_offset(nsteps, NT, a.K, sizeof(T));
+        hipLaunchKernelGGL((mvw_kernel<T, NT>), dim3(nb), dim3(256), shm, st, a);
+    } else if (h.variant == 0 && narrow) {
         const size_t shm = (size_t)NARROW * 8 + (size_t)2 * NARROW * 256 * 8 + (size_t)a.K * NARROW * sizeof(T) +
                            (size_t)(a.K + 2 * NARROW) * sizeof(int);
         hipLaunchKernelGGL((mvn_kernel<T>), dim3(nb), dim3(256), shm, st, a);
@@ -783,21 +902,31 @@ static hipError_t run_mv(const MVArgs &h, hipStream_t st)
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !h.partials) return e;
-    hipLaunchKernelGGL(mv_reduce_kernel, dim3(2 * h.kout), dim3(256), 0, st, h.partials, nb, 2 * h.kout, h.sums);
+    hipLaunchKernelGGL(mv_reduce_kernel, dim3(2 * h.kout), dim3(256), 0, st, h.partials, nb, 2 * h.kout, h.kout,
+                       h.sums_ld > 0 ? h.sums_ld : h.kout, h.sums);
     return hipGetLastError();
 }
 
 hipError_t launch_mv(int dtype, const MVArgs &a, hipStream_t st)
 {
     if (a.N == 0) return hipSuccess;
-    if (a.nin < 1 || a.nin > 3 || a.nside < 1 || a.nside > 2) return hipErrorInvalidValue;
-    for (int b = 0; b < a.nin; b++)
-        if (a.ld[b] > MAXW || a.ld[b] < 1 || a.k[b] < 1) return hipErrorInvalidValue;
+    if (a.nin < 1 || a.nin > MV_MAX_IN || a.nside < 1 || a.nside > 2) return hipErrorInvalidValue;
+    // the wide kernel takes more than 3 pieces, stored rows wider than MAXW
+    // (pieces of a wider block), X parts of several pieces and chunked outputs
+    bool wide = a.nin > 3 || a.n0 != 1 || (a.ld2 > 0 && a.ld2 != a.kout) || (a.sums_ld > 0 && a.sums_ld != a.kout);
+    for (int b = 0; b < a.nin; b++) {
+        if (a.ld[b] < 1 || a.k[b] < 1 || a.k[b] > MAXW || a.coff[b] < 0) return hipErrorInvalidValue;
+        if (a.cols[b] ? a.coff[b] != 0 : a.coff[b] + a.k[b] > a.ld[b]) return hipErrorInvalidValue;
+        if (a.ld[b] > MAXW || a.coff[b]) wide = true;
+    }
     if (a.kout < 1 || a.kout > 32) return hipErrorInvalidValue;
+    if (a.out2[0] && (a.n0 < 1 || a.n0 > a.nin)) return hipErrorInvalidValue;
     if (a.partials && (a.nside != 2 || !a.out2[0])) return hipErrorInvalidValue;
     const bool two = a.kout > 16;
-    if (dtype == DT_F32) return two ? run_mv<float, 2>(a, st) : run_mv<float, 1>(a, st);
-    return two ? run_mv<double, 2>(a, st) : run_mv<double, 1>(a, st);
+    if (wide && !mv_wide_chunk(dtype, a.nin, a.k)) return hipErrorInvalidValue;
+    if (wide && two && mv_wide_chunk(dtype, a.nin, a.k) < 32) return hipErrorInvalidValue;
+    if (dtype == DT_F32) return two ? run_mv<float, 2>(a, wide, st) : run_mv<float, 1>(a, wide, st);
+    return two ? run_mv<double, 2>(a, wide, st) : run_mv<double, 1>(a, wide, st);
 }
 
 }  // namespace lobpcg

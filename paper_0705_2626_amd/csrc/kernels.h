@@ -55,11 +55,23 @@ bool coarse_solve_fits(int dtype, const Grid3 &g);
 // With partials/sums (needs two sides and out2) it also forms the residual
 // R = out2[1] - out2[0] diag(theta), writes its columns with wpos[c] >= 0 to
 // Wout (N x nW) and sums[c] = sum_p R_pc^2, sums[kout + c] = sum_p out2[0]_pc^2.
+// Inputs wider than 32 columns, or more than 3 inputs, go to a separate wide
+// kernel: the caller splits each block into pieces of at most 32 columns
+// (MV_MAX_IN pieces in all) and, with out2, gives the number n0 of leading
+// pieces that form the X part in0 C_0.  Outputs wider than 32 columns are
+// computed in chunks of columns by separate launches: ld2 is then the row
+// stride of out2 and add (and the pointers are offset to the chunk), and
+// sums_ld the offset of the second half of sums.
+static const int MV_MAX_IN = 12;
 struct MVArgs {
-    const void *in[2][3];
-    int ld[3], k[3];
-    const int *cols[3];
+    const void *in[2][MV_MAX_IN];
+    int ld[MV_MAX_IN], k[MV_MAX_IN];
+    const int *cols[MV_MAX_IN];
+    int coff[MV_MAX_IN] = {};   // first column of a piece within its stored rows (wide kernel only)
     int nin, nside, kout;
+    int n0 = 1;             // leading pieces of the X part (with out2)
+    int ld2 = 0;            // row stride of out2 and add (0: kout)
+    int sums_ld = 0;        // sums[c] and sums[sums_ld + c] (0: kout)
     const void *C;          // device, element type of the blocks, (sum k) x kout
     const void *add;
     void *out[2];
@@ -78,6 +90,10 @@ struct MVArgs {
 };
 int mv_blocks(long long N);
 hipError_t launch_mv(int dtype, const MVArgs &a, hipStream_t st);
+// widest output chunk (32, 16, or 0 if none fits in LDS) of the wide kernel
+// for input pieces of the given widths
+int mv_wide_chunk(int dtype, int nin, const int *k);
+static const int MV_PIECE = 32;     // columns per input piece and per output chunk
 
 // out[p][jj] = in[p][map[jj]] for jj < nout (in: N x ld)
 hipError_t launch_gather_cols(int dtype, long long N, const void *in, int ld, const int *map, int nout, void *out,

@@ -25,7 +25,7 @@ namespace {
 const size_t ALIGN = 256;
 // The Gram kernel keeps 3m-column row chunks and the combine kernel its
 // (3m x m) coefficients in LDS; this bounds m.
-const int LOBPCG_MAX_M = 32;
+const int LOBPCG_MAX_M = 128;
 const int COEF_SLOTS = 16;
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
@@ -164,6 +164,7 @@ struct lobpcg_ctx {
     bool profile, reactivate;
     int mv_variant, gram_staged, gram_nt4, gram_nt32;  // kernel variants (see LOBPCG_OPT_KERNELS)
     bool fp32_explicit;           // FP32 phase: Gram diagonal blocks computed, not assumed
+    bool fp64_explicit;           // the same for FP64 iterations
     bool fold;                    // Cholesky-QR factors of W_J, P_J folded into Gram and coefficients
     bool hasB;                    // A x = lambda B x with B = diag (FP64 only)
     lobpcg_op Bop;
@@ -355,13 +356,12 @@ int gram(lobpcg_ctx *c, int dt, int n, const void *const *S, const void *const *
     // with BS the "S^T S" products are S^T BS: Rm takes those columns from BS
     const int sb = BS ? 6 : 0;
     // Lm = S; Rm as above.  rs[j] / ra[j]: column of Rm holding S_j / AS_j (-1: none)
-    a.KL = K;
-    for (int i = 0; i < K; i++) a.lmap[i] = (unsigned short)((blk[i] << 8) | col[i]);
+    std::vector<unsigned short> lmap(K), rmap;
+    for (int i = 0; i < K; i++) lmap[i] = (unsigned short)((blk[i] << 8) | col[i]);
     std::vector<int> rs(K, -1), ra(K, -1);
-    int KR = 0;
     auto addr = [&](int arr, int i, std::vector<int> &pos) {
-        pos[i] = KR;
-        a.rmap[KR++] = (unsigned short)((arr << 8) | col[i]);
+        pos[i] = (int)rmap.size();
+        rmap.push_back((unsigned short)((arr << 8) | col[i]));
     };
     if (pform) {
         for (int i = w[0]; i < K; i++) addr(sb + blk[i], i, rs);
@@ -377,8 +377,7 @@ int gram(lobpcg_ctx *c, int dt, int n, const void *const *S, const void *const *
         if (AS)
             for (int i = 0; i < K; i++) addr(3 + blk[i], i, ra);
     }
-    a.KR = KR;
-    if (K > GX_MAX_L || KR > GX_MAX_R) return LOBPCG_ERR_ARG;
+    const int KR = (int)rmap.size();
     // the entries wanted, as (row of Lm, column of Rm) pairs, and their tiles
     struct Want { int i, j, mat, r; };
     std::vector<Want> want;
@@ -392,41 +391,100 @@ int gram(lobpcg_ctx *c, int dt, int n, const void *const *S, const void *const *
     for (const Want &q : want) tiles.push_back(((q.i / 16) << 8) | (q.r / 16));
     std::sort(tiles.begin(), tiles.end());
     tiles.erase(std::unique(tiles.begin(), tiles.end()), tiles.end());
-    if (tiles.empty() || (int)tiles.size() > GX_MAX_TILES) return LOBPCG_ERR_ARG;
-    a.ntiles = (int)tiles.size();
-    for (int t = 0; t < a.ntiles; t++) a.ta[t] = tiles[t] >> 8, a.tb[t] = tiles[t] & 255;
+    if (tiles.empty()) return LOBPCG_ERR_ARG;
+    // Launches: the tiles in order, as many per launch as its argument
+    // tables hold (one launch whenever the whole product fits)
+    struct Launch { std::vector<int> la, lb; int t0, t1; };
+    std::vector<Launch> launches;
+    {
+        Launch cur{{}, {}, 0, 0};
+        for (int t = 0; t < (int)tiles.size(); t++) {
+            const int ta = tiles[t] >> 8, tb = tiles[t] & 255;
+            const bool newa = std::find(cur.la.begin(), cur.la.end(), ta) == cur.la.end();
+            const bool newb = std::find(cur.lb.begin(), cur.lb.end(), tb) == cur.lb.end();
+            if (cur.t1 > cur.t0 && (cur.t1 - cur.t0 >= GX_MAX_TILES || (newa && (int)cur.la.size() >= GX_MAX_L / 16) ||
+                                    (newb && (int)cur.lb.size() >= GX_MAX_R / 16))) {
+                launches.push_back(cur);
+                cur = Launch{{}, {}, t, t};
+            }
+            if (std::find(cur.la.begin(), cur.la.end(), ta) == cur.la.end()) cur.la.push_back(ta);
+            if (std::find(cur.lb.begin(), cur.lb.end(), tb) == cur.lb.end()) cur.lb.push_back(tb);
+            cur.t1 = t + 1;
+        }
+        launches.push_back(cur);
+    }
+    const int KLp = (K + 15) / 16 * 16, KRp = (KR + 15) / 16 * 16;
+    std::vector<double> M((size_t)KLp * KRp, 0.0);
     a.N = c->N;
     a.partials = c->d_gram_part;
     a.out = c->d_gram_out;
     a.max_nt = c->gram_nt4 ? GX_MAXB : 2;
     a.max_nt32 = c->gram_nt4 ? GX_MAXB : c->gram_nt32;
-    prof_begin(c, step);
-    if (launch_gramx(dt, a, c->st) != hipSuccess) return LOBPCG_ERR_HIP;
-    prof_end(c);
-    {
-        // the columns of each array that some tile reads, once
-        std::vector<char> used(GX_MAX_ARR, 0);
+    const bool single = launches.size() == 1 && K <= GX_MAX_L && KR <= GX_MAX_R;
+    for (const Launch &L : launches) {
+        // the launch's Lm / Rm: its 16-column blocks, in order; a partial last
+        // block is padded with copies of its first column (results unused)
+        std::vector<int> gta, gtb;   // global block of each local tile
+        if (single) {
+            a.KL = K;
+            a.KR = KR;
+            std::copy(lmap.begin(), lmap.end(), a.lmap);
+            std::copy(rmap.begin(), rmap.end(), a.rmap);
+        } else {
+            a.KL = 16 * (int)L.la.size();
+            a.KR = 16 * (int)L.lb.size();
+            for (int u = 0; u < (int)L.la.size(); u++)
+                for (int v = 0; v < 16; v++) {
+                    const int i = 16 * L.la[u] + v;
+                    a.lmap[16 * u + v] = lmap[i < K ? i : 16 * L.la[u]];
+                }
+            for (int u = 0; u < (int)L.lb.size(); u++)
+                for (int v = 0; v < 16; v++) {
+                    const int j = 16 * L.lb[u] + v;
+                    a.rmap[16 * u + v] = rmap[j < KR ? j : 16 * L.lb[u]];
+                }
+        }
+        a.ntiles = L.t1 - L.t0;
         for (int t = 0; t < a.ntiles; t++) {
-            for (int i = 16 * a.ta[t]; i < std::min(K, 16 * a.ta[t] + 16); i++) used[a.lmap[i] >> 8] = 1;
-            for (int j = 16 * a.tb[t]; j < std::min(KR, 16 * a.tb[t] + 16); j++) used[a.rmap[j] >> 8] = 1;
+            const int ta = tiles[L.t0 + t] >> 8, tb = tiles[L.t0 + t] & 255;
+            gta.push_back(ta);
+            gtb.push_back(tb);
+            a.ta[t] = single ? ta : (int)(std::find(L.la.begin(), L.la.end(), ta) - L.la.begin());
+            a.tb[t] = single ? tb : (int)(std::find(L.lb.begin(), L.lb.end(), tb) - L.lb.begin());
         }
-        double ncols = 0.0;
-        for (int b = 0; b < GX_MAX_ARR; b++)
-            if (used[b]) ncols += w[b % 3];
-        add_bytes(c, step, ncols * c->N * esize(dt));
+        prof_begin(c, step);
+        if (launch_gramx(dt, a, c->st) != hipSuccess) return LOBPCG_ERR_HIP;
+        prof_end(c);
+        if (single) {
+            // the columns of each array that some tile reads, once
+            std::vector<char> used(GX_MAX_ARR, 0);
+            for (int t = 0; t < a.ntiles; t++) {
+                for (int i = 16 * a.ta[t]; i < std::min(K, 16 * a.ta[t] + 16); i++) used[a.lmap[i] >> 8] = 1;
+                for (int j = 16 * a.tb[t]; j < std::min(KR, 16 * a.tb[t] + 16); j++) used[a.rmap[j] >> 8] = 1;
+            }
+            double ncols = 0.0;
+            for (int b = 0; b < GX_MAX_ARR; b++)
+                if (used[b]) ncols += w[b % 3];
+            add_bytes(c, step, ncols * c->N * esize(dt));
+        } else {
+            // the distinct columns this launch reads
+            std::vector<unsigned short> cl(a.lmap, a.lmap + a.KL);
+            cl.insert(cl.end(), a.rmap, a.rmap + a.KR);
+            std::sort(cl.begin(), cl.end());
+            cl.erase(std::unique(cl.begin(), cl.end()), cl.end());
+            add_bytes(c, step, (double)cl.size() * c->N * esize(dt));
+        }
+        HIPCHK(hipMemcpyAsync(h, c->d_gram_out, (size_t)a.ntiles * 256 * 8, hipMemcpyDeviceToHost, c->st));
+        int s = sync(c);
+        if (s) return s;
+        // tiles -> dense Lm^T Rm (entry e = r*64 + lane of the MFMA accumulator)
+        for (int t = 0; t < a.ntiles; t++)
+            for (int e = 0; e < 256; e++) {
+                const int r = e / 64, lane = e % 64;
+                const int row = dt == DT_F32 ? 4 * (lane / 16) + r : lane / 16 + 4 * r;
+                M[(size_t)(16 * gta[t] + row) * KRp + 16 * gtb[t] + lane % 16] = h[(size_t)t * 256 + e];
+            }
     }
-    HIPCHK(hipMemcpyAsync(h, c->d_gram_out, (size_t)a.ntiles * 256 * 8, hipMemcpyDeviceToHost, c->st));
-    int s = sync(c);
-    if (s) return s;
-    // tiles -> dense Lm^T Rm (entry e = r*64 + lane of the MFMA accumulator)
-    const int KLp = (K + 15) / 16 * 16, KRp = (KR + 15) / 16 * 16;
-    std::vector<double> M((size_t)KLp * KRp, 0.0);
-    for (int t = 0; t < a.ntiles; t++)
-        for (int e = 0; e < 256; e++) {
-            const int r = e / 64, lane = e % 64;
-            const int row = dt == DT_F32 ? 4 * (lane / 16) + r : lane / 16 + 4 * r;
-            M[(size_t)(16 * a.ta[t] + row) * KRp + 16 * a.tb[t] + lane % 16] = h[(size_t)t * 256 + e];
-        }
     SS.assign((size_t)K * K, 0.0);
     if (SAS) SAS->assign((size_t)K * K, 0.0);
     for (const Want &q : want) {
@@ -467,47 +525,117 @@ struct MV {
 
 int mv(lobpcg_ctx *c, int dt, const MV &q, const double *C, int step)
 {
-    MVArgs a;
     int K = 0;
-    for (int s2 = 0; s2 < 2; s2++)
-        for (int i = 0; i < 3; i++) a.in[s2][i] = q.in[s2][i];
-    for (int i = 0; i < 3; i++) {
-        a.ld[i] = q.ld[i];
-        a.k[i] = i < q.nin ? q.k[i] : 0;
-        a.cols[i] = q.cols[i];
-        K += a.k[i];
+    bool wide = q.kout > MV_PIECE;
+    for (int i = 0; i < q.nin; i++) {
+        K += q.k[i];
+        wide = wide || q.ld[i] > MV_PIECE || q.k[i] > MV_PIECE;
     }
-    a.nin = q.nin;
+    auto account = [&](int kout) {
+        const int nout = q.opos ? std::min(q.nout, kout) : kout;
+        double cols = (double)K * q.nside + (q.add ? kout : 0);
+        cols += (double)q.nside * ((q.out[0] ? nout : 0) + (q.out2[0] ? kout : 0));
+        if (q.resid && q.Wout) cols += std::min(q.nW, kout);
+        add_bytes(c, step, cols * c->N * esize(dt));
+    };
+    MVArgs a;
     a.nside = q.nside;
-    a.kout = q.kout;
-    a.add = q.add;
-    for (int s2 = 0; s2 < 2; s2++) {
-        a.out[s2] = q.out[s2];
-        a.out2[s2] = q.out2[s2];
-    }
-    a.opos = q.opos;
-    a.nout = q.nout;
+    a.N = c->N;
+    a.variant = c->mv_variant;
+    a.partials = q.resid ? c->d_mv_part : nullptr;
+    a.sums = q.resid ? c->d_res_out : nullptr;
     a.theta = q.theta;
     a.wpos = q.wpos;
     a.Wout = q.Wout;
     a.nW = q.nW;
-    a.partials = q.resid ? c->d_mv_part : nullptr;
-    a.sums = q.resid ? c->d_res_out : nullptr;
-    a.N = c->N;
-    a.variant = c->mv_variant;
-    int s = upload_coef(c, dt, C, K, q.kout, &a.C);
-    if (s) return s;
-    prof_begin(c, step);
-    hipError_t e = launch_mv(dt, a, c->st);
-    prof_end(c);
-    {
-        const int nout = q.opos ? q.nout : q.kout;
-        double cols = (double)K * q.nside + (q.add ? q.kout : 0);
-        cols += (double)q.nside * ((q.out[0] ? nout : 0) + (q.out2[0] ? q.kout : 0));
-        if (q.resid && q.Wout) cols += q.nW;
-        add_bytes(c, step, cols * c->N * esize(dt));
+    if (!wide) {
+        for (int s2 = 0; s2 < 2; s2++)
+            for (int i = 0; i < 3; i++) a.in[s2][i] = q.in[s2][i];
+        for (int i = 0; i < 3; i++) {
+            a.ld[i] = q.ld[i];
+            a.k[i] = i < q.nin ? q.k[i] : 0;
+            a.cols[i] = q.cols[i];
+        }
+        a.nin = q.nin;
+        a.kout = q.kout;
+        a.add = q.add;
+        for (int s2 = 0; s2 < 2; s2++) {
+            a.out[s2] = q.out[s2];
+            a.out2[s2] = q.out2[s2];
+        }
+        a.opos = q.opos;
+        a.nout = q.nout;
+        int s = upload_coef(c, dt, C, K, q.kout, &a.C);
+        if (s) return s;
+        prof_begin(c, step);
+        hipError_t e = launch_mv(dt, a, c->st);
+        prof_end(c);
+        account(q.kout);
+        return e == hipSuccess ? LOBPCG_OK : LOBPCG_ERR_HIP;
     }
-    return e == hipSuccess ? LOBPCG_OK : LOBPCG_ERR_HIP;
+    // Wide blocks: each input split into pieces of at most MV_PIECE columns
+    // (a column range, or a range of its column list), the outputs computed
+    // MV_PIECE (or 16) columns per launch.  The pieces keep the row order of C.
+    int np = 0, n0 = 0;
+    for (int i = 0; i < q.nin; i++)
+        for (int off = 0; off < q.k[i]; off += MV_PIECE) {
+            if (np >= MV_MAX_IN) return LOBPCG_ERR_ARG;
+            for (int s2 = 0; s2 < 2; s2++) a.in[s2][np] = q.in[s2][i];
+            a.ld[np] = q.ld[i];
+            a.k[np] = std::min(MV_PIECE, q.k[i] - off);
+            a.cols[np] = q.cols[i] ? q.cols[i] + off : nullptr;
+            a.coff[np] = q.cols[i] ? 0 : off;
+            if (i == 0) n0++;
+            np++;
+        }
+    a.nin = np;
+    a.n0 = n0;
+    const int chunk = mv_wide_chunk(dt, np, a.k);
+    if (!chunk) return LOBPCG_ERR_ARG;
+    // the output columns of out[] through a position list (identity if none)
+    const int *opos = q.opos;
+    int nout = q.nout;
+    if (!opos && (q.out[0] || q.out[1])) {
+        std::vector<int> id(q.kout);
+        for (int j = 0; j < q.kout; j++) id[j] = j;
+        int s2 = upload_cols(c, id, &opos);
+        if (s2) return s2;
+        nout = q.kout;
+    }
+    const size_t es = esize(dt);
+    // the column chunks of C one after another (K x kc each), in one upload
+    std::vector<double> Cs((size_t)K * q.kout);
+    for (int c0 = 0; c0 < q.kout; c0 += chunk) {
+        const int kc = std::min(chunk, q.kout - c0);
+        for (int r = 0; r < K; r++)
+            for (int j = 0; j < kc; j++) Cs[(size_t)K * c0 + (size_t)r * kc + j] = C[(size_t)r * q.kout + c0 + j];
+    }
+    const void *dC;
+    int s = upload_coef(c, dt, Cs.data(), K, q.kout, &dC);
+    if (s) return s;
+    for (int c0 = 0; c0 < q.kout; c0 += chunk) {
+        const int kc = std::min(chunk, q.kout - c0);
+        a.C = (const char *)dC + (size_t)K * c0 * es;
+        a.kout = kc;
+        a.ld2 = q.kout;
+        a.sums_ld = q.kout;
+        a.add = q.add ? (const char *)q.add + c0 * es : nullptr;
+        for (int s2 = 0; s2 < 2; s2++) {
+            a.out[s2] = q.out[s2];
+            a.out2[s2] = q.out2[s2] ? (char *)q.out2[s2] + c0 * es : nullptr;
+        }
+        a.opos = opos ? opos + c0 : nullptr;
+        a.nout = nout;
+        a.theta = q.theta ? q.theta + c0 : nullptr;
+        a.wpos = q.wpos ? q.wpos + c0 : nullptr;
+        a.sums = q.resid ? c->d_res_out + c0 : nullptr;
+        prof_begin(c, step);
+        hipError_t e = launch_mv(dt, a, c->st);
+        prof_end(c);
+        account(kc);
+        if (e != hipSuccess) return LOBPCG_ERR_HIP;
+    }
+    return LOBPCG_OK;
 }
 
 int upload_doubles(lobpcg_ctx *c, const std::vector<double> &v, const double **dptr)
@@ -711,38 +839,43 @@ std::vector<int> positions(const std::vector<int> &sub, const std::vector<int> &
 int constrain(lobpcg_ctx *c, const void *V, int k, void *dst, int step)
 {
     const int ny = c->ny;
-    GramXArgs a;
-    for (int b = 0; b < GX_MAX_ARR; b++) a.arr[b] = nullptr, a.ld[b] = 1;
-    a.arr[0] = c->Y, a.ld[0] = ny;
-    a.arr[1] = V, a.ld[1] = k;
-    a.KL = ny;
-    a.KR = k;
-    for (int i = 0; i < ny; i++) a.lmap[i] = (unsigned short)i;
-    for (int j = 0; j < k; j++) a.rmap[j] = (unsigned short)((1 << 8) | j);
-    const int TL = (ny + 15) / 16, TR = (k + 15) / 16;
-    a.ntiles = TL * TR;
-    for (int t = 0; t < a.ntiles; t++) a.ta[t] = t / TR, a.tb[t] = t % TR;
-    a.N = c->N;
-    a.partials = c->d_gram_part;
-    a.out = c->d_gram_out;
-    a.max_nt = 2;
-    a.max_nt32 = c->gram_nt32;
-    prof_begin(c, step);
-    if (launch_gramx(DT_F64, a, c->st) != hipSuccess) return LOBPCG_ERR_HIP;
-    prof_end(c);
-    add_bytes(c, step, (double)(ny + k) * c->N * 8.0);
-    double *h = (double *)(c->h_pin + c->h_gram_off);
-    HIPCHK(hipMemcpyAsync(h, c->d_gram_out, (size_t)a.ntiles * 256 * 8, hipMemcpyDeviceToHost, c->st));
-    int s = sync(c);
-    if (s) return s;
-    // Y^T V (ny x k) from the tiles (FP64 accumulator layout: row l/16 + 4r)
+    // Y^T V (ny x k) in launches of at most GX_MAX_L rows
     std::vector<double> G((size_t)ny * k);
-    for (int t = 0; t < a.ntiles; t++)
-        for (int e = 0; e < 256; e++) {
-            const int r = e / 64, lane = e % 64;
-            const int i = 16 * a.ta[t] + lane / 16 + 4 * r, j = 16 * a.tb[t] + lane % 16;
-            if (i < ny && j < k) G[(size_t)i * k + j] = h[(size_t)t * 256 + e];
-        }
+    for (int i0 = 0; i0 < ny; i0 += GX_MAX_L) {
+        const int nr = std::min(GX_MAX_L, ny - i0);
+        GramXArgs a;
+        for (int b = 0; b < GX_MAX_ARR; b++) a.arr[b] = nullptr, a.ld[b] = 1;
+        a.arr[0] = c->Y, a.ld[0] = ny;
+        a.arr[1] = V, a.ld[1] = k;
+        a.KL = nr;
+        a.KR = k;
+        for (int i = 0; i < nr; i++) a.lmap[i] = (unsigned short)(i0 + i);
+        for (int j = 0; j < k; j++) a.rmap[j] = (unsigned short)((1 << 8) | j);
+        const int TL = (nr + 15) / 16, TR = (k + 15) / 16;
+        a.ntiles = TL * TR;
+        if (k > GX_MAX_R || a.ntiles > GX_MAX_TILES) return LOBPCG_ERR_ARG;
+        for (int t = 0; t < a.ntiles; t++) a.ta[t] = t / TR, a.tb[t] = t % TR;
+        a.N = c->N;
+        a.partials = c->d_gram_part;
+        a.out = c->d_gram_out;
+        a.max_nt = 2;
+        a.max_nt32 = c->gram_nt32;
+        prof_begin(c, step);
+        if (launch_gramx(DT_F64, a, c->st) != hipSuccess) return LOBPCG_ERR_HIP;
+        prof_end(c);
+        add_bytes(c, step, (double)(nr + k) * c->N * 8.0);
+        double *h = (double *)(c->h_pin + c->h_gram_off);
+        HIPCHK(hipMemcpyAsync(h, c->d_gram_out, (size_t)a.ntiles * 256 * 8, hipMemcpyDeviceToHost, c->st));
+        int s = sync(c);
+        if (s) return s;
+        // FP64 accumulator layout: row l/16 + 4r
+        for (int t = 0; t < a.ntiles; t++)
+            for (int e = 0; e < 256; e++) {
+                const int r = e / 64, lane = e % 64;
+                const int i = 16 * a.ta[t] + lane / 16 + 4 * r, j = 16 * a.tb[t] + lane % 16;
+                if (i < nr && j < k) G[(size_t)(i0 + i) * k + j] = h[(size_t)t * 256 + e];
+            }
+    }
     if (!all_finite(G)) return LOBPCG_ERR_NONFINITE;
     // C = (RY^T RY)^-1 G: forward then back substitution, column by column
     std::vector<double> C(G);
@@ -1441,6 +1574,7 @@ int lobpcg_setup(lobpcg_ctx **out, const lobpcg_op *A, const lobpcg_op *B, const
     c->gram_nt4 = 0;
     c->gram_nt32 = 2;
     c->fp32_explicit = true;
+    c->fp64_explicit = false;
     c->fold = true;
     c->Y = nullptr;
     c->ny = 0;
@@ -1486,6 +1620,7 @@ int lobpcg_set_option(lobpcg_ctx *c, int key, double v)
     case LOBPCG_OPT_REACTIVATE: c->reactivate = v != 0; return LOBPCG_OK;
     case LOBPCG_OPT_FP32_EXPLICIT_GRAM: c->fp32_explicit = v != 0; return LOBPCG_OK;
     case LOBPCG_OPT_FOLD_CHOLQR: c->fold = v != 0; return LOBPCG_OK;
+    case LOBPCG_OPT_FP64_EXPLICIT_GRAM: c->fp64_explicit = v != 0; return LOBPCG_OK;
     case LOBPCG_OPT_KERNELS:
         if (v < 0 || v > 31 || ((int)v & 3) == 3) return LOBPCG_ERR_ARG;
         c->mv_variant = (int)v & 3;
@@ -1588,7 +1723,8 @@ static int solve_impl(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, con
             ps.cur = 0;
             s = init_phase(c, A, DT_F64, c->b64, ps, false, true);
             if (s == LOBPCG_OK)
-                s = run_phase(c, A, DT_F64, c->b64, ps, tol, normA, maxit, iters, h_hist, false, false, outcome);
+                s = run_phase(c, A, DT_F64, c->b64, ps, tol, normA, maxit, iters, h_hist, c->fp64_explicit, false,
+                              outcome);
         }
     } else {
         if (ny) {
@@ -1600,7 +1736,8 @@ static int solve_impl(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, con
         }
         s = init_phase(c, A, DT_F64, c->b64, ps, true, false);
         if (s == LOBPCG_OK)
-            s = run_phase(c, A, DT_F64, c->b64, ps, tol, normA, maxit, iters, h_hist, false, false, outcome);
+            s = run_phase(c, A, DT_F64, c->b64, ps, tol, normA, maxit, iters, h_hist, c->fp64_explicit, false,
+                          outcome);
     }
     *h_iters = iters;
     c->stats.iters_total = iters;

@@ -24,6 +24,7 @@ F64, F32 = 0, 1
 OPT_SWITCH_TOL, OPT_STALL_WINDOW, OPT_STALL_FACTOR, OPT_PROFILE, OPT_REACTIVATE, OPT_KERNELS = 0, 1, 2, 3, 4, 5
 OPT_FP32_EXPLICIT_GRAM = 6
 OPT_FOLD_CHOLQR = 7
+OPT_FP64_EXPLICIT_GRAM = 8
 STEP_NAMES = ["residual", "precond", "ortho", "apply_A", "gram", "rr_host", "update", "other"]
 
 

@@ -60,7 +60,7 @@ def test_workspace_bytes_scales_with_problem():
 @pytest.mark.parametrize("dims,levels,m,prec,want", [
     ((4, 4, 4), None, 0, 0, L.ERR_ARG),            # m < 1
     ((3, 3, 3), None, 10, 0, L.ERR_ARG),           # 3m > N
-    ((16, 16, 16), None, 33, 0, L.ERR_ARG),        # beyond the supported block size
+    ((16, 16, 16), None, 129, 0, L.ERR_ARG),       # beyond the supported block size
     ((16, 16, 16), 6, 4, 0, L.ERR_ARG),            # too many levels for the grid
     ((16, 16, 16), 2, 4, 7, L.ERR_ARG),            # bad precision
     ((0, 16, 16), None, 4, 0, L.ERR_ARG),          # empty grid

@@ -253,6 +253,61 @@ def test_combine(N, ks, kout, use_cols, prec, variant):
     np.testing.assert_allclose(out, ref, rtol=0, atol=tol * (np.abs(np.hstack(sel)) @ np.abs(C)).max())
 
 
+# blocks wider than 32 columns: the inputs go to the kernels in pieces of at
+# most 32 columns and the outputs in chunks of 32 (or 16) columns
+@pytest.mark.parametrize("N,ks,kout,use_cols", [(20011, (50,), 50, False), (9001, (64, 40, 33), 64, True),
+                                                (5003, (100, 100, 100), 100, False), (3001, (33, 7), 40, False),
+                                                (777, (128,), 3, True), (4099, (5, 70), 128, False)])
+@pytest.mark.parametrize("prec", [L.FP64, L.MIXED])
+def test_combine_wide(N, ks, kout, use_cols, prec):
+    ctx = ctx_for((N, 1, 1), min(128, N // 3), None, L.MIXED)
+    dtype = torch.float64 if prec == L.FP64 else torch.float32
+    rng = np.random.default_rng(N + kout)
+    ld = [k + (3 if use_cols and k + 3 <= 128 else 0) for k in ks]
+    ins = [synth.random_block(N, l, seed=i + 200).astype(np.float32 if prec == L.MIXED else np.float64)
+           for i, l in enumerate(ld)]
+    cols = [np.sort(rng.choice(l, size=k, replace=False)) for l, k in zip(ld, ks)] if use_cols else None
+    C = rng.standard_normal((sum(ks), kout))
+    add = synth.random_block(N, kout, seed=98).astype(ins[0].dtype)
+    out = host(L.lobpcg_combine(ctx, [dev(x, dtype) for x in ins], C, kout, cols=cols, add=dev(add, dtype)))
+    sel = [x.astype(np.float64)[:, c] if cols else x.astype(np.float64) for x, c in zip(ins, cols or [None] * len(ins))]
+    ref = np.hstack(sel) @ (C.astype(np.float32).astype(np.float64) if prec == L.MIXED else C) + add
+    tol = 1e-14 if prec == L.FP64 else 4 * sum(ks) * EPS32
+    np.testing.assert_allclose(out, ref, rtol=0, atol=tol * (np.abs(np.hstack(sel)) @ np.abs(C)).max())
+
+
+@pytest.mark.parametrize("N,widths", [(20011, (50, 50, 50)), (5003, (100, 100, 100)), (3001, (97, 45, 13)),
+                                      (9001, (128,)), (7777, (40, 33))])
+@pytest.mark.parametrize("prec", [L.FP64, L.MIXED])
+@pytest.mark.parametrize("paper", [False, True])
+def test_gram_wide(N, widths, prec, paper):
+    """Gram products wider than one launch's tables: the tiles are spread over
+    several launches."""
+    if paper and len(widths) < 2:
+        pytest.skip("the paper's form needs two blocks")
+    ctx = ctx_for((N, 1, 1), min(128, N // 3), None, L.MIXED)
+    npdt, tdt = (np.float64, torch.float64) if prec == L.FP64 else (np.float32, torch.float32)
+    S = [synth.random_block(N, w, seed=220 + i).astype(npdt) for i, w in enumerate(widths)]
+    AS = [synth.random_block(N, w, seed=240 + i).astype(npdt) for i, w in enumerate(widths)]
+    SS, SAS = L.lobpcg_gram(ctx, [dev(x, tdt) for x in S], [dev(a, tdt) for a in AS], paper_form=paper)
+    Sf, ASf = np.hstack(S).astype(np.float64), np.hstack(AS).astype(np.float64)
+    blk = np.concatenate([np.full(w, b) for b, w in enumerate(widths)])
+    wantB = blk[:, None] != blk[None, :] if paper else np.ones((len(blk), len(blk)), bool)
+    wantA = ~((blk[:, None] == 0) & (blk[None, :] == 0)) if paper else np.ones_like(wantB)
+    if prec == L.FP64:
+        tolB = 1e-13 * N * np.ones_like(SS)
+        tolA = 1e-13 * N * np.ones_like(SS)
+    else:
+        tolB = 64 * EPS32 * (np.abs(Sf).T @ np.abs(Sf)) + 1e-30
+        tolA = 64 * EPS32 * (np.abs(Sf).T @ np.abs(ASf)) + 1e-30
+    assert np.all(np.abs(SS - Sf.T @ Sf)[wantB] <= tolB[wantB])
+    np.testing.assert_array_equal(SS[~wantB], 0.0)
+    iu = np.triu(np.ones_like(wantA), 0) & wantA
+    assert np.all(np.abs(SAS - Sf.T @ ASf)[iu] <= tolA[iu])
+    np.testing.assert_array_equal(SAS[~wantA], 0.0)
+    np.testing.assert_array_equal(SAS, SAS.T)
+
+
 # ---------------------------------------------------------------- residual and norms (steps 7-8)
 
 @pytest.mark.parametrize("N,m,J", [(4096, 4, [0, 1, 2, 3]), (70001, 32, list(range(0, 32, 3))), (999, 7, [6]),
