@@ -28,6 +28,11 @@ Block-size study (Section 4, LOBPCG performance vs block size, m = 1..98 on
 the 128^3 Laplacian to tol 1e-8): python bench.py --sweep-m 1,2,4,...,98
 prints one JSON line per (m, precision) with the solve time, the iteration
 counts and the time of each step class; the headline line is not printed.
+
+Problem-size study: python bench.py --sweep-n 48,64,...,464 solves the n^3
+Laplacian at m=8 (and m=32 up to n=256), mixed and FP64, one JSON line each.
+Seed spread: python bench.py --seeds 2,3,4,5,6 solves the headline problem
+from each start block, one JSON line each and a line of medians.
 """
 import argparse
 import json
@@ -83,6 +88,10 @@ def main():
                     help="skip the extra solve with per-step HIP-event timing (then the roofline is the stencil's)")
     ap.add_argument("--sweep-m", default=None,
                     help="comma-separated block sizes: the block-size study instead of the headline run")
+    ap.add_argument("--sweep-n", default=None,
+                    help="comma-separated grid sizes: the problem-size study instead of the headline run")
+    ap.add_argument("--seeds", default=None,
+                    help="comma-separated start-block seeds: the seed spread instead of the headline run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see the design notes on how "
@@ -106,6 +115,12 @@ def main():
     if args.sweep_m:
         sweep_block_size(args, L, synth, torch, dev)
         return
+    if args.sweep_n:
+        sweep_problem_size(args, L, synth, torch, dev)
+        return
+    if args.seeds:
+        seed_spread(args, L, synth, torch, dev)
+        return
     n, m, levels, tol = args.n, args.m, args.levels, args.tol
     dims = (n, n, n)
     N = n ** 3
@@ -115,7 +130,11 @@ def main():
     exact, _ = closed_form.smallest(*dims, m)
 
     def run(prec, K, W):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
         ctx = L.lobpcg_setup(A, T, m, prec, device=dev)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - ts
         res = None
         for _ in range(W):
             res = L.lobpcg_solve(ctx, X0, tol, args.maxit)
@@ -146,7 +165,7 @@ def main():
         r = results[-1]
         acc = {"max_rel_err_closed_form": float(np.max(np.abs(r.lam / exact - 1))),
                "max_resid": float(r.resid.max()), "iters": r.iters,
-               "iters_fp32": stats["iters_fp32"], "iters_fp64": stats["iters_fp64"]}
+               "iters_fp32": stats["iters_fp32"], "iters_fp64": stats["iters_fp64"], "setup_s": setup_s}
         del ctx
         torch.cuda.empty_cache()
         return dt, acc, steps, r
@@ -224,6 +243,90 @@ def main():
         out["cpu_baseline"] = cpu_baseline(dims, m, levels, X0.cpu().numpy(),
                                            fp64["iters"] if fp64 else acc_mixed["iters"])
     print(json.dumps(out), flush=True)
+
+
+def levels_for(n):
+    """V-cycle depth of the size studies: halve while the coarsest grid keeps
+    at least 6 points per axis (128 -> 5 levels, 256 -> 6, 464 -> 7)."""
+    levels = 1
+    while (n >> levels) >= 6:
+        levels += 1
+    return levels
+
+
+def timed_solve(L, torch, A, T, m, prec, X0, tol, maxit, dev):
+    """(setup s, solve s, result, stats) for one solve after a 2-iteration
+    warm-up solve on the same context."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx = L.lobpcg_setup(A, T, m, prec, device=dev)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    L.lobpcg_solve(ctx, X0, tol, 2, hist=False, raise_on_error=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = L.lobpcg_solve(ctx, X0, tol, maxit, hist=False, raise_on_error=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = L.lobpcg_get_stats(ctx)
+    del ctx
+    return setup, dt, r, st
+
+
+def sweep_problem_size(args, L, synth, torch, dev):
+    """Time to tol vs grid size (n^3 unknowns) at m = 8, and m = 32 up to
+    n = 256, mixed and FP64."""
+    from oracle import closed_form  # closed form of the spectrum, used only to report accuracy
+    for n in [int(v) for v in args.sweep_n.split(",")]:
+        dims = (n, n, n)
+        N = n ** 3
+        levels = levels_for(n)
+        A, T = L.Op(*dims), L.Precond(levels)
+        for m in ((8, 32) if n <= 256 else (8,)):
+            X0 = torch.from_numpy(synth.x0_uniform(N, m, seed=2)).to(dev)
+            exact, _ = closed_form.smallest(*dims, m)
+            for prec, name in ((L.MIXED, "mixed"), (L.FP64, "fp64")):
+                setup, dt, r, st = timed_solve(L, torch, A, T, m, prec, X0, args.tol, args.maxit, dev)
+                ok = r.status in (L.OK, L.NOT_CONVERGED)
+                print(json.dumps({"sweep": "problem_size", "n": n, "N": N, "m": m, "levels": levels,
+                                  "precision": name, "status": L.status_string(r.status), "setup_s": setup,
+                                  "time_s": dt, "iters": r.iters, "iters_fp32": st["iters_fp32"],
+                                  "iters_fp64": st["iters_fp64"], "ms_per_iter": dt * 1e3 / max(r.iters, 1),
+                                  "unknown_iters_per_s": N * m * r.iters / dt,
+                                  "max_rel_err_closed_form":
+                                      float(np.max(np.abs(r.lam - exact) / exact)) if ok else None,
+                                  "max_resid": float(r.resid.max()) if ok else None}), flush=True)
+                del r
+                torch.cuda.empty_cache()
+            del X0
+
+
+def seed_spread(args, L, synth, torch, dev):
+    """The headline problem from several start blocks: the spread of
+    iteration counts and times that Section 4 reports across random starts."""
+    n, m, levels = args.n, args.m, args.levels
+    dims = (n, n, n)
+    N = n ** 3
+    A, T = L.Op(*dims), L.Precond(levels)
+    times = {"mixed": [], "fp64": []}
+    iters = {"mixed": [], "fp64": []}
+    for seed in [int(v) for v in args.seeds.split(",")]:
+        X0 = torch.from_numpy(synth.x0_uniform(N, m, seed=seed)).to(dev)
+        for prec, name in ((L.MIXED, "mixed"), (L.FP64, "fp64")):
+            setup, dt, r, st = timed_solve(L, torch, A, T, m, prec, X0, args.tol, args.maxit, dev)
+            times[name].append(dt)
+            iters[name].append(r.iters)
+            print(json.dumps({"sweep": "seeds", "n": n, "m": m, "seed": seed, "precision": name,
+                              "status": L.status_string(r.status), "setup_s": setup, "time_s": dt,
+                              "iters": r.iters, "iters_fp32": st["iters_fp32"], "iters_fp64": st["iters_fp64"],
+                              "max_resid": float(r.resid.max()) if r.resid is not None else None}), flush=True)
+            del r
+            torch.cuda.empty_cache()
+        del X0
+    print(json.dumps({"sweep": "seeds", "summary": True,
+                      "median_time_s": {k: float(np.median(v)) for k, v in times.items()},
+                      "min_max_time_s": {k: [min(v), max(v)] for k, v in times.items()},
+                      "min_max_iters": {k: [min(v), max(v)] for k, v in iters.items()}}), flush=True)
 
 
 def sweep_block_size(args, L, synth, torch, dev):
