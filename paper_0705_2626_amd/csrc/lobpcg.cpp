@@ -1079,7 +1079,12 @@ int folded_step(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState
     const double *dtheta;
     s = upload_cols(c, jpos, &djpos);
     if (s) return s;
-    if (nP) {
+    // P_J is all of P, in order, whenever J has not changed since P was
+    // written: then it is read whole (16-byte fragment loads) rather than
+    // through a column list
+    bool p_whole = nP == np;
+    for (int i = 0; i < nP && p_whole; i++) p_whole = ppos[i] == i;
+    if (nP && !p_whole) {
         s = upload_cols(c, ppos, &dppos);
         if (s) return s;
     }
