@@ -52,8 +52,8 @@ HBM_PEAK_GBPS = 8000.0
 # two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy;
 # valid only while the kernel source is the one the counters were taken with.
 TRAFFIC = {
-    "update": {"bytes_per_launch": 17.333e9, "source": "paper_0705_2626_amd/csrc/k_update.hip",
-               "sha1": "e56dc89c5cc953cae557064e89bb1dcf7d507097", "profile": "profiles/lobpcg_mixed_n256_m32_hbm_traffic.md"},
+    "update": {"bytes_per_launch": 17.675e9, "source": "paper_0705_2626_amd/csrc/k_update.hip",
+               "sha1": "23090b686783f1af5c9ab1385c5ed5272fd12606", "profile": "profiles/lobpcg_mixed_n256_m32_hbm_traffic.md"},
 }
 
 
