@@ -834,17 +834,18 @@ static const size_t MVW_MAX_LDS = 64 * 1024 - 256;   // with the kernel's static
 int mv_wide_chunk(int dtype, int nin, const int *k)
 {
     const size_t esz = dtype == DT_F32 ? 4 : 8;
+    if (mvw_lds(4, esz, nin, k) <= MVW_MAX_LDS) return 64;
     if (mvw_lds(2, esz, nin, k) <= MVW_MAX_LDS) return 32;
     if (mvw_lds(1, esz, nin, k) <= MVW_MAX_LDS) return 16;
     return 0;
 }
 
-template <typename T, int NT>
-static hipError_t run_mv(const MVArgs &h, bool wide, hipStream_t st)
+template <typename T>
+static MVDev<T> make_dev(const MVArgs &h, bool &any_wide)
 {
     MVDev<T> a;
     a.K = 0;
-    bool any_wide = false;
+    any_wide = false;
     for (int b = 0; b < MV_MAX_IN; b++) {
         const bool used = b < h.nin;
         for (int s = 0; s < 2; s++) a.in[s][b] = used ? (const T *)h.in[s][b] : nullptr;
@@ -875,17 +876,44 @@ static hipError_t run_mv(const MVArgs &h, bool wide, hipStream_t st)
     a.nW = h.nW;
     a.partials = h.partials;
     a.N = h.N;
+    return a;
+}
+
+// the column sums of the residual, reduced in a fixed order
+static hipError_t mv_reduce(const MVArgs &h, int nb, hipStream_t st)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !h.partials) return e;
+    hipLaunchKernelGGL(mv_reduce_kernel, dim3(2 * h.kout), dim3(256), 0, st, h.partials, nb, 2 * h.kout, h.kout,
+                       h.sums_ld > 0 ? h.sums_ld : h.kout, h.sums);
+    return hipGetLastError();
+}
+
+// blocks wider than MAXW columns (pieces, chunked outputs): mvw_kernel
+template <typename T, int NT>
+static hipError_t run_mvw(const MVArgs &h, hipStream_t st)
+{
+    bool any_wide;
+    MVDev<T> a = make_dev<T>(h, any_wide);
+    const int nb = mv_blocks(h.N);
+    int nsteps = 0;
+    for (int b = 0; b < h.nin; b++) nsteps += (h.k[b] + 3) / 4;
+    const size_t shm = mvf_stage_offset(nsteps, NT, a.K, sizeof(T));
+    hipLaunchKernelGGL((mvw_kernel<T, NT>), dim3(nb), dim3(256), shm, st, a);
+    return mv_reduce(h, nb, st);
+}
+
+template <typename T, int NT>
+static hipError_t run_mv(const MVArgs &h, hipStream_t st)
+{
+    bool any_wide;
+    MVDev<T> a = make_dev<T>(h, any_wide);
     const int NC = NT * 16;
     const int nb = mv_blocks(h.N);
     bool narrow = h.kout <= NARROW;
     for (int b = 0; b < h.nin; b++) narrow = narrow && h.ld[b] <= NARROW;
     const size_t tail = (size_t)NC * 8 + (size_t)16 * 2 * NC * 8 + (size_t)(a.K + 4 + 2 * NC) * sizeof(int);
-    if (wide) {
-        int nsteps = 0;
-        for (int b = 0; b < h.nin; b++) nsteps += (h.k[b] + 3) / 4;
-        const size_t shm = mvf_stage_offset(nsteps, NT, a.K, sizeof(T));
-        hipLaunchKernelGGL((mvw_kernel<T, NT>), dim3(nb), dim3(256), shm, st, a);
-    } else if (h.variant == 0 && narrow) {
+    if (h.variant == 0 && narrow) {
         const size_t shm = (size_t)NARROW * 8 + (size_t)2 * NARROW * 256 * 8 + (size_t)a.K * NARROW * sizeof(T) +
                            (size_t)(a.K + 2 * NARROW) * sizeof(int);
         hipLaunchKernelGGL((mvn_kernel<T>), dim3(nb), dim3(256), shm, st, a);
@@ -903,11 +931,7 @@ static hipError_t run_mv(const MVArgs &h, bool wide, hipStream_t st)
         else
             hipLaunchKernelGGL((mvd_kernel<T, NT>), dim3(nb), dim3(256), shm, st, a);
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !h.partials) return e;
-    hipLaunchKernelGGL(mv_reduce_kernel, dim3(2 * h.kout), dim3(256), 0, st, h.partials, nb, 2 * h.kout, h.kout,
-                       h.sums_ld > 0 ? h.sums_ld : h.kout, h.sums);
-    return hipGetLastError();
+    return mv_reduce(h, nb, st);
 }
 
 hipError_t launch_mv(int dtype, const MVArgs &a, hipStream_t st)
@@ -922,14 +946,20 @@ hipError_t launch_mv(int dtype, const MVArgs &a, hipStream_t st)
         if (a.cols[b] ? a.coff[b] != 0 : a.coff[b] + a.k[b] > a.ld[b]) return hipErrorInvalidValue;
         if (a.ld[b] > MAXW || a.coff[b]) wide = true;
     }
-    if (a.kout < 1 || a.kout > 32) return hipErrorInvalidValue;
+    if (a.kout < 1 || a.kout > (wide ? 64 : 32)) return hipErrorInvalidValue;
     if (a.out2[0] && (a.n0 < 1 || a.n0 > a.nin)) return hipErrorInvalidValue;
     if (a.partials && (a.nside != 2 || !a.out2[0])) return hipErrorInvalidValue;
+    if (wide) {
+        // 16, 32 or 64 output columns per launch, as the coefficients fit LDS
+        const int nt = a.kout > 32 ? 4 : a.kout > 16 ? 2 : 1;
+        if (mv_wide_chunk(dtype, a.nin, a.k) < 16 * nt) return hipErrorInvalidValue;
+        if (dtype == DT_F32)
+            return nt == 4 ? run_mvw<float, 4>(a, st) : nt == 2 ? run_mvw<float, 2>(a, st) : run_mvw<float, 1>(a, st);
+        return nt == 4 ? run_mvw<double, 4>(a, st) : nt == 2 ? run_mvw<double, 2>(a, st) : run_mvw<double, 1>(a, st);
+    }
     const bool two = a.kout > 16;
-    if (wide && !mv_wide_chunk(dtype, a.nin, a.k)) return hipErrorInvalidValue;
-    if (wide && two && mv_wide_chunk(dtype, a.nin, a.k) < 32) return hipErrorInvalidValue;
-    if (dtype == DT_F32) return two ? run_mv<float, 2>(a, wide, st) : run_mv<float, 1>(a, wide, st);
-    return two ? run_mv<double, 2>(a, wide, st) : run_mv<double, 1>(a, wide, st);
+    if (dtype == DT_F32) return two ? run_mv<float, 2>(a, st) : run_mv<float, 1>(a, st);
+    return two ? run_mv<double, 2>(a, st) : run_mv<double, 1>(a, st);
 }
 
 }  // namespace lobpcg

@@ -93,7 +93,7 @@ hipError_t launch_mv(int dtype, const MVArgs &a, hipStream_t st);
 // widest output chunk (32, 16, or 0 if none fits in LDS) of the wide kernel
 // for input pieces of the given widths
 int mv_wide_chunk(int dtype, int nin, const int *k);
-static const int MV_PIECE = 32;     // columns per input piece and per output chunk
+static const int MV_PIECE = 32;     // columns per input piece (and the widest non-wide output)
 
 // out[p][jj] = in[p][map[jj]] for jj < nout (in: N x ld)
 hipError_t launch_gather_cols(int dtype, long long N, const void *in, int ld, const int *map, int nout, void *out,
