@@ -36,19 +36,24 @@ def check_orthonormal(X, atol):
     np.testing.assert_allclose(G, np.eye(G.shape[0]), rtol=0, atol=atol)
 
 
-def test_n128_m16_fp64_multigrid():
-    """FP64, n=128 (N=2,097,152), m=16, V(2,2) with 5 levels, tol 1e-8.  The
-    block edge cuts the 6-fold group lambda_12..17: eigenvalues still agree
-    with the closed form; the cut group's vectors are checked by residual."""
-    n, m, tol = 128, 16, 1e-8
+@pytest.mark.parametrize("tol,rtol", [(1e-8, 1e-8), (1.5e-9, 1e-10)])
+def test_n128_m16_fp64_multigrid(tol, rtol):
+    """FP64, n=128 (N=2,097,152), m=16, V(2,2) with 5 levels.  The block edge
+    cuts the 6-fold group lambda_12..17: eigenvalues still agree with the
+    closed form; the cut group's vectors are checked by residual.  The bound
+    |lambda_i - theta_i| <= (rho ||A||)^2 / gap_i (gap_i: distance to the
+    nearest other eigenvalue, 1.8e-3 for the cut group) allows up to 5e-9
+    relative at rho = 1e-8 and keeps every pair within 1e-10 at rho =
+    1.5e-9, the FP64 agreement asked of the solver (measured: 4e-12 and
+    9e-13)."""
+    n, m = 128, 16
     N = n ** 3
     ctx = L.lobpcg_setup(L.Op(n, n, n), L.Precond(5), m, L.FP64)
     r = L.lobpcg_solve(ctx, dev(synth.x0_uniform(N, m, seed=2)), tol, 300)
     exact, _ = closed_form.smallest(n, n, n, m)
     assert r.status == L.OK
     assert r.resid.max() <= tol
-    # |lambda - theta| <= ||r||^2 / gap, ||r|| = tol * ||A|| = 1.2e-7, gap >= 4e-4
-    np.testing.assert_allclose(r.lam, exact, rtol=1e-8)
+    np.testing.assert_allclose(r.lam, exact, rtol=rtol)
     check_orthonormal(r.X, 1e-10)
     del ctx, r
     release()
