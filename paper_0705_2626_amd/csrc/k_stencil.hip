@@ -39,7 +39,7 @@ __device__ __forceinline__ vec<T, V> lap(const vec<T, V> &c, const vec<T, V> &zm
 // the wave must call this (the shuffles are wave-wide).
 template <typename T, int V>
 __device__ __forceinline__ void x_neighbours(const vec<T, V> &cur, const T *__restrict__ u, i64 i, i64 sx,
-                                             int x, int nx, int L, vec<T, V> &xm, vec<T, V> &xp)
+                                             int x, int nx, int L, bool row_ok, vec<T, V> &xm, vec<T, V> &xp)
 {
     const int lane = threadIdx.x & 63;
     const bool in_m = lane >= L, in_p = lane + L < 64;
@@ -48,9 +48,11 @@ __device__ __forceinline__ void x_neighbours(const vec<T, V> &cur, const T *__re
         xm.v[q] = __shfl(cur.v[q], in_m ? lane - L : lane, 64);
         xp.v[q] = __shfl(cur.v[q], in_p ? lane + L : lane, 64);
     }
-    if (x == 0) xm = vzero<T, V>();
+    // a row outside the grid (only the last rows of a thread's row block)
+    // has no neighbours to load: its results are not stored
+    if (x == 0 || !row_ok) xm = vzero<T, V>();
     else if (!in_m) xm = vload<T, V>(u + i - sx);
-    if (x + 1 == nx) xp = vzero<T, V>();
+    if (x + 1 == nx || !row_ok) xp = vzero<T, V>();
     else if (!in_p) xp = vload<T, V>(u + i + sx);
 }
 
@@ -59,14 +61,15 @@ __device__ __forceinline__ void x_neighbours(const vec<T, V> &cur, const T *__re
 // EPI_RESID : out = b - s * L7 u
 // EPI_JACOBI2: two sweeps from zero with right-hand side u:
 //             x1 = c1 u, out = x1 + c1 (u - s L7 x1)
-template <typename T, int V, int EPI>
+template <typename T, int V, int EPI, int R>
 __global__ void __launch_bounds__(256) stencil7_kernel(int nx, int ny, int nz, int L, int zchunk,
                                                        const T *__restrict__ u, T *__restrict__ out,
                                                        const T *__restrict__ b, T s, T c1)
 {
     const unsigned nbx = gridDim.x;
     const unsigned bx = xcd_remap(blockIdx.x, nbx);
-    const i64 plane = (i64)nx * ny * L;   // threads per z-plane
+    const int nyr = (ny + R - 1) / R;                  // row blocks of R rows
+    const i64 plane = (i64)nx * nyr * L;               // threads per z-plane
     const i64 t0 = (i64)bx * blockDim.x + threadIdx.x;
     // lanes past the plane stay (on the plane's last item, without storing):
     // every lane of a wave takes part in the x-neighbour exchange
@@ -75,40 +78,61 @@ __global__ void __launch_bounds__(256) stencil7_kernel(int nx, int ny, int nz, i
     const int c = (int)(t % L);
     const i64 pxy = t / L;
     const int x = (int)(pxy % nx);
-    const int y = (int)(pxy / nx);
+    const int y0 = (int)(pxy / nx) * R;
     const int z0 = blockIdx.y * zchunk;
     const int z1 = min(nz, z0 + zchunk);
     const i64 sx = (i64)L * V, sy = (i64)nx * L * V, sz = (i64)nx * ny * L * V;   // element strides
-    const i64 base = (pxy * L + c) * V;
+    const i64 base = (((i64)y0 * nx + x) * L + c) * V;                           // row y0
     const vec<T, V> zero = vzero<T, V>();
-    vec<T, V> prev = z0 > 0 ? vload<T, V>(u + base + (z0 - 1) * sz) : zero;
-    vec<T, V> cur = vload<T, V>(u + base + z0 * sz);
+    // rows y0 .. y0+R-1 (those inside the grid) marched in z together: the
+    // y-neighbours between them come from registers, only rows y0-1 and
+    // y0+R are loaded
+    bool rok[R];
+    vec<T, V> prev[R], cur[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        rok[r] = y0 + r < ny;
+        const i64 br = base + r * sy;
+        prev[r] = (rok[r] && z0 > 0) ? vload<T, V>(u + br + (z0 - 1) * sz) : zero;
+        cur[r] = rok[r] ? vload<T, V>(u + br + z0 * sz) : zero;
+    }
     for (int z = z0; z < z1; z++) {
         const i64 i = base + z * sz;
-        vec<T, V> next = (z + 1 < nz) ? vload<T, V>(u + i + sz) : zero;
-        vec<T, V> xm, xp;
-        x_neighbours<T, V>(cur, u, i, sx, x, nx, L, xm, xp);
-        vec<T, V> ym = y > 0 ? vload<T, V>(u + i - sy) : zero;
-        vec<T, V> yp = y + 1 < ny ? vload<T, V>(u + i + sy) : zero;
-        vec<T, V> au = lap<T, V>(cur, prev, next, xm, xp, ym, yp);
-        vec<T, V> o;
-        if (EPI == EPI_APPLY) {
+        vec<T, V> next[R];
 #pragma unroll
-            for (int q = 0; q < V; q++) o.v[q] = s * au.v[q];
-        } else if (EPI == EPI_JACOBI2) {
+        for (int r = 0; r < R; r++) next[r] = (rok[r] && z + 1 < nz) ? vload<T, V>(u + i + r * sy + sz) : zero;
+        const vec<T, V> ybelow = y0 > 0 ? vload<T, V>(u + i - sy) : zero;
+        const vec<T, V> yabove = (y0 + R < ny) ? vload<T, V>(u + i + R * sy) : zero;
 #pragma unroll
-            for (int q = 0; q < V; q++) o.v[q] = c1 * cur.v[q] + c1 * (cur.v[q] - s * (c1 * au.v[q]));
-        } else {
-            vec<T, V> bb = vload<T, V>(b + i);
+        for (int r = 0; r < R; r++) {
+            const i64 ir = i + r * sy;
+            vec<T, V> xm, xp;
+            x_neighbours<T, V>(cur[r], u, ir, sx, x, nx, L, rok[r], xm, xp);
+            const vec<T, V> ym = r == 0 ? ybelow : cur[r - 1];
+            const vec<T, V> yp = r == R - 1 ? yabove : cur[r + 1];
+            vec<T, V> au = lap<T, V>(cur[r], prev[r], next[r], xm, xp, ym, yp);
+            vec<T, V> o;
+            if (EPI == EPI_APPLY) {
 #pragma unroll
-            for (int q = 0; q < V; q++) {
-                T r = bb.v[q] - s * au.v[q];
-                o.v[q] = (EPI == EPI_JACOBI) ? cur.v[q] + c1 * r : r;
+                for (int q = 0; q < V; q++) o.v[q] = s * au.v[q];
+            } else if (EPI == EPI_JACOBI2) {
+#pragma unroll
+                for (int q = 0; q < V; q++) o.v[q] = c1 * cur[r].v[q] + c1 * (cur[r].v[q] - s * (c1 * au.v[q]));
+            } else {
+                vec<T, V> bb = rok[r] ? vload<T, V>(b + ir) : zero;
+#pragma unroll
+                for (int q = 0; q < V; q++) {
+                    T rr = bb.v[q] - s * au.v[q];
+                    o.v[q] = (EPI == EPI_JACOBI) ? cur[r].v[q] + c1 * rr : rr;
+                }
             }
+            if (active && rok[r]) vstore_nt<T, V>(out + ir, o);
         }
-        if (active) vstore_nt<T, V>(out + i, o);
-        prev = cur;
-        cur = next;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            prev[r] = cur[r];
+            cur[r] = next[r];
+        }
     }
 }
 
@@ -141,7 +165,7 @@ __global__ void __launch_bounds__(256) varcoef7_kernel(int nx, int ny, int nz, i
         const i64 i = base + z * sz;
         vec<T, V> next = (z + 1 < nz) ? vload<T, V>(u + i + sz) : zero;
         vec<T, V> xm, xp;
-        x_neighbours<T, V>(cur, u, i, sx, x, nx, L, xm, xp);
+        x_neighbours<T, V>(cur, u, i, sx, x, nx, L, true, xm, xp);
         vec<T, V> ym = y > 0 ? vload<T, V>(u + i - sy) : zero;
         vec<T, V> yp = y + 1 < ny ? vload<T, V>(u + i + sy) : zero;
         const i64 fxi = ((i64)z * ny + y) * (nx + 1) + x;
@@ -185,6 +209,9 @@ static int pick_vec(int k)
     return 1;
 }
 
+// y-rows per thread: two for FP64 blocks (one y-neighbour row fewer to fetch
+// per output: measured faster), one for FP32 blocks (there the second row's
+// registers cost occupancy, 8 -> 6 waves per SIMD, and the kernel was slower)
 template <typename T, int V, int EPI>
 static hipError_t run_stencil(const Grid3 &g, int k, const void *u, void *out, const void *b, double s, double c1,
                               hipStream_t st)
@@ -192,9 +219,15 @@ static hipError_t run_stencil(const Grid3 &g, int k, const void *u, void *out, c
     const int L = k / V;
     dim3 grid;
     int zchunk;
-    geometry(g.nx, g.ny, g.nz, L, grid, zchunk);
-    hipLaunchKernelGGL((stencil7_kernel<T, V, EPI>), grid, dim3(256), 0, st, g.nx, g.ny, g.nz, L, zchunk,
-                       (const T *)u, (T *)out, (const T *)b, (T)s, (T)c1);
+    if (sizeof(T) == 8 && g.ny >= 2) {
+        geometry(g.nx, (g.ny + 1) / 2, g.nz, L, grid, zchunk);
+        hipLaunchKernelGGL((stencil7_kernel<T, V, EPI, 2>), grid, dim3(256), 0, st, g.nx, g.ny, g.nz, L, zchunk,
+                           (const T *)u, (T *)out, (const T *)b, (T)s, (T)c1);
+    } else {
+        geometry(g.nx, g.ny, g.nz, L, grid, zchunk);
+        hipLaunchKernelGGL((stencil7_kernel<T, V, EPI, 1>), grid, dim3(256), 0, st, g.nx, g.ny, g.nz, L, zchunk,
+                           (const T *)u, (T *)out, (const T *)b, (T)s, (T)c1);
+    }
     return hipGetLastError();
 }
 
