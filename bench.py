@@ -55,7 +55,7 @@ HBM_PEAK_GBPS = 8000.0
 # valid only while the kernel source is the one the counters were taken with.
 TRAFFIC = {
     "update": {"bytes_per_launch": 17.675e9, "source": "paper_0705_2626_amd/csrc/k_update.hip",
-               "sha1": "12a92f8bd371cc3a37ce71e5f48bb0eb2741832a", "profile": "profiles/lobpcg_mixed_n256_m32_hbm_traffic.md"},
+               "sha1": "35448b6ad4de34776aca9259452fad5fb9fd8ece", "profile": "profiles/lobpcg_mixed_n256_m32_hbm_traffic.md"},
 }
 
 

@@ -14,12 +14,14 @@
 // A workgroup (4 waves) walks tiles of 64 grid points; each wave multiplies
 // its 16 points by the coefficients (kept in LDS) with 16x16x4 MFMA, NT
 // 16-column output tiles at a time.  The MFMA A-fragment of a k-step is 16
-// rows x 4 consecutive columns of an input.  For a narrow input (at most 8
-// stored columns) those 16 rows are one short contiguous run and the
-// fragment is loaded straight from global memory.  A wide input is staged: its
-// 64 rows (a contiguous run of 64*ld elements) are read with 16-byte loads,
-// one stage ahead of their use so that the next wide input's loads are in
-// flight while the current one is multiplied, and moved through LDS.
+// rows x 4 columns of an input.  Four kernels share this scheme:
+//   mvf_kernel  (default) fragments loaded straight from global memory with
+//               16-byte loads, the k-sum split in contiguous quarters;
+//   mvn_kernel  at most 8 columns in and out: one point per thread, plain FMA;
+//   mv_kernel / mvd_kernel  (kernel variants 2 / 1) wide inputs staged through
+//               LDS one stage ahead / per-element fragment loads;
+//   mvw_kernel  blocks wider than 32 columns: up to 12 input pieces of at most
+//               32 columns, 16, 32 or 64 output columns per launch.
 // Per-workgroup partial sums of the norms are added in a fixed order by a
 // second kernel.
 #include "common.h"
