@@ -5,9 +5,9 @@
 // same kernel, with a different epilogue, gives the multigrid smoother and
 // residual (weighted Jacobi on the level operator s*L7, s = 4^-l).
 //
-// Mapping: one thread owns V consecutive columns of one (x, y) grid column and
-// marches in z, so the z-1 / z / z+1 values stay in registers and every
-// element is fetched from HBM once.  The x-1 / x+1 neighbours are the centre
+// Mapping: one thread owns V consecutive columns of one (x, y) grid column (of
+// two adjacent y-rows for FP64 blocks) and marches in z, so the z-1 / z / z+1
+// values stay in registers and every element is fetched from HBM once.  The x-1 / x+1 neighbours are the centre
 // values of lanes -L / +L of the same wave and are exchanged by cross-lane
 // shuffles (only lanes at a wave edge load them); the y neighbours are the
 // centre values of threads of the same or a nearby workgroup, fetched through
