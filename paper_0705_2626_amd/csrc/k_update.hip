@@ -191,7 +191,9 @@ __device__ __forceinline__ void mv_setup(const MVShared<T, NT> &sh, const MVDev<
 }
 
 // write the outputs of side s for the 16 points of this wave
-template <typename T, int NT, typename SH, bool SKIP2 = false>
+// LDSACC: the residual sums of squares accumulate in this lane's own entries
+// of sh.red (the slots mv_norms reduces) instead of in sr / sx
+template <typename T, int NT, typename SH, bool SKIP2 = false, bool LDSACC = false>
 __device__ __forceinline__ void mv_outputs(const MVDev<T> &a, const SH &sh, int s, i64 p0w,
                                            const typename Mfma<T>::acc (&acc)[NT],
                                            const typename Mfma<T>::acc (&acc2)[NT],
@@ -216,8 +218,14 @@ __device__ __forceinline__ void mv_outputs(const MVDev<T> &a, const SH &sh, int 
             if (resid && s == 1) {
                 const double x = (double)keepX[nt][r];
                 const double rv = (double)acc2[nt][r] - sh.theta[c] * x;
-                sr[nt] += rv * rv;
-                sx[nt] += x * x;
+                if (LDSACC) {
+                    const int slot = (threadIdx.x >> 6) * 4 + (lane >> 4);
+                    sh.red[(slot * 2 + 0) * (NT * 16) + c] += rv * rv;
+                    sh.red[(slot * 2 + 1) * (NT * 16) + c] += x * x;
+                } else {
+                    sr[nt] += rv * rv;
+                    sx[nt] += x * x;
+                }
                 const int w = sh.wpos[c];
                 if (w >= 0) a.Wout[p * a.nW + w] = (T)rv;
             }
@@ -226,17 +234,19 @@ __device__ __forceinline__ void mv_outputs(const MVDev<T> &a, const SH &sh, int 
 }
 
 // per-workgroup norm sums: lanes l, l+16, l+32, l+48 of every wave share a column
-template <typename T, int NT, typename SH>
+template <typename T, int NT, typename SH, bool LDSACC = false>
 __device__ __forceinline__ void mv_norms(const MVDev<T> &a, const SH &sh, const double (&sr)[NT],
                                          const double (&sx)[NT], int wave, int lane)
 {
     const int NC = NT * 16, tid = threadIdx.x;
     const int slot = wave * 4 + (lane >> 4);
+    if (!LDSACC) {
 #pragma unroll
-    for (int nt = 0; nt < NT; nt++) {
-        const int c = 16 * nt + (lane & 15);
-        sh.red[(slot * 2 + 0) * NC + c] = sr[nt];
-        sh.red[(slot * 2 + 1) * NC + c] = sx[nt];
+        for (int nt = 0; nt < NT; nt++) {
+            const int c = 16 * nt + (lane & 15);
+            sh.red[(slot * 2 + 0) * NC + c] = sr[nt];
+            sh.red[(slot * 2 + 1) * NC + c] = sx[nt];
+        }
     }
     __syncthreads();
     for (int e = tid; e < 2 * a.kout; e += blockDim.x) {
@@ -474,6 +484,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
         sh.wpos[c] = (c < a.kout && a.wpos) ? a.wpos[c] : -1;
         sh.theta[c] = (c < a.kout && a.theta) ? a.theta[c] : 0.0;
     }
+    // the residual sums of squares accumulate in LDS (registers are kept for
+    // the loads in flight); each lane owns its entries
+    {
+        const int slot = wave * 4 + (lane >> 4);
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+            const int c = 16 * nt + (lane & 15);
+            sh.red[(slot * 2 + 0) * NC + c] = 0.0;
+            sh.red[(slot * 2 + 1) * NC + c] = 0.0;
+        }
+    }
     __syncthreads();
 
     const bool has2 = a.out2[0] != nullptr;
@@ -541,7 +562,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                     // four consecutive columns of one row and stores 16 bytes.
                     // The tile is private to this wave and LDS operations of
                     // one wave complete in order.
-                    mv_outputs<T, NT, MVFShared<T, NT>, true>(a, sh, s, p0w, acc, acc2, keepX, sr, sx, lane);
+                    mv_outputs<T, NT, MVFShared<T, NT>, true, true>(a, sh, s, p0w, acc, acc2, keepX, sr, sx, lane);
                     T *st = sh.stage + wave * 16 * (NC + 4);
 #pragma unroll
                     for (int r = 0; r < 4; r++)
@@ -559,7 +580,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                     }
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 } else {
-                    mv_outputs<T, NT>(a, sh, s, p0w, acc, acc2, keepX, sr, sx, lane);
+                    mv_outputs<T, NT, MVFShared<T, NT>, false, true>(a, sh, s, p0w, acc, acc2, keepX, sr, sx, lane);
                 }
                 if (s == 0) {
 #pragma unroll
@@ -593,7 +614,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                     for (int nt = 0; nt < NT; nt++) acc2[nt] = acc[nt];
                     input(acc2, s, 0, prow, pok);
                 }
-                mv_outputs<T, NT>(a, sh, s, p0w, acc, acc2, keepX, sr, sx, lane);
+                mv_outputs<T, NT, MVFShared<T, NT>, false, true>(a, sh, s, p0w, acc, acc2, keepX, sr, sx, lane);
                 if (s == 0) {
 #pragma unroll
                     for (int nt = 0; nt < NT; nt++) keepX[nt] = acc2[nt];
@@ -601,7 +622,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
             }
         }
     }
-    if (a.partials) mv_norms<T, NT>(a, sh, sr, sx, wave, lane);
+    if (a.partials) mv_norms<T, NT, MVFShared<T, NT>, true>(a, sh, sr, sx, wave, lane);
 }
 
 // Wide kernel: blocks of more than MAXW columns, given as up to MV_MAX_IN
