@@ -164,7 +164,11 @@ enum {
                                     /* multi-column-tile Gram kernel also for narrow   */
                                     /* single-block Grams; bit 3: up to four Gram      */
                                     /* tiles per wave (default two); bit 4: the same   */
-                                    /* for FP32 blocks only                            */
+                                    /* for FP32 blocks only; bit 5: Gram operands      */
+                                    /* loaded per tile group rather than staged once   */
+                                    /* per row chunk through LDS (bits 3-4 apply to    */
+                                    /* that kernel and to products with more operand   */
+                                    /* blocks than the LDS-staged kernel holds)        */
     LOBPCG_OPT_FP32_EXPLICIT_GRAM = 6,/* MIXED: 1 (default) FP32 iterations compute   */
                                     /* X^T X, X^T AX, W^T W, P^T P rather than taking  */
                                     /* I and Lambda for them as the paper's form does  */

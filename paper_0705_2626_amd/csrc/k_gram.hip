@@ -197,6 +197,165 @@ __global__ void __launch_bounds__(256) gramx_reduce_kernel(const double *__restr
     if (sub == 0 && q < total) out[q] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
 }
 
+// The same products with each row chunk staged once through LDS.  The
+// direct kernel above loads every 16-column operand block once per tile
+// group that uses it (about five times over for the Rayleigh-Ritz products),
+// and that traffic through the per-CU vector cache, not HBM, limits it.  Here
+// a workgroup of GY_WAVES waves walks whole row chunks of the distinct
+// 16-column panels of Lm and Rm (at most GY_MAX_P): every thread loads
+// elements of two neighbouring panels of one row (a whole 128-byte line when
+// the panels are the two halves of a 32-column block), stores them into one
+// of two LDS buffers, and after one barrier the waves multiply out their own
+// tiles from LDS while the next chunk's loads are in flight.  Products with
+// few panels stack several row sub-chunks into one LDS buffer, so that every
+// chunk moves the same number of bytes.  Each wave takes a
+// contiguous run of the tiles (sorted by Lm panel, so the Lm operands are
+// mostly read once per chunk); its sums go to its own partial tiles, so the
+// partials and their reduction are those of the direct kernel and results are
+// reproducible bit for bit.
+static const int GY_WAVES = 8;
+static const int GY_MAX_P = 12;
+static const int GY_TPW = GX_MAX_TILES / GY_WAVES;   // most tiles per wave
+static const int GY_BLOCKS = 512;
+
+template <typename T>
+struct GYDev {
+    const T *arr[GX_MAX_ARR];
+    int ld[GX_MAX_ARR];
+    const T *safe;                        // a valid element: the address of every load that is not needed
+    // slot-panel columns, (array << 8) | column, 0xFFFF: none (zeros).  Load
+    // slot q (a pair of slot-panels 2q, 2q + 1) holds panel pair q % npairs
+    // of row sub-chunk sub[q]; slots past nsub * npairs are unused.
+    unsigned short pcode[GY_MAX_P][16];
+    int sub[GY_MAX_P / 2];
+    int npairs, nsub, ntiles;
+    int wn[GY_WAVES];   // tiles of each wave
+    // per wave: Lm panel | Rm panel << 8 | tile << 16 (panels of sub-chunk 0;
+    // 32-bit entries keep the scalar loads of a wave's row dword-aligned)
+    int wtile[GY_WAVES][GY_TPW];
+    i64 N;
+    double *partials;   // [gridDim.x][ntiles][256]
+};
+
+// rows per sub-chunk (one 16-column panel row is 64 / 128 bytes) and the LDS
+// panel stride, padded so that the four 16-lane groups of a store hit
+// different banks
+template <typename T>
+struct GYShape {
+    static const int RC = 128 / sizeof(T);
+    static const int PS = RC * 16 + 32;
+    static const int RPT = RC / 16;   // rows per thread and load slot
+};
+
+template <typename T, int TPW>
+__global__ void __launch_bounds__(64 * GY_WAVES) gramy_kernel(GYDev<T> a)
+{
+    typedef GYShape<T> S;
+    typedef typename Mfma<T>::acc accT;
+    typedef const __attribute__((address_space(1))) T *gptr;   // global loads, not flat ones
+    const int BUF = GY_MAX_P * S::PS;
+    const int NQ = GY_MAX_P / 2;   // load slots
+    __shared__ T lds[2 * BUF];
+    __shared__ const T *tptr[GY_MAX_P * 16];
+    __shared__ int tld[GY_MAX_P * 16];   // 0: a column of zeros (read from a.safe)
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (tid < GY_MAX_P * 16) {
+        const int code = a.pcode[tid >> 4][tid & 15];
+        const bool ok = code != 0xFFFF;
+        tptr[tid] = ok ? a.arr[code >> 8] + (code & 255) : a.safe;
+        tld[tid] = ok ? a.ld[code >> 8] : 0;
+    }
+    __syncthreads();
+    const i64 N = a.N, rows_chunk = (i64)a.nsub * S::RC, nchunks = (N + rows_chunk - 1) / rows_chunk;
+    // loads: lanes 0-31 take one row, 32-63 the next; 16 lanes per panel
+    const int lc = lane & 15, lpan = (lane >> 4) & 1, lrow = 2 * wave + (lane >> 5);
+    const int soff = lpan * S::PS + lrow * 16 + lc;
+    // Every thread issues the same NQ * RPT loads per chunk, rows past N and
+    // unused columns from valid addresses (zeroed when stored), so that the
+    // loads in flight can be counted and waited for one chunk at a time.
+    typedef T Stage[NQ][S::RPT];
+    auto rowof = [&](i64 ch, int q, int i) { return ch * rows_chunk + (i64)a.sub[q] * S::RC + lrow + 16 * i; };
+    auto gload = [&](Stage &st, i64 ch) {
+#pragma unroll
+        for (int q = 0; q < NQ; q++) {
+            const int e = (2 * q + lpan) * 16 + lc;
+            const gptr base = (gptr)tptr[e];
+            const int ldv = tld[e];
+#pragma unroll
+            for (int i = 0; i < S::RPT; i++) st[q][i] = base[min(rowof(ch, q, i), N - 1) * ldv];
+        }
+    };
+    auto lstore = [&](int buf, const Stage &st, i64 ch) {
+        T *L = lds + buf * BUF + soff;
+#pragma unroll
+        for (int q = 0; q < NQ; q++) {
+            const bool okc = tld[(2 * q + lpan) * 16 + lc] > 0;
+#pragma unroll
+            for (int i = 0; i < S::RPT; i++)
+                L[2 * q * S::PS + 256 * i] = (okc && rowof(ch, q, i) < N) ? st[q][i] : T(0);
+        }
+    };
+
+    const int nt = a.wn[wave], nsub = a.nsub, subp = 2 * a.npairs * S::PS;
+    int pa[TPW], pb[TPW];
+#pragma unroll
+    for (int j = 0; j < TPW; j++) pa[j] = (a.wtile[wave][j] & 255) * S::PS, pb[j] = ((a.wtile[wave][j] >> 8) & 255) * S::PS;
+    accT acc[TPW];
+    double sums[TPW][4];   // FP32 blocks: FP64 running sums of the sub-chunk products
+#pragma unroll
+    for (int j = 0; j < TPW; j++) {
+        acc[j] = acc_zero<T>();
+#pragma unroll
+        for (int r = 0; r < 4; r++) sums[j][r] = 0.0;
+    }
+    // MFMA operands: lane l, k-step s reads row 4s + l/16, column l%16 of a
+    // panel; a wave's consecutive tiles mostly share their Lm panel, whose
+    // operands then stay in registers
+    const int roff = (lane >> 4) * 16 + lc;
+    auto compute = [&](int buf) {
+        for (int sb = 0; sb < nsub; sb++) {
+            const T *L = lds + buf * BUF + roff + sb * subp;
+            T av[S::RC / 4];
+#pragma unroll
+            for (int j = 0; j < TPW; j++) {
+                if (j < nt) {
+                    if (j == 0 || pa[j] != pa[j - 1])
+#pragma unroll
+                        for (int s = 0; s < S::RC / 4; s++) av[s] = L[pa[j] + 64 * s];
+#pragma unroll
+                    for (int s = 0; s < S::RC / 4; s++) acc[j] = Mfma<T>::mma(av[s], L[pb[j] + 64 * s], acc[j]);
+                    if (sizeof(T) == 4) {
+#pragma unroll
+                        for (int r = 0; r < 4; r++) sums[j][r] += (double)acc[j][r];
+                        acc[j] = acc_zero<T>();
+                    }
+                }
+            }
+        }
+    };
+    // the loads of chunk c + G (G = gridDim.x) are in flight while chunk c is
+    // multiplied out; the two LDS buffers alternate, and each was last read
+    // before the previous barrier
+    const i64 G = gridDim.x;
+    Stage st;
+    i64 ch = blockIdx.x;
+    gload(st, ch);
+    for (int buf = 0; ch < nchunks; ch += G, buf ^= 1) {
+        lstore(buf, st, ch);
+        __syncthreads();
+        gload(st, ch + G);
+        compute(buf);
+    }
+#pragma unroll
+    for (int j = 0; j < TPW; j++)
+        if (j < nt) {
+            double *o = a.partials + ((i64)blockIdx.x * a.ntiles + (a.wtile[wave][j] >> 16)) * 256 + lane;
+#pragma unroll
+            for (int r = 0; r < 4; r++) o[r * 64] = sizeof(T) == 4 ? sums[j][r] : (double)acc[j][r];
+        }
+}
+
 // A single narrow block (S^T S for W_J or P_J with at most 8 columns, the
 // Cholesky Gram matrices of steps 11 and 14): one grid row per thread, the
 // W(W+1)/2 products accumulated in FP64, then summed across each wave with a
@@ -290,6 +449,89 @@ size_t gram_partials_bytes(long long N)
     return tiles > rows ? tiles : rows;
 }
 
+// The LDS-staged kernel when the tiles' operand blocks fit its panel table;
+// false: they do not (nothing launched).  Column codes are checked by the caller.
+template <typename T>
+static bool run_gramy(const GramXArgs &h, hipStream_t st, hipError_t &err)
+{
+    GYDev<T> a;
+    a.safe = nullptr;
+    for (int i = 0; i < GX_MAX_ARR; i++) {
+        a.arr[i] = (const T *)h.arr[i];
+        a.ld[i] = h.ld[i];
+    }
+    // the distinct panels (16 column codes each) of the tiles' Lm and Rm blocks
+    unsigned short pcode[GY_MAX_P][16];
+    int np = 0;
+    auto panel = [&](const unsigned short *map, int K, int blk) -> int {
+        unsigned short code[16];
+        for (int v = 0; v < 16; v++) code[v] = 16 * blk + v < K ? map[16 * blk + v] : 0xFFFF;
+        for (int p = 0; p < np; p++)
+            if (std::equal(code, code + 16, pcode[p])) return p;
+        if (np == GY_MAX_P) return -1;
+        std::copy(code, code + 16, pcode[np]);
+        return np++;
+    };
+    int pl[GX_MAX_L / 16], pr[GX_MAX_R / 16];
+    std::fill(pl, pl + GX_MAX_L / 16, -1);
+    std::fill(pr, pr + GX_MAX_R / 16, -1);
+    // tiles (sorted by Lm block) dealt in contiguous runs whose lengths
+    // differ by at most one, longer runs first: waves w and w + 4 share a SIMD
+    int nw[GY_WAVES] = {};
+    for (int w = 0; w < GY_WAVES; w++) nw[w] = h.ntiles / GY_WAVES + (w < h.ntiles % GY_WAVES ? 1 : 0);
+    for (int t = 0, w = 0, j = 0; t < h.ntiles; t++) {
+        int &l = pl[h.ta[t]], &r = pr[h.tb[t]];
+        if (l < 0 && (l = panel(h.lmap, h.KL, h.ta[t])) < 0) return false;
+        if (r < 0 && (r = panel(h.rmap, h.KR, h.tb[t])) < 0) return false;
+        while (j == nw[w]) w++, j = 0;
+        a.wtile[w][j++] = l | r << 8 | t << 16;
+    }
+    int tpw = 0;
+    for (int w = 0; w < GY_WAVES; w++) {
+        a.wn[w] = nw[w];
+        tpw = std::max(tpw, nw[w]);
+        for (int j = nw[w]; j < GY_TPW; j++) a.wtile[w][j] = 0;
+    }
+    // load slots: panel pairs, repeated for as many row sub-chunks as fit
+    const int NQ = GY_MAX_P / 2;
+    a.npairs = (np + 1) / 2;
+    a.nsub = NQ / a.npairs;
+    for (int q = 0; q < NQ; q++) {
+        const bool used = q < a.nsub * a.npairs;
+        a.sub[q] = used ? q / a.npairs : 0;
+        for (int lp = 0; lp < 2; lp++) {
+            const int p = 2 * (q % a.npairs) + lp;
+            for (int v = 0; v < 16; v++) {
+                const unsigned short c = used && p < np ? pcode[p][v] : 0xFFFF;
+                a.pcode[2 * q + lp][v] = c;
+                if (c != 0xFFFF && !a.safe) a.safe = a.arr[c >> 8] + (c & 255);
+            }
+        }
+    }
+    if (!a.safe) return false;
+    a.ntiles = h.ntiles;
+    a.N = h.N;
+    a.partials = h.partials;
+    const i64 rows = (i64)a.nsub * GYShape<T>::RC, nchunks = (h.N + rows - 1) / rows;
+    const int nb = (int)std::min<i64>(std::min<i64>(nchunks, gram_blocks(h.N)), GY_BLOCKS);
+    const dim3 grid(nb), block(64 * GY_WAVES);
+    if (tpw <= 2)
+        hipLaunchKernelGGL((gramy_kernel<T, 2>), grid, block, 0, st, a);
+    else if (tpw <= 4)
+        hipLaunchKernelGGL((gramy_kernel<T, 4>), grid, block, 0, st, a);
+    else if (tpw <= 6)
+        hipLaunchKernelGGL((gramy_kernel<T, 6>), grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL((gramy_kernel<T, 8>), grid, block, 0, st, a);
+    err = hipGetLastError();
+    if (err != hipSuccess) return true;
+    const i64 total = (i64)h.ntiles * 256;
+    hipLaunchKernelGGL(gramx_reduce_kernel, dim3((unsigned)((total + 63) / 64)), dim3(256), 0, st, h.partials, nb,
+                       h.ntiles, h.out);
+    err = hipGetLastError();
+    return true;
+}
+
 template <typename T>
 static hipError_t run_gramx(const GramXArgs &h, hipStream_t st)
 {
@@ -309,6 +551,10 @@ static hipError_t run_gramx(const GramXArgs &h, hipStream_t st)
         const int ar = h.rmap[i] >> 8, col = h.rmap[i] & 255;
         if (ar >= GX_MAX_ARR || !h.arr[ar] || col >= h.ld[ar]) return hipErrorInvalidValue;
         a.rmap[i] = h.rmap[i];
+    }
+    if (!h.direct) {
+        hipError_t e = hipSuccess;
+        if (run_gramy<T>(h, st, e)) return e;
     }
     // tiles grouped by their Lm block, NT slots per group (the widest run of
     // one Lm block, at most GX_MAXB); empty slots compute nothing useful

@@ -149,6 +149,7 @@ struct GramXArgs {
     double *out;        // device [ntiles][256]
     int max_nt;         // most tiles per wave for FP64 blocks (1, 2 or GX_MAXB)
     int max_nt32;       // the same for FP32 blocks
+    int direct = 0;     // 1: the direct-load kernel even where the LDS-staged one fits
 };
 size_t gram_partials_bytes(long long N);
 hipError_t launch_gramx(int dtype, const GramXArgs &a, hipStream_t st);

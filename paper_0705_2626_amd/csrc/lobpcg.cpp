@@ -162,7 +162,7 @@ struct lobpcg_ctx {
     int stall_window;
     double stall_factor;
     bool profile, reactivate;
-    int mv_variant, gram_staged, gram_nt4, gram_nt32;  // kernel variants (see LOBPCG_OPT_KERNELS)
+    int mv_variant, gram_staged, gram_nt4, gram_nt32, gram_direct;  // kernel variants (see LOBPCG_OPT_KERNELS)
     bool fp32_explicit;           // FP32 phase: Gram diagonal blocks computed, not assumed
     bool fp64_explicit;           // the same for FP64 iterations
     bool fold;                    // Cholesky-QR factors of W_J, P_J folded into Gram and coefficients
@@ -420,6 +420,7 @@ int gram(lobpcg_ctx *c, int dt, int n, const void *const *S, const void *const *
     a.out = c->d_gram_out;
     a.max_nt = c->gram_nt4 ? GX_MAXB : 2;
     a.max_nt32 = c->gram_nt4 ? GX_MAXB : c->gram_nt32;
+    a.direct = c->gram_direct;
     const bool single = launches.size() == 1 && K <= GX_MAX_L && KR <= GX_MAX_R;
     for (const Launch &L : launches) {
         // the launch's Lm / Rm: its 16-column blocks, in order; a partial last
@@ -860,6 +861,7 @@ int constrain(lobpcg_ctx *c, const void *V, int k, void *dst, int step)
         a.out = c->d_gram_out;
         a.max_nt = 2;
         a.max_nt32 = c->gram_nt32;
+        a.direct = c->gram_direct;
         prof_begin(c, step);
         if (launch_gramx(DT_F64, a, c->st) != hipSuccess) return LOBPCG_ERR_HIP;
         prof_end(c);
@@ -1578,6 +1580,7 @@ int lobpcg_setup(lobpcg_ctx **out, const lobpcg_op *A, const lobpcg_op *B, const
     c->gram_staged = 0;
     c->gram_nt4 = 0;
     c->gram_nt32 = 2;
+    c->gram_direct = 0;
     c->fp32_explicit = true;
     c->fp64_explicit = false;
     c->fold = true;
@@ -1627,11 +1630,12 @@ int lobpcg_set_option(lobpcg_ctx *c, int key, double v)
     case LOBPCG_OPT_FOLD_CHOLQR: c->fold = v != 0; return LOBPCG_OK;
     case LOBPCG_OPT_FP64_EXPLICIT_GRAM: c->fp64_explicit = v != 0; return LOBPCG_OK;
     case LOBPCG_OPT_KERNELS:
-        if (v < 0 || v > 31 || ((int)v & 3) == 3) return LOBPCG_ERR_ARG;
+        if (v < 0 || v > 63 || ((int)v & 3) == 3) return LOBPCG_ERR_ARG;
         c->mv_variant = (int)v & 3;
         c->gram_staged = ((int)v & 4) != 0;
         c->gram_nt4 = ((int)v & 8) != 0;
         c->gram_nt32 = ((int)v & 16) ? 4 : 2;
+        c->gram_direct = ((int)v & 32) != 0;
         return LOBPCG_OK;
     default: return LOBPCG_ERR_ARG;
     }

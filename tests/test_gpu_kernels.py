@@ -141,8 +141,10 @@ def test_vcycle_large_coarsest_grid_uses_global_sweeps():
 # ---------------------------------------------------------------- Gram products (steps 17-23, 3, 11, 14)
 
 # variant 0: the kernel chosen by shape (one row per thread for a single block
-# of at most 8 columns), 4: always the MFMA kernel, 8: up to four tiles per wave
-@pytest.mark.parametrize("variant", [0, 4, 8])
+# of at most 8 columns, else the LDS-staged MFMA kernel), 4: always an MFMA
+# kernel, 32: the direct-load MFMA kernel, 40: the same with up to four tiles
+# per wave
+@pytest.mark.parametrize("variant", [0, 4, 32, 40])
 @pytest.mark.parametrize("N,widths", [(4096, (8, 3, 3)), (33 * 17 * 9, (32, 32, 32)), (1000, (4,)),
                                       (70001, (16, 16)), (5003, (5, 7, 2)), (200000, (32, 17, 17)),
                                       (300007, (1,)), (12345, (32, 1, 1))])
@@ -161,7 +163,7 @@ def test_gram_fp64(N, widths, variant):
     np.testing.assert_allclose(SS, SS.T)      # lower triangle mirrored
 
 
-@pytest.mark.parametrize("variant", [0, 4, 8, 16])
+@pytest.mark.parametrize("variant", [0, 4, 32, 48])
 @pytest.mark.parametrize("N,widths", [(4096, (8, 3, 3)), (70001, (32, 32, 32)), (5003, (5, 7, 2)),
                                       (99999, (32, 1, 1)), (77777, (2,)), (3001, (17, 9)), (129, (33,))])
 def test_gram_fp32(N, widths, variant):

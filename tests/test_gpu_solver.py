@@ -190,7 +190,7 @@ def test_error_paths():
         L.lobpcg_solve(ctx, dev(synth.x0_uniform(N, m)), -1.0, 10)
 
 
-@pytest.mark.parametrize("variant", [1, 2, 4, 8])
+@pytest.mark.parametrize("variant", [1, 2, 4, 8, 32])
 @pytest.mark.parametrize("m", [6, 12])
 def test_kernel_variants_give_the_same_solution(variant, m):
     """The default multivector / Gram kernels and the other variants agree."""
@@ -318,8 +318,11 @@ def test_explicit_gram_fp64_matches_oracle():
     np.testing.assert_allclose(r.lam, ref.lam, rtol=1e-10)
     assert r.resid.max() <= tol
     assert abs(r.iters - ref.iters) <= 1, (r.iters, ref.iters)
+    # this run sits next to a loss of orthogonality: its residuals amplify
+    # differences in the Gram products' summation order (row blocking), so
+    # the histories agree to 1e-5 here rather than 1e-6
     k = min(8, r.iters)
-    np.testing.assert_allclose(r.hist[:k], ref.hist[:k], rtol=1e-6)
+    np.testing.assert_allclose(r.hist[:k], ref.hist[:k], rtol=1e-5)
 
 
 def test_block_of_98_fp64():
