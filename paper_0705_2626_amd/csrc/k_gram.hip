@@ -274,26 +274,30 @@ __global__ void __launch_bounds__(64 * GY_WAVES) gramy_kernel(GYDev<T> a)
     // Every thread issues the same NQ * RPT loads per chunk, rows past N and
     // unused columns from valid addresses (zeroed when stored), so that the
     // loads in flight can be counted and waited for one chunk at a time.
+    // Element offsets are 32-bit (the host checks N * ld < 2^32).
     typedef T Stage[NQ][S::RPT];
-    auto rowof = [&](i64 ch, int q, int i) { return ch * rows_chunk + (i64)a.sub[q] * S::RC + lrow + 16 * i; };
+    const unsigned N32 = (unsigned)N;
+    auto row0 = [&](i64 ch) { return (unsigned)(ch * rows_chunk) + (unsigned)lrow; };
     auto gload = [&](Stage &st, i64 ch) {
+        const unsigned r0 = row0(ch);
 #pragma unroll
         for (int q = 0; q < NQ; q++) {
             const int e = (2 * q + lpan) * 16 + lc;
             const gptr base = (gptr)tptr[e];
-            const int ldv = tld[e];
+            const unsigned ldv = (unsigned)tld[e], rq = r0 + (unsigned)(a.sub[q] * S::RC);
 #pragma unroll
-            for (int i = 0; i < S::RPT; i++) st[q][i] = base[min(rowof(ch, q, i), N - 1) * ldv];
+            for (int i = 0; i < S::RPT; i++) st[q][i] = base[min(rq + 16u * i, N32 - 1u) * ldv];
         }
     };
     auto lstore = [&](int buf, const Stage &st, i64 ch) {
         T *L = lds + buf * BUF + soff;
+        const unsigned r0 = row0(ch);
 #pragma unroll
         for (int q = 0; q < NQ; q++) {
             const bool okc = tld[(2 * q + lpan) * 16 + lc] > 0;
+            const unsigned rq = r0 + (unsigned)(a.sub[q] * S::RC);
 #pragma unroll
-            for (int i = 0; i < S::RPT; i++)
-                L[2 * q * S::PS + 256 * i] = (okc && rowof(ch, q, i) < N) ? st[q][i] : T(0);
+            for (int i = 0; i < S::RPT; i++) L[2 * q * S::PS + 256 * i] = (okc && rq + 16u * i < N32) ? st[q][i] : T(0);
         }
     };
 
@@ -509,6 +513,13 @@ static bool run_gramy(const GramXArgs &h, hipStream_t st, hipError_t &err)
         }
     }
     if (!a.safe) return false;
+    // 32-bit element offsets: every row of every used array (and the rows a
+    // prefetch past the end computes before clamping) must be addressable
+    for (int p = 0; p < GY_MAX_P; p++)
+        for (int v = 0; v < 16; v++)
+            if (a.pcode[p][v] != 0xFFFF && (unsigned long long)(h.N + 2 * GY_BLOCKS * 6 * GYShape<T>::RC) *
+                                                   (unsigned long long)h.ld[a.pcode[p][v] >> 8] >= (1ull << 32))
+                return false;
     a.ntiles = h.ntiles;
     a.N = h.N;
     a.partials = h.partials;
