@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(256) gramx_reduce_kernel(const double *__restr
 // and that traffic through the per-CU vector cache, not HBM, limits it.  Here
 // a workgroup of GY_WAVES waves walks whole row chunks of the distinct
 // 16-column panels of Lm and Rm (at most GY_MAX_P): every thread loads
-// elements of two neighbouring panels of one row (a whole 128-byte line when
+// elements of two neighbouring panels of two rows (whole 128-byte lines when
 // the panels are the two halves of a 32-column block), stores them into one
 // of two LDS buffers, and after one barrier the waves multiply out their own
 // tiles from LDS while the next chunk's loads are in flight.  Products with
@@ -237,12 +237,13 @@ struct GYDev {
     double *partials;   // [gridDim.x][ntiles][256]
 };
 
-// rows per sub-chunk (one 16-column panel row is 64 / 128 bytes) and the LDS
-// panel stride, padded so that the four 16-lane groups of a store hit
-// different banks
+// rows per sub-chunk (one 16-column panel row is 64 / 128 bytes; 48 FP32
+// rows keep two workgroups' double buffers within one CU's LDS) and the LDS
+// panel stride (= 32 mod 64 words, so that the four 16-lane groups of a
+// store hit different banks)
 template <typename T>
 struct GYShape {
-    static const int RC = 128 / sizeof(T);
+    static const int RC = sizeof(T) == 4 ? 48 : 16;
     static const int PS = RC * 16 + 32;
     static const int RPT = RC / 16;   // rows per thread and load slot
 };
@@ -268,8 +269,9 @@ __global__ void __launch_bounds__(64 * GY_WAVES) gramy_kernel(GYDev<T> a)
     }
     __syncthreads();
     const i64 N = a.N, rows_chunk = (i64)a.nsub * S::RC, nchunks = (N + rows_chunk - 1) / rows_chunk;
-    // loads: lanes 0-31 take one row, 32-63 the next; 16 lanes per panel
-    const int lc = lane & 15, lpan = (lane >> 4) & 1, lrow = 2 * wave + (lane >> 5);
+    // loads: lanes 0-31 take two rows of one panel, 32-63 the same rows of
+    // the next panel (16 lanes per panel row)
+    const int lc = lane & 15, lpan = lane >> 5, lrow = 2 * wave + ((lane >> 4) & 1);
     const int soff = lpan * S::PS + lrow * 16 + lc;
     // Every thread issues the same NQ * RPT loads per chunk, rows past N and
     // unused columns from valid addresses (zeroed when stored), so that the
