@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(256) gramx_reduce_kernel(const double *__restr
 // partials and their reduction are those of the direct kernel and results are
 // reproducible bit for bit.
 static const int GY_WAVES = 8;
-static const int GY_MAX_P = 12;
+static const int GY_MAX_P = 18;   // panels of the 9-slot shape
 static const int GY_TPW = GX_MAX_TILES / GY_WAVES;   // most tiles per wave
 static const int GY_BLOCKS = 512;
 
@@ -237,31 +237,33 @@ struct GYDev {
     double *partials;   // [gridDim.x][ntiles][256]
 };
 
-// rows per sub-chunk (one 16-column panel row is 64 / 128 bytes; 48 FP32
-// rows keep two workgroups' double buffers within one CU's LDS) and the LDS
-// panel stride (= 32 mod 64 words, so that the four 16-lane groups of a
-// store hit different banks)
-template <typename T>
+// Two shapes of the LDS buffers, NQ load slots of two panels each: 6 slots
+// (up to 12 panels) of 48 FP32 / 16 FP64 rows, or 9 slots (up to 18 panels)
+// of 32 FP32 / 16 FP64 rows; either way two workgroups' double buffers fill
+// one CU's LDS.  RC: rows per sub-chunk; PS: LDS panel stride (= 32 mod 64
+// words for FP32, so that the four 16-lane groups of a store hit different
+// banks); RPT: rows per thread and load slot.
+template <typename T, int NQ>
 struct GYShape {
-    static const int RC = sizeof(T) == 4 ? 48 : 16;
-    static const int PS = RC * 16 + 32;
-    static const int RPT = RC / 16;   // rows per thread and load slot
+    static const int RC = sizeof(T) == 4 ? (NQ == 6 ? 48 : 32) : 16;
+    static const int PS = RC * 16 + (sizeof(T) == 8 && NQ == 9 ? 16 : 32);
+    static const int RPT = RC / 16;
 };
 
-template <typename T, int TPW>
+template <typename T, int TPW, int NQ>
 __global__ void __launch_bounds__(64 * GY_WAVES) gramy_kernel(GYDev<T> a)
 {
-    typedef GYShape<T> S;
+    typedef GYShape<T, NQ> S;
     typedef typename Mfma<T>::acc accT;
     typedef const __attribute__((address_space(1))) T *gptr;   // global loads, not flat ones
-    const int BUF = GY_MAX_P * S::PS;
-    const int NQ = GY_MAX_P / 2;   // load slots
+    const int NP = 2 * NQ;   // slot-panels
+    const int BUF = NP * S::PS;
     __shared__ T lds[2 * BUF];
-    __shared__ const T *tptr[GY_MAX_P * 16];
-    __shared__ int tld[GY_MAX_P * 16];   // 0: a column of zeros (read from a.safe)
+    __shared__ const T *tptr[NP * 16];
+    __shared__ int tld[NP * 16];   // 0: a column of zeros (read from a.safe)
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    if (tid < GY_MAX_P * 16) {
+    if (tid < NP * 16) {
         const int code = a.pcode[tid >> 4][tid & 15];
         const bool ok = code != 0xFFFF;
         tptr[tid] = ok ? a.arr[code >> 8] + (code & 255) : a.safe;
@@ -499,10 +501,11 @@ static bool run_gramy(const GramXArgs &h, hipStream_t st, hipError_t &err)
         for (int j = nw[w]; j < GY_TPW; j++) a.wtile[w][j] = 0;
     }
     // load slots: panel pairs, repeated for as many row sub-chunks as fit
-    const int NQ = GY_MAX_P / 2;
+    const int NQ = np <= 12 ? 6 : 9;
+    const int RC = NQ == 6 ? GYShape<T, 6>::RC : GYShape<T, 9>::RC;
     a.npairs = (np + 1) / 2;
     a.nsub = NQ / a.npairs;
-    for (int q = 0; q < NQ; q++) {
+    for (int q = 0; q < GY_MAX_P / 2; q++) {
         const bool used = q < a.nsub * a.npairs;
         a.sub[q] = used ? q / a.npairs : 0;
         for (int lp = 0; lp < 2; lp++) {
@@ -519,23 +522,30 @@ static bool run_gramy(const GramXArgs &h, hipStream_t st, hipError_t &err)
     // prefetch past the end computes before clamping) must be addressable
     for (int p = 0; p < GY_MAX_P; p++)
         for (int v = 0; v < 16; v++)
-            if (a.pcode[p][v] != 0xFFFF && (unsigned long long)(h.N + 2 * GY_BLOCKS * 6 * GYShape<T>::RC) *
-                                                   (unsigned long long)h.ld[a.pcode[p][v] >> 8] >= (1ull << 32))
+            if (a.pcode[p][v] != 0xFFFF &&
+                (unsigned long long)(h.N + 2 * GY_BLOCKS * 9 * RC) * (unsigned long long)h.ld[a.pcode[p][v] >> 8] >=
+                    (1ull << 32))
                 return false;
     a.ntiles = h.ntiles;
     a.N = h.N;
     a.partials = h.partials;
-    const i64 rows = (i64)a.nsub * GYShape<T>::RC, nchunks = (h.N + rows - 1) / rows;
+    const i64 rows = (i64)a.nsub * RC, nchunks = (h.N + rows - 1) / rows;
     const int nb = (int)std::min<i64>(std::min<i64>(nchunks, gram_blocks(h.N)), GY_BLOCKS);
     const dim3 grid(nb), block(64 * GY_WAVES);
-    if (tpw <= 2)
-        hipLaunchKernelGGL((gramy_kernel<T, 2>), grid, block, 0, st, a);
-    else if (tpw <= 4)
-        hipLaunchKernelGGL((gramy_kernel<T, 4>), grid, block, 0, st, a);
-    else if (tpw <= 6)
-        hipLaunchKernelGGL((gramy_kernel<T, 6>), grid, block, 0, st, a);
-    else
-        hipLaunchKernelGGL((gramy_kernel<T, 8>), grid, block, 0, st, a);
+#define GY_LAUNCH(TPW_, NQ_) hipLaunchKernelGGL((gramy_kernel<T, TPW_, NQ_>), grid, block, 0, st, a)
+    const int tv = tpw <= 2 ? 2 : tpw <= 4 ? 4 : tpw <= 6 ? 6 : 8;
+    if (NQ == 6) {
+        if (tv == 2) GY_LAUNCH(2, 6);
+        else if (tv == 4) GY_LAUNCH(4, 6);
+        else if (tv == 6) GY_LAUNCH(6, 6);
+        else GY_LAUNCH(8, 6);
+    } else {
+        if (tv == 2) GY_LAUNCH(2, 9);
+        else if (tv == 4) GY_LAUNCH(4, 9);
+        else if (tv == 6) GY_LAUNCH(6, 9);
+        else GY_LAUNCH(8, 9);
+    }
+#undef GY_LAUNCH
     err = hipGetLastError();
     if (err != hipSuccess) return true;
     const i64 total = (i64)h.ntiles * 256;

@@ -147,7 +147,7 @@ def test_vcycle_large_coarsest_grid_uses_global_sweeps():
 @pytest.mark.parametrize("variant", [0, 4, 32, 40])
 @pytest.mark.parametrize("N,widths", [(4096, (8, 3, 3)), (33 * 17 * 9, (32, 32, 32)), (1000, (4,)),
                                       (70001, (16, 16)), (5003, (5, 7, 2)), (200000, (32, 17, 17)),
-                                      (300007, (1,)), (12345, (32, 1, 1))])
+                                      (300007, (1,)), (12345, (32, 1, 1)), (50021, (32, 31, 31))])
 def test_gram_fp64(N, widths, variant):
     dims = (N, 1, 1)
     ctx = ctx_for(dims, 32)
@@ -165,7 +165,8 @@ def test_gram_fp64(N, widths, variant):
 
 @pytest.mark.parametrize("variant", [0, 4, 32, 48])
 @pytest.mark.parametrize("N,widths", [(4096, (8, 3, 3)), (70001, (32, 32, 32)), (5003, (5, 7, 2)),
-                                      (99999, (32, 1, 1)), (77777, (2,)), (3001, (17, 9)), (129, (33,))])
+                                      (99999, (32, 1, 1)), (77777, (2,)), (3001, (17, 9)), (129, (33,)),
+                                      (50021, (32, 31, 31))])
 def test_gram_fp32(N, widths, variant):
     ctx = ctx_for((N, 1, 1), 32, None, L.MIXED)
     L.lobpcg_set_option(ctx, L.OPT_KERNELS, variant)
