@@ -239,8 +239,8 @@ struct GYDev {
 
 // Two shapes of the LDS buffers, NQ load slots of two panels each: 6 slots
 // (up to 12 panels) of 48 FP32 / 16 FP64 rows, or 9 slots (up to 18 panels)
-// of 32 FP32 / 16 FP64 rows; either way two workgroups' double buffers fill
-// one CU's LDS.  RC: rows per sub-chunk; PS: LDS panel stride (= 32 mod 64
+// of 32 FP32 / 16 FP64 rows; either way two workgroups' double buffers fit
+// in one CU's 160 KB of LDS.  RC: rows per sub-chunk; PS: LDS panel stride (= 32 mod 64
 // words for FP32, so that the four 16-lane groups of a store hit different
 // banks); RPT: rows per thread and load slot.
 template <typename T, int NQ>
