@@ -96,8 +96,8 @@ def main():
                     help="comma-separated start-block seeds: the seed spread instead of the headline run")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see the design notes on how "
-              "the solver would shard); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path (how it would shard is "
+              "described with the design); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
