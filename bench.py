@@ -129,7 +129,8 @@ def main():
     X0 = torch.from_numpy(synth.x0_uniform(N, m, seed=2)).to(dev)
     A, T = L.Op(*dims), L.Precond(levels)
     from oracle import closed_form  # closed form of the spectrum, used only to report accuracy
-    exact, _ = closed_form.smallest(*dims, m)
+    exact_next, _ = closed_form.smallest(*dims, m + 1)
+    exact = exact_next[:m]
 
     def run(prec, K, W):
         torch.cuda.synchronize()
@@ -183,8 +184,13 @@ def main():
         if steps64:
             fp64["steps"] = steps64
         lam_agree = float(np.max(np.abs(r_mixed.lam / r64.lam - 1)))
+        gates = headline_gates(exact_next, r_mixed, r64, t_mixed, t64, tol)
+        del r64
     else:
         lam_agree = None
+        gates = None
+    del r_mixed
+    torch.cuda.empty_cache()
 
     # ---- stencil SpMM on the N x m FP32 block, HIP events on the library's stream
     ctx = L.lobpcg_setup(A, L.Precond(None), m, L.MIXED, device=dev)
@@ -224,6 +230,8 @@ def main():
         "speedup_mixed_vs_fp64": (fp64["value"] / t_mixed) if fp64 else None,
         "mixed_vs_fp64_max_rel_lambda_diff": lam_agree,
         "spmm": {"GBps": spmm_gbps, "dtype": "f32", "block": [N, m], "ms": spmm_ms},
+        "gates": ({name: {"pass": ok, "value": v, "limit": lim} for name, ok, v, lim in gates}
+                  if gates is not None else None),
     }
     if steps_mixed:
         out["mixed"]["steps"] = steps_mixed
@@ -248,6 +256,88 @@ def main():
         out["cpu_baseline"] = cpu_baseline(dims, m, levels, X0.cpu().numpy(),
                                            fp64["iters"] if fp64 else acc_mixed["iters"])
     print(json.dumps(out), flush=True)
+    if gates is not None and not all(ok for _, ok, _, _ in gates):
+        print("headline gates failed: " + ", ".join("%s %.3g > %.3g" % (nm, v, lim)
+                                                    for nm, ok, v, lim in gates if not ok), file=sys.stderr)
+        sys.exit(1)
+
+
+def degenerate_groups(exact, rel=1e-12):
+    """Index lists of the groups of equal closed-form eigenvalues among the
+    first len(exact) (ascending)."""
+    groups, cur = [], [0]
+    for j in range(1, len(exact)):
+        if exact[j] - exact[cur[0]] <= rel * exact[j]:
+            cur.append(j)
+        else:
+            groups.append(cur)
+            cur = [j]
+    groups.append(cur)
+    return groups
+
+
+def headline_gates(exact, r_mixed, r64, t_mixed, t64, tol, norm_A=12.0):
+    """Acceptance checks of the headline problem (Section 2.2's iteration
+    judged by Section 4.1's closed form), as a list of
+    (name, passed, value, limit).
+
+    exact: the closed-form eigenvalues lambda_1..lambda_{m+1} (one beyond the
+    block, for the gaps).  r_mixed, r64: solve results (lam, X on the device,
+    resid = explicit FP64 residual norms rho_j).  t_mixed, t64: solve times.
+      - every explicit residual <= tol, in both solves;
+      - mixed eigenvalues within 1e-6 (relative) of the closed form;
+      - FP64 eigenvalues within the a-posteriori bound (rho_j ||A||)^2 / gap_j
+        of the closed form (gap_j: distance to the nearest other eigenvalue);
+      - mixed and FP64 eigenvalues within 1e-6 (relative) of each other;
+      - for every complete group of equal eigenvalues G (the block edge of
+        the headline problem falls between groups), the sine of the largest
+        principal angle between the mixed and the FP64 span of G is at most
+        (||R_G^mixed|| + ||R_G^fp64||) / delta_G (Davis-Kahan for each
+        solve against the exact invariant subspace, then the triangle
+        inequality; ||R_G|| <= ||A|| (sum rho_j^2)^(1/2), delta_G the
+        distance from G's eigenvalue to the rest of the spectrum);
+      - X^T X = I to 1e-9 in both solves;
+      - the mixed solve faster than the FP64 one.
+    """
+    import torch
+
+    m = len(r_mixed.lam)
+    lam_ex = np.asarray(exact[:m])
+    out = []
+
+    def gate(name, value, limit):
+        out.append((name, bool(value <= limit), float(value), float(limit)))
+
+    gate("mixed_max_resid", float(np.max(r_mixed.resid)), tol)
+    gate("fp64_max_resid", float(np.max(r64.resid)), tol)
+    gate("mixed_vs_closed_form_rel", float(np.max(np.abs(r_mixed.lam / lam_ex - 1))), 1e-6)
+    worst = 0.0
+    for j in range(m):
+        others = np.abs(np.asarray(exact) - lam_ex[j])
+        gap = others[others > 1e-12 * lam_ex[j]].min()
+        bound = (norm_A * r64.resid[j]) ** 2 / gap
+        worst = max(worst, abs(r64.lam[j] - lam_ex[j]) / max(bound, 1e-300))
+    gate("fp64_vs_closed_form_over_bound", worst, 1.0)
+    gate("mixed_vs_fp64_rel", float(np.max(np.abs(r_mixed.lam / r64.lam - 1))), 1e-6)
+    groups = degenerate_groups(np.asarray(exact))
+    complete = [g for g in groups if g[-1] < m]
+    worst = 0.0
+    for g in complete:
+        Qm, Q64 = r_mixed.X[:, g], r64.X[:, g]
+        E = Qm - Q64 @ (Q64.T @ Qm)
+        s = float(torch.linalg.eigvalsh((E.T @ E).cpu()).max().clamp(min=0.0).sqrt())
+        lam_g = lam_ex[g[0]]
+        outside = [exact[j] for j in range(len(exact)) if j not in g]
+        delta = min(abs(v - lam_g) for v in outside)
+        bound = norm_A * (np.sqrt(np.sum(np.asarray(r_mixed.resid)[g] ** 2)) +
+                          np.sqrt(np.sum(np.asarray(r64.resid)[g] ** 2))) / delta
+        worst = max(worst, s / bound)
+    gate("principal_angles_over_bound", worst, 1.0)
+    for name, r in (("mixed", r_mixed), ("fp64", r64)):
+        G = (r.X.T @ r.X).cpu().numpy()
+        gate(name + "_orthonormality", float(np.abs(G - np.eye(m)).max()), 1e-9)
+    gate("mixed_over_fp64_time", t_mixed / t64, 1.0)
+    return out
 
 
 def levels_for(n):

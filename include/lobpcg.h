@@ -94,9 +94,14 @@ typedef struct lobpcg_ctx lobpcg_ctx;   /* opaque */
 int lobpcg_workspace_bytes(const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T,
                            int m, int precision, size_t *bytes);
 
-/* Create a context.  d_workspace: caller-owned device memory of at least
- * lobpcg_workspace_bytes bytes, 256-byte aligned, kept alive until
- * lobpcg_destroy.  stream: a hipStream_t (NULL = the default stream). */
+/* Create a context: the set-up phase that Section 4's timing tables report
+ * apart from the solve (operator, preconditioner hierarchy, and room for the
+ * 6m vectors that Section 2.2 keeps so that A X and A P need no extra A
+ * products).  d_workspace: caller-owned device memory of
+ * at least lobpcg_workspace_bytes bytes, 256-byte aligned, kept alive until
+ * lobpcg_destroy.  stream: a hipStream_t (NULL = the default stream).
+ * Errors: ARG (as lobpcg_workspace_bytes), WORKSPACE (too small, misaligned
+ * or NULL), HIP (the pinned host staging could not be allocated). */
 int lobpcg_setup(lobpcg_ctx **ctx, const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T,
                  int m, int precision, void *d_workspace, size_t ws_bytes, void *stream);
 
@@ -146,7 +151,12 @@ int lobpcg_solve_constrained(lobpcg_ctx *ctx, const lobpcg_op *A, const lobpcg_o
 int lobpcg_eig_grad_k(lobpcg_ctx *ctx, const double *d_X, const double *h_gbar, int m,
                       double *d_gkx, double *d_gky, double *d_gkz);
 
+/* Release a context made by lobpcg_setup (its host and pinned-host buffers;
+ * the caller's workspace is left alone).  NULL is a no-op. */
 void lobpcg_destroy(lobpcg_ctx *ctx);
+/* A static, human-readable name of a status code above, including the
+ * failure modes Section 2.2 names (Cholesky of steps 3 and 11 failing,
+ * Rayleigh-Ritz of step 24 failing); "unknown status" for other values. */
 const char *lobpcg_status_string(int status);
 
 /* ---------------------------------------------------------------- options and statistics */

@@ -27,6 +27,10 @@ const size_t ALIGN = 256;
 // (3m x m) coefficients in LDS; this bounds m.
 const int LOBPCG_MAX_M = 128;
 const int COEF_SLOTS = 16;
+// Entries of one coefficient ring slot: the (3m x m) update coefficients of
+// steps 25-33, or the ((k + ny) x k) ones of a constraint projection (k <= m,
+// ny <= LOBPCG_MAX_M).
+size_t coef_slot_entries(int m) { return (size_t)std::max(3 * m, m + LOBPCG_MAX_M) * m; }
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 size_t esize(int dt) { return dt == DT_F32 ? 4 : 8; }
@@ -114,11 +118,10 @@ Layout make_layout(const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond 
             for (int j = 0; j < 3; j++) L.mg.push_back(take((size_t)L.levels.back().n() * m * esize(L.mg_dtype)));
         }
     }
-    const int K = 3 * m;
     L.lambda = take(sizeof(double) * m);
     L.jpos = take(sizeof(int) * m);
     L.cols = take(sizeof(int) * COEF_SLOTS * m);
-    L.coef = take((size_t)COEF_SLOTS * K * m * 8);
+    L.coef = take((size_t)COEF_SLOTS * coef_slot_entries(m) * 8);
     L.gram_out = take((size_t)GX_MAX_TILES * 256 * 8);
     L.gram_part = take(gram_partials_bytes(N));
     L.res_part = take((size_t)residual_blocks(N, m) * 2 * m * 8);
@@ -243,10 +246,11 @@ int upload_coef(lobpcg_ctx *c, int dt, const double *C, int rows, int cols, cons
         int s = sync(c);
         if (s) return s;
     }
-    const size_t slot_bytes = (size_t)3 * c->m * c->m * 8;
+    const size_t n = (size_t)rows * cols;
+    if (rows < 0 || cols < 0 || n > coef_slot_entries(c->m)) return LOBPCG_ERR_ARG;
+    const size_t slot_bytes = coef_slot_entries(c->m) * 8;
     char *h = c->h_pin + c->h_coef_off + c->coef_slot * slot_bytes;
     char *d = c->d_coef + c->coef_slot * slot_bytes;
-    const size_t n = (size_t)rows * cols;
     if (dt == DT_F32) {
         float *hf = (float *)h;
         for (size_t i = 0; i < n; i++) hf[i] = (float)C[i];
@@ -262,6 +266,7 @@ int upload_coef(lobpcg_ctx *c, int dt, const double *C, int rows, int cols, cons
 int upload_cols(lobpcg_ctx *c, const std::vector<int> &cols, const int **dptr)
 {
     // same ring index as the coefficients, separate area
+    if (cols.size() > (size_t)c->m) return LOBPCG_ERR_ARG;
     if (c->coef_slot >= COEF_SLOTS) {
         int s = sync(c);
         if (s) return s;
@@ -1560,7 +1565,7 @@ int lobpcg_setup(lobpcg_ctx **out, const lobpcg_op *A, const lobpcg_op *B, const
         off = o + b;
         return o;
     };
-    c->h_coef_off = take((size_t)COEF_SLOTS * 3 * m * m * 8);
+    c->h_coef_off = take((size_t)COEF_SLOTS * coef_slot_entries(m) * 8);
     c->h_cols_off = take((size_t)COEF_SLOTS * m * sizeof(int));
     c->h_gram_off = take((size_t)GX_MAX_TILES * 256 * 8);
     c->h_res_off = take((size_t)2 * m * 8);

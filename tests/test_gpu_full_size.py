@@ -8,6 +8,7 @@ orthonormality of X, and for the eigenvalue adjoint the Euler identity and a
 central finite difference of warm-started solves along a seeded direction.
 """
 import gc
+import time
 
 import numpy as np
 import pytest
@@ -34,6 +35,59 @@ def release():
 def check_orthonormal(X, atol):
     G = (X.T @ X).cpu().numpy()
     np.testing.assert_allclose(G, np.eye(G.shape[0]), rtol=0, atol=atol)
+
+
+def timed_solve(ctx, X0, tol, maxit):
+    L.lobpcg_solve(ctx, X0, tol, 2, hist=False, raise_on_error=False)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = L.lobpcg_solve(ctx, X0, tol, maxit, hist=False)
+    torch.cuda.synchronize()
+    return r, time.perf_counter() - t0
+
+
+def test_n256_m32_mixed_and_fp64():
+    """The headline problem: n=256 (N=16,777,216), m=32, V(2,2) with 6 levels,
+    tol 1e-8, start block uniform[-1,1] seed 2, in the benchmark's launch
+    configuration, mixed precision and FP64.  The gates of the benchmark
+    (every explicit residual <= tol; mixed eigenvalues within 1e-6 of the
+    closed form of Section 4.1; FP64 eigenvalues within the a-posteriori
+    bound; mixed and FP64 eigenvalues within 1e-6 of each other; principal
+    angles between the mixed and FP64 spans of every complete group of equal
+    eigenvalues within the Davis-Kahan bound; X^T X = I to 1e-9; mixed faster
+    than FP64).  Then the FP64 form to rho <= 3.7e-10, where the a-posteriori
+    bound (rho ||A||)^2 / gap guarantees 1e-10 relative for every pair
+    (gap lambda_33 - lambda_32 = 1.5e-4 at the block edge)."""
+    import bench
+
+    n, m, levels, tol = 256, 32, 6, 1e-8
+    N = n ** 3
+    X0 = dev(synth.x0_uniform(N, m, seed=2))
+    exact, _ = closed_form.smallest(n, n, n, m + 1)
+    A, T = L.Op(n, n, n), L.Precond(levels)
+    ctx = L.lobpcg_setup(A, T, m, L.MIXED)
+    rm, tm = timed_solve(ctx, X0, tol, 300)
+    assert rm.status == L.OK
+    del ctx
+    release()
+    ctx = L.lobpcg_setup(A, T, m, L.FP64)
+    r64, t64 = timed_solve(ctx, X0, tol, 300)
+    assert r64.status == L.OK
+    gates = bench.headline_gates(exact, rm, r64, tm, t64, tol)
+    for name, ok, value, limit in gates:
+        print("%-32s %-5s %.3e (limit %.3e)" % (name, ok, value, limit))
+    failed = [(name, value, limit) for name, ok, value, limit in gates if not ok]
+    assert not failed, failed
+    del rm, r64
+    release()
+    tight = 3.7e-10
+    r = L.lobpcg_solve(ctx, X0, tight, 400, hist=False)
+    assert r.status == L.OK
+    assert r.resid.max() <= tight
+    np.testing.assert_allclose(r.lam, exact[:m], rtol=1e-10)
+    check_orthonormal(r.X, 1e-9)
+    del ctx, r, X0
+    release()
 
 
 @pytest.mark.parametrize("tol,rtol", [(1e-8, 1e-8), (1.5e-9, 1e-10)])

@@ -354,6 +354,30 @@ def test_hundred_constraints_give_the_next_eigenpairs():
     assert np.abs(Y.T @ r.X.cpu().numpy()).max() < 1e-10
 
 
+def test_one_column_with_sixty_four_constraints():
+    """m = 1 with 64 constraint vectors: the projection's (1 + 64) x 1
+    coefficients exceed 3 m^2 entries, the size of an update's coefficient
+    slot (regression test for the slot size), and the 64-column Y takes the
+    general (wide) block product."""
+    dims, ny, m, tol = (12, 10, 8), 64, 1, 1e-9
+    N = int(np.prod(dims))
+    lam, ijk = closed_form.smallest(*dims, ny + m + 1)
+    assert lam[ny] - lam[ny - 1] > 5e-3 and lam[ny + 1] - lam[ny] > 5e-3
+    Y = sine_block(dims, ijk[:ny])
+    ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(2), m, L.FP64)
+    # a single vector converging to lambda_65 (relative gap 6e-3 to
+    # lambda_66) takes some hundreds of iterations, in the oracle too
+    for seed in (3, 4):     # twice on one context: the ring slots are reused
+        X0 = synth.x0_uniform(N, m, seed=seed)
+        r = L.lobpcg_solve(ctx, dev(X0), tol, 1000, Y=dev(Y))
+        ref = olob.laplace7_solver(dims, m, X0, tol, 1000, levels=2, Y=Y)
+        assert r.status == L.OK and ref.status == olob.OK
+        np.testing.assert_allclose(r.lam, lam[ny:ny + m], rtol=1e-9)
+        np.testing.assert_allclose(r.lam, ref.lam, rtol=1e-9)
+        assert r.resid.max() <= tol
+        assert np.abs(Y.T @ r.X.cpu().numpy()).max() < 1e-10
+
+
 # ---------------------------------------------------------------- constraints Y (steps 2 and 10)
 
 def sine_block(dims, ijk):
