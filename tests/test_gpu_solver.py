@@ -33,8 +33,41 @@ def solve(dims, m, levels, prec, tol, maxit, seed=2, A=None):
     return ctx, r, X0
 
 
+def active_sets(hist, tol):
+    """The active set J of every iteration, replayed from a residual history
+    with the soft-locking rule both implementations follow: J keeps the
+    columns above tol; if it empties while some column is above tol again,
+    those columns are active again."""
+    J, out = np.arange(hist.shape[1]), []
+    for rho in hist:
+        J = J[rho[J] > tol]
+        if J.size == 0:
+            J = np.flatnonzero(rho > tol)
+        out.append(tuple(J.tolist()))
+    return out
+
+
+def group_histories(hist, groups):
+    """Per group of equal eigenvalues, the root sum of squares of its columns'
+    residual norms: unlike a single column's norm, it does not depend on how
+    the group's Ritz vectors are rotated within the group."""
+    return np.stack([np.sqrt((hist[:, g] ** 2).sum(axis=1)) for g in groups], axis=1)
+
+
 def test_fp64_unpreconditioned_n16_matches_oracle():
-    """Plain FP64 LOBPCG, n=16, m=4, no preconditioner, tol 1e-8."""
+    """Plain FP64 LOBPCG, n=16, m=4, no preconditioner, tol 1e-8.
+
+    lambda_2..4 is a triple eigenvalue.  Within such a group the Ritz vectors
+    are fixed only up to a rotation, which rounding chooses: the oracle run
+    from X0 perturbed by 1e-15 (relative) splits the group's residual among
+    its three columns differently after about 40 iterations, while the
+    group's root sum of squares stays within 1e-8.  So the histories are
+    compared per group (the simple lambda_1 alone, the triple by its root
+    sum of squares) at 1e-6 relative, up to the first iteration at which the
+    active sets differ (a column of the group crossing tol in one run and
+    not the other).  After that iteration the runs take different steps;
+    the iteration counts must then agree within 2 plus the oracle's own
+    spread over rounding-level perturbations of X0."""
     dims, m, tol = (16, 16, 16), 4, 1e-8
     ctx, r, X0 = solve(dims, m, None, L.FP64, tol, 500)
     ref = olob.laplace7_solver(dims, m, X0, tol, 500)
@@ -45,13 +78,21 @@ def test_fp64_unpreconditioned_n16_matches_oracle():
     # agree to the accuracy that tolerance buys: relative 1e-10 in FP64
     np.testing.assert_allclose(r.lam, ref.lam, rtol=1e-10)
     assert r.resid.max() <= tol
-    # without a preconditioner the degenerate triple lambda_2..4 converges
-    # slowly and the iteration at which each of its columns crosses tol (and
-    # is locked or re-activated) flips on rounding: allow 5% of the count
-    assert abs(r.iters - ref.iters) <= max(2, 0.05 * ref.iters), (r.iters, ref.iters)
-    # residual histories follow the oracle's while they are well above rounding
-    k = min(30, r.iters, ref.iters)
-    np.testing.assert_allclose(r.hist[:k], ref.hist[:k], rtol=1e-5)
+    Jg, Jo = active_sets(r.hist, tol), active_sets(ref.hist, tol)
+    k = min(len(Jg), len(Jo))
+    kd = next((i for i in range(k) if Jg[i] != Jo[i]), None)
+    upto = k if kd is None else kd + 1      # the histories of iteration kd still agree
+    groups = [[0], [1, 2, 3]]
+    np.testing.assert_allclose(group_histories(r.hist[:upto], groups), group_histories(ref.hist[:upto], groups),
+                               rtol=1e-6, atol=1e-14)
+    if kd is None:
+        assert abs(r.iters - ref.iters) <= 2, (r.iters, ref.iters)
+    else:
+        rng = np.random.default_rng(11)
+        counts = [olob.laplace7_solver(dims, m, X0 * (1 + 1e-15 * rng.standard_normal(X0.shape)), tol, 500).iters
+                  for _ in range(3)]
+        lo, hi = min(counts + [ref.iters]), max(counts + [ref.iters])
+        assert lo - 2 <= r.iters <= hi + 2, (r.iters, ref.iters, counts, kd)
 
 
 @pytest.mark.parametrize("dims,m,levels", [((24, 20, 16), 6, 3), ((32, 32, 32), 8, 3), ((33, 31, 30), 10, 4)])
@@ -318,11 +359,15 @@ def test_explicit_gram_fp64_matches_oracle():
     np.testing.assert_allclose(r.lam, ref.lam, rtol=1e-10)
     assert r.resid.max() <= tol
     assert abs(r.iters - ref.iters) <= 1, (r.iters, ref.iters)
-    # this run sits next to a loss of orthogonality: its residuals amplify
-    # differences in the Gram products' summation order (row blocking), so
-    # the histories agree to 1e-5 here rather than 1e-6
+    assert active_sets(r.hist, tol) == active_sets(ref.hist, tol)
+    # the histories agree at 1e-6 over the first 8 iterations; later the
+    # columns of the close pair lambda_39, lambda_40 (relative gap 1.8e-3),
+    # whose split between the two Ritz vectors is ill-determined until they
+    # converge, amplify rounding differences steadily (the oracle's own runs
+    # from X0 perturbed by 1e-15 drift the same way, from 7e-8 at iteration
+    # 8 to 1.3e-6 at iteration 16)
     k = min(8, r.iters)
-    np.testing.assert_allclose(r.hist[:k], ref.hist[:k], rtol=1e-5)
+    np.testing.assert_allclose(r.hist[:k], ref.hist[:k], rtol=1e-6, atol=1e-14)
 
 
 def test_block_of_98_fp64():
