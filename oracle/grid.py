@@ -70,6 +70,30 @@ def varcoef7(dims, kx, ky, kz, u):
     return _shape_back(out, u)
 
 
+def mass7(dims, b0, b1, u):
+    """B u for a 7-point mass-type operator: (B u)_p = b0 u_p + b1 * (sum of u
+    over the up to six axis neighbours of p inside the grid).  It is
+    symmetric, and positive definite when b0 > 6 |b1| (strict diagonal
+    dominance): a stand-in for a consistent finite-element mass matrix, the
+    kind of B the generalized problem of Section 2.1.1 is written for.
+    Plain numpy on a zero-padded copy of the grid."""
+    nx, ny, nz = dims
+    uc = _colmajor(u)
+    k = uc.shape[1]
+    g = np.zeros((nz + 2, ny + 2, nx + 2, k))
+    g[1:-1, 1:-1, 1:-1] = np.stack([uc[:, j].reshape(nz, ny, nx) for j in range(k)], axis=3)
+    nb = (g[1:-1, 1:-1, :-2] + g[1:-1, 1:-1, 2:] + g[1:-1, :-2, 1:-1] + g[1:-1, 2:, 1:-1]
+          + g[:-2, 1:-1, 1:-1] + g[2:, 1:-1, 1:-1])
+    out = b0 * g[1:-1, 1:-1, 1:-1] + b1 * nb
+    res = np.asfortranarray(np.stack([out[..., j].ravel() for j in range(k)], axis=1))
+    return _shape_back(res, u)
+
+
+def gershgorin_mass7(b0, b1):
+    """||B||_inf bound b0 + 6 |b1|."""
+    return abs(b0) + 6.0 * abs(b1)
+
+
 def restrict(fine, coarse, r):
     uc = _colmajor(r)
     out = np.empty((coarse[0] * coarse[1] * coarse[2], uc.shape[1]), order="F")

@@ -222,9 +222,10 @@ def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactiva
 
 
 def laplace7_solver(dims, m, X0, tol, maxit, levels=None, nu_pre=2, nu_post=2, coarse_sweeps=20,
-                    omega=2.0 / 3.0, callback=None, Y=None, bdiag=None, explicit_gram=False):
+                    omega=2.0 / 3.0, callback=None, Y=None, bdiag=None, explicit_gram=False, bmass=None):
     """LOBPCG on the 7-point Laplacian with optional V-cycle preconditioning,
-    constraints Y and a positive diagonal B = diag(bdiag) (a lumped mass)."""
+    constraints Y and B = diag(bdiag) (a lumped mass) or B = the 7-point
+    mass-type operator with coefficients bmass = (b0, b1)."""
     from . import grid, mg
     A = lambda V: grid.laplace7(dims, V)
     T = None
@@ -234,6 +235,9 @@ def laplace7_solver(dims, m, X0, tol, maxit, levels=None, nu_pre=2, nu_post=2, c
     if bdiag is not None:
         d = np.asarray(bdiag, dtype=np.float64).reshape(-1)
         Bop = lambda V: d[:, None] * V
+    elif bmass is not None:
+        b0, b1 = bmass
+        Bop = lambda V: grid.mass7(dims, b0, b1, V)
     return lobpcg(A, X0, tol, maxit, grid.gershgorin_laplace7(), apply_T=T, callback=callback, Y=Y, apply_B=Bop,
                   explicit_gram=explicit_gram)
 

@@ -537,3 +537,66 @@ def test_diagonal_B_matches_dense_generalized_eigenproblem():
     assert r.status == lobpcg.OK
     np.testing.assert_allclose(r.lam, mu[[1, 3, 4]], rtol=1e-10)
     assert np.abs(Y.T @ (d[:, None] * r.X)).max() < 1e-10
+
+
+def dense_mass7_by_neighbours(nx, ny, nz, b0, b1):
+    """B[p, p] = b0 and B[p, q] = b1 for the axis neighbours q of p, entered
+    point by point."""
+    N = nx * ny * nz
+    B = np.zeros((N, N))
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                p = x + nx * (y + ny * z)
+                B[p, p] = b0
+                for dx, dy, dz in ((-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)):
+                    a, b, c = x + dx, y + dy, z + dz
+                    if 0 <= a < nx and 0 <= b < ny and 0 <= c < nz:
+                        B[p, a + nx * (b + ny * c)] = b1
+    return B
+
+
+@pytest.mark.parametrize("b0,b1", [(0.5, 1.0 / 12.0), (1.0, -0.1)])
+def test_mass7_matches_neighbour_assembly(b0, b1):
+    dims = (5, 4, 3)
+    N = 60
+    U = np.random.default_rng(31).standard_normal((N, 3))
+    np.testing.assert_allclose(grid.mass7(dims, b0, b1, U), dense_mass7_by_neighbours(*dims, b0, b1) @ U,
+                               rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("b0,b1", [(0.5, 1.0 / 12.0), (1.0, -0.1)])
+def test_mass7_B_closed_form(b0, b1):
+    """B = b0 I + b1 (6 I - L7) shares the sine eigenvectors of L7, so the
+    pencil (L7, B) has eigenvalues mu / (b0 + b1 (6 - mu)) for the closed-form
+    mu; the map is increasing while b0 > 6 |b1|, so the smallest eigenvalues
+    of the pencil are those of the smallest mu.  X comes out B-orthonormal."""
+    dims, m = (12, 10, 8), 4
+    N = int(np.prod(dims))
+    mu, _ = closed_form.smallest(*dims, m)
+    want = mu / (b0 + b1 * (6.0 - mu))
+    r = lobpcg.laplace7_solver(dims, m, synth.x0_uniform(N, m, seed=3), 1e-10, 300, levels=2, bmass=(b0, b1))
+    assert r.status == lobpcg.OK
+    np.testing.assert_allclose(r.lam, want, rtol=1e-9)
+    np.testing.assert_allclose(r.X.T @ grid.mass7(dims, b0, b1, r.X), np.eye(m), atol=1e-10)
+
+
+def test_mass7_B_matches_dense_generalized_eigenproblem():
+    """The pencil (A, B) with A = -div(k grad u) (lognormal k) and the
+    7-point mass-type B, N = 72: eigenvalues of the dense generalized
+    problem (scipy.linalg.eigh(A, B)) with B assembled neighbour by
+    neighbour."""
+    import scipy.linalg
+    dims, m, b0, b1 = (6, 4, 3), 3, 0.5, 1.0 / 12.0
+    N = int(np.prod(dims))
+    kx, ky, kz = lognormal_faces(dims, seed=8)
+    A = dense_varcoef_by_faces(*dims, kx, ky, kz)
+    B = dense_mass7_by_neighbours(*dims, b0, b1)
+    mu = scipy.linalg.eigh(A, B, eigvals_only=True)
+    assert np.all(np.diff(mu[:m + 1]) > 1e-6)
+    Aop = lambda V: grid.varcoef7(dims, kx, ky, kz, V)
+    Bop = lambda V: grid.mass7(dims, b0, b1, V)
+    r = lobpcg.lobpcg(Aop, synth.x0_uniform(N, m, seed=9), 1e-11, 500,
+                      grid.gershgorin_varcoef7(dims, kx, ky, kz), apply_B=Bop)
+    assert r.status == lobpcg.OK
+    np.testing.assert_allclose(r.lam, mu[:m], rtol=1e-10)
