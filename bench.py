@@ -94,7 +94,17 @@ def main():
                     help="comma-separated grid sizes: the problem-size study instead of the headline run")
     ap.add_argument("--seeds", default=None,
                     help="comma-separated start-block seeds: the seed spread instead of the headline run")
+    ap.add_argument("--cpu-baseline-full", action="store_true",
+                    help="instead of the headline run: the FP64 oracle's full time to residual 1e-8 on the "
+                         "host's physical cores, 16^3 m=4 without preconditioner (median of 3) and 128^3 m=16 "
+                         "with the 5-level V-cycle; one JSON line")
+    ap.add_argument("--opt", action="append", default=[],
+                    help="NAME=VALUE: a solver option (lobpcg_set_option, NAME without the OPT_ prefix, e.g. "
+                         "LOCK_GAP=1e-3) set on every context of the run")
     args = ap.parse_args()
+    if args.cpu_baseline_full:
+        cpu_baseline_full()
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path (how it would shard is "
               "described with the design); use --gpus 1", file=sys.stderr)
@@ -104,6 +114,19 @@ def main():
 
     import paper_0705_2626_amd as L
     import synth
+
+    options = []
+    for o in args.opt:
+        name, val = o.split("=", 1)
+        options.append((getattr(L, "OPT_" + name.upper()), float(val)))
+    setup = L.lobpcg_setup
+
+    def setup_with_options(*a, **k):
+        ctx = setup(*a, **k)
+        for key, val in options:
+            L.lobpcg_set_option(ctx, key, val)
+        return ctx
+    L.lobpcg_setup = setup_with_options
 
     torch.cuda.init()
     dev = torch.device("cuda:0")
@@ -461,6 +484,73 @@ def sweep_block_size(args, L, synth, torch, dev):
         del X0
 
 
+def physical_cores():
+    """Physical cores among the CPUs this process may run on (lscpu's
+    core/socket pairs of the allowed CPUs), and the allowed logical CPUs."""
+    import subprocess
+    allowed = os.sched_getaffinity(0)
+    try:
+        out = subprocess.run(["lscpu", "-p=cpu,core,socket"], capture_output=True, text=True, check=True).stdout
+        pairs = set()
+        for line in out.splitlines():
+            if line.startswith("#"):
+                continue
+            cpu, core, sock = (int(v) for v in line.split(","))
+            if cpu in allowed:
+                pairs.add((core, sock))
+        return len(pairs), len(allowed)
+    except (OSError, ValueError, subprocess.CalledProcessError):
+        return len(allowed), len(allowed)
+
+
+_CPU_FULL_CHILD = r"""
+import json, sys, time
+import numpy as np
+sys.path.insert(0, %r)
+import synth
+from oracle import lobpcg as olob
+out = {}
+for name, dims, m, levels, reps in (("16^3 m=4, no preconditioner", (16, 16, 16), 4, None, 3),
+                                    ("128^3 m=16, 5-level V-cycle", (128, 128, 128), 16, 5, 1)):
+    N = dims[0] * dims[1] * dims[2]
+    X0 = synth.x0_uniform(N, m, seed=2)
+    times, iters = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        r = olob.laplace7_solver(dims, m, X0, 1e-8, 500, levels=levels)
+        times.append(time.perf_counter() - t0)
+        iters.append(int(r.iters))
+        assert r.status == olob.OK
+    out[name] = {"seconds_each": times, "median_s": float(np.median(times)), "iterations": iters,
+                 "max_resid": float(r.resid.max())}
+    print(json.dumps({"done": name, **out[name]}), file=sys.stderr, flush=True)
+print(json.dumps(out), flush=True)
+"""
+
+
+def cpu_baseline_full():
+    """The oracle's full time to residual 1e-8 at 16^3 (m=4, median of 3) and
+    128^3 (m=16, 5-level V-cycle), run in a child process whose OpenMP and
+    BLAS thread counts are the physical cores available here."""
+    import subprocess
+    phys, logical = physical_cores()
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        env[k] = str(phys)
+    t0 = time.perf_counter()
+    p = subprocess.run([sys.executable, "-u", "-c", _CPU_FULL_CHILD % ROOT], env=env, capture_output=True,
+                       text=True)
+    if p.returncode != 0:
+        print(p.stderr, file=sys.stderr)
+        sys.exit(p.returncode)
+    res = json.loads(p.stdout.strip().splitlines()[-1])
+    print(json.dumps({"metric": "FP64 oracle time to residual 1e-8 on the host", "unit": "s",
+                      "cores": phys, "logical_cpus_allowed": logical,
+                      "threads_env": {k: env[k] for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS",
+                                                          "MKL_NUM_THREADS")},
+                      "kind": "oracle", "results": res, "wall_s": time.perf_counter() - t0}), flush=True)
+
+
 def cpu_baseline(dims, m, levels, X0, iters):
     """The FP64 oracle at the benchmark size: setup (steps 3-4) plus one loop
     iteration, timed, and extrapolated to `iters` iterations."""
@@ -479,10 +569,14 @@ def cpu_baseline(dims, m, levels, X0, iters):
     t_setup = marks[0] - t0
     t_iter = t_end - marks[0]
     est = t_setup + iters * t_iter
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": est, "unit": "s", "cores": threads, "kind": "oracle",
+    phys, logical = physical_cores()
+    threads = int(os.environ.get("OMP_NUM_THREADS", logical))
+    return {"value": est, "unit": "s", "cores": threads, "physical_cores": phys, "kind": "oracle",
+            "extrapolated": True,
+            "threads_env": {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS")},
             "sample": "FP64 oracle at the same size (n=%d, m=%d): setup + 1 iteration (with the final explicit "
-                      "residual) timed (%.1f s + %.1f s), extrapolated to %d iterations" % (dims[0], m, t_setup, t_iter, iters)}
+                      "residual) timed (%.1f s + %.1f s), extrapolated to %d iterations; the full solves at "
+                      "16^3 and 128^3 are bench.py --cpu-baseline-full" % (dims[0], m, t_setup, t_iter, iters)}
 
 
 if __name__ == "__main__":

@@ -47,7 +47,7 @@ enum {
 };
 
 /* ---------------------------------------------------------------- descriptors */
-enum { LOBPCG_OP_LAPLACE7 = 0, LOBPCG_OP_VARCOEF7 = 1, LOBPCG_OP_DIAG = 2 };
+enum { LOBPCG_OP_LAPLACE7 = 0, LOBPCG_OP_VARCOEF7 = 1, LOBPCG_OP_DIAG = 2, LOBPCG_OP_MASS7 = 3 };
 enum { LOBPCG_PC_NONE = 0, LOBPCG_PC_GMG_V = 1 };
 enum { LOBPCG_FP64 = 0, LOBPCG_MIXED = 1 };     /* solver precision           */
 enum { LOBPCG_F64 = 0, LOBPCG_F32 = 1 };        /* element type of one block  */
@@ -65,6 +65,10 @@ typedef struct lobpcg_op {
     const double *kx, *ky, *kz;     /* VARCOEF7 only, else NULL */
     const double *diag;             /* DIAG only: N positive FP64 entries (device), */
                                     /* B = diag(diag), e.g. a lumped mass matrix    */
+    double b0, b1;                  /* MASS7 only: (B u)_p = b0 u_p + b1 (sum of u  */
+                                    /* over the axis neighbours of p in the grid),  */
+                                    /* b0 > 6 |b1| (symmetric positive definite);   */
+                                    /* a consistent-mass-like B with off-diagonals  */
 } lobpcg_op;
 
 /* Preconditioner T (Section 2.1.1 requires it linear, symmetric, positive
@@ -86,8 +90,9 @@ typedef struct lobpcg_ctx lobpcg_ctx;   /* opaque */
 /* ---------------------------------------------------------------- solver */
 
 /* Device workspace needed by lobpcg_setup for this problem, in bytes.
- * B: NULL (B = I) or a DIAG operator of A's dimensions (A x = lambda B x,
- * Section 2.1.1; FP64 precision only, else ERR_UNSUPPORTED).  m: block
+ * B: NULL (B = I), or a DIAG or MASS7 operator of A's dimensions
+ * (A x = lambda B x, Section 2.1.1, with the B-orthonormalisation and the
+ * B X, B W, B P recurrences of Section 2.2).  m: block
  * size, 1 <= m <= 128 and 3m <= N (blocks of more than 32 columns run through
  * a general path of the block kernels: slower per column).  Pure host code:
  * callable without a GPU. */
@@ -107,8 +112,8 @@ int lobpcg_setup(lobpcg_ctx **ctx, const lobpcg_op *A, const lobpcg_op *B, const
 
 /* Solve for the m smallest eigenpairs (Section 2.2, steps 1-37, no
  * constraints; see lobpcg_solve_constrained for steps 2 and 10).  B must be
- * NULL or the DIAG operator given to setup (its array may differ between
- * calls); with B, X is B-orthonormal and rho_j = ||A x_j - lambda_j B x_j|| /
+ * NULL or an operator of the kind given to setup (a DIAG array or the MASS7
+ * coefficients may differ between calls); with B, X is B-orthonormal and rho_j = ||A x_j - lambda_j B x_j|| /
  * (||A|| ||B x_j||) (for B = I the definition below).  A must have the dimensions and kind given to setup (its
  * face arrays may differ between calls); T must equal setup's.
  *   d_X0         N x m FP64 start block (linearly independent columns)
@@ -187,6 +192,10 @@ enum {
                                     /* and the update coefficients (W_J R^-1 and       */
                                     /* P_J R^-1 are never formed; same algebra, fewer  */
                                     /* passes); 0: applied to the blocks               */
+    LOBPCG_OPT_LOCK_GAP = 9,        /* soft locking by clusters: a column below tol    */
+                                    /* stays active while an unconverged active column */
+                                    /* has a Ritz value within this relative distance  */
+                                    /* of its own (0 <= value < 1)                     */
     LOBPCG_OPT_FP64_EXPLICIT_GRAM = 8 /* 1: FP64 iterations compute the block diagonal */
                                     /* of gramB and X^T AX too (the variant Section    */
                                     /* 2.2 reports testing in MATLAB: better           */

@@ -18,7 +18,7 @@
 
 namespace lobpcg {
 
-enum { EPI_APPLY = 0, EPI_JACOBI = 1, EPI_RESID = 2, EPI_JACOBI2 = 3 };
+enum { EPI_APPLY = 0, EPI_JACOBI = 1, EPI_RESID = 2, EPI_JACOBI2 = 3, EPI_MASS = 4 };
 
 template <typename T, int V>
 __device__ __forceinline__ vec<T, V> lap(const vec<T, V> &c, const vec<T, V> &zm, const vec<T, V> &zp,
@@ -61,6 +61,8 @@ __device__ __forceinline__ void x_neighbours(const vec<T, V> &cur, const T *__re
 // EPI_RESID : out = b - s * L7 u
 // EPI_JACOBI2: two sweeps from zero with right-hand side u:
 //             x1 = c1 u, out = x1 + c1 (u - s L7 x1)
+// EPI_MASS  : out = c1 u + s (sum of the six neighbours), the 7-point
+//             mass-type operator B with b0 = c1, b1 = s
 template <typename T, int V, int EPI, int R>
 __global__ void __launch_bounds__(256) stencil7_kernel(int nx, int ny, int nz, int L, int zchunk,
                                                        const T *__restrict__ u, T *__restrict__ out,
@@ -110,8 +112,16 @@ __global__ void __launch_bounds__(256) stencil7_kernel(int nx, int ny, int nz, i
             x_neighbours<T, V>(cur[r], u, ir, sx, x, nx, L, rok[r], xm, xp);
             const vec<T, V> ym = r == 0 ? ybelow : cur[r - 1];
             const vec<T, V> yp = r == R - 1 ? yabove : cur[r + 1];
-            vec<T, V> au = lap<T, V>(cur[r], prev[r], next[r], xm, xp, ym, yp);
             vec<T, V> o;
+            if (EPI == EPI_MASS) {
+#pragma unroll
+                for (int q = 0; q < V; q++)
+                    o.v[q] = c1 * cur[r].v[q] +
+                             s * (prev[r].v[q] + next[r].v[q] + xm.v[q] + xp.v[q] + ym.v[q] + yp.v[q]);
+                if (active && rok[r]) vstore_nt<T, V>(out + ir, o);
+                continue;
+            }
+            vec<T, V> au = lap<T, V>(cur[r], prev[r], next[r], xm, xp, ym, yp);
             if (EPI == EPI_APPLY) {
 #pragma unroll
                 for (int q = 0; q < V; q++) o.v[q] = s * au.v[q];
@@ -250,6 +260,7 @@ static hipError_t dispatch_epi(int epi, const Grid3 &g, int k, const void *u, vo
     case EPI_APPLY: return dispatch_vec<T, EPI_APPLY>(g, k, u, out, b, s, c1, st);
     case EPI_JACOBI: return dispatch_vec<T, EPI_JACOBI>(g, k, u, out, b, s, c1, st);
     case EPI_JACOBI2: return dispatch_vec<T, EPI_JACOBI2>(g, k, u, out, b, s, c1, st);
+    case EPI_MASS: return dispatch_vec<T, EPI_MASS>(g, k, u, out, b, s, c1, st);
     default: return dispatch_vec<T, EPI_RESID>(g, k, u, out, b, s, c1, st);
     }
 }
@@ -258,6 +269,13 @@ hipError_t launch_laplace7(int dtype, const Grid3 &g, int k, const void *u, void
 {
     if (dtype == DT_F32) return dispatch_epi<float>(EPI_APPLY, g, k, u, out, nullptr, s, 0.0, st);
     return dispatch_epi<double>(EPI_APPLY, g, k, u, out, nullptr, s, 0.0, st);
+}
+
+hipError_t launch_mass7(int dtype, const Grid3 &g, int k, double b0, double b1, const void *u, void *out,
+                        hipStream_t st)
+{
+    if (dtype == DT_F32) return dispatch_epi<float>(EPI_MASS, g, k, u, out, nullptr, b1, b0, st);
+    return dispatch_epi<double>(EPI_MASS, g, k, u, out, nullptr, b1, b0, st);
 }
 
 hipError_t launch_jacobi(int dtype, const Grid3 &g, int k, const void *x, const void *b, void *out, double s,

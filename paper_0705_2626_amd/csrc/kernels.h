@@ -17,6 +17,9 @@ struct Grid3 {
 // ---- stencils (k_stencil.hip)
 // out = s * L7 u
 hipError_t launch_laplace7(int dtype, const Grid3 &g, int k, const void *u, void *out, double s, hipStream_t st);
+// out = b0 u + b1 (sum of the six axis neighbours of u), zero beyond the grid
+hipError_t launch_mass7(int dtype, const Grid3 &g, int k, double b0, double b1, const void *u, void *out,
+                        hipStream_t st);
 // out = x + omega/(6 s) (b - s L7 x)        (weighted Jacobi on s*L7)
 hipError_t launch_jacobi(int dtype, const Grid3 &g, int k, const void *x, const void *b, void *out, double s,
                          double omega, hipStream_t st);

@@ -49,6 +49,7 @@ struct Blocks {
 struct Layout {
     size_t blocks64, blocks32;          // offsets (or SIZE_MAX if absent)
     size_t blocksB;                     // the five FP64 B-blocks (or SIZE_MAX)
+    size_t blocksB32;                   // the five FP32 B-blocks of the mixed solver (or SIZE_MAX)
     std::vector<size_t> mg;             // per level l >= 1: x, b, t (3 entries each)
     size_t lambda, jpos, cols, coef, gram_out, gram_part, res_part, mv_part, res_out, wvec;
     size_t total;
@@ -65,16 +66,22 @@ bool op_ok(const lobpcg_op *A)
     return false;
 }
 
+// B of A's grid: a positive diagonal, or the 7-point mass-type operator
+// b0 I + b1 (neighbour sum) with b0 > 6 |b1| (strictly diagonally dominant)
+bool b_ok(const lobpcg_op *A, const lobpcg_op *B)
+{
+    if (B->nx != A->nx || B->ny != A->ny || B->nz != A->nz) return false;
+    if (B->kind == LOBPCG_OP_DIAG) return B->diag != nullptr;
+    if (B->kind == LOBPCG_OP_MASS7)
+        return std::isfinite(B->b0) && std::isfinite(B->b1) && B->b0 > 6.0 * std::fabs(B->b1);
+    return false;
+}
+
 int check_common(const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T, int m, int precision)
 {
     if (!op_ok(A)) return LOBPCG_ERR_ARG;
     if (precision != LOBPCG_FP64 && precision != LOBPCG_MIXED) return LOBPCG_ERR_ARG;
-    if (B) {
-        // B = diag(d): a positive diagonal of A's grid, FP64 solver only
-        if (B->kind != LOBPCG_OP_DIAG || !B->diag || B->nx != A->nx || B->ny != A->ny || B->nz != A->nz)
-            return LOBPCG_ERR_ARG;
-        if (precision != LOBPCG_FP64) return LOBPCG_ERR_UNSUPPORTED;
-    }
+    if (B && !b_ok(A, B)) return LOBPCG_ERR_ARG;
     const long long N = (long long)A->nx * A->ny * A->nz;
     if (m < 1 || m > LOBPCG_MAX_M || 3LL * m > N) return LOBPCG_ERR_ARG;
     if (T) {
@@ -109,6 +116,7 @@ Layout make_layout(const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond 
     L.blocks64 = take(11 * (size_t)N * m * 8);
     L.blocks32 = precision == LOBPCG_MIXED ? take(11 * (size_t)N * m * 4) : (size_t)-1;
     L.blocksB = B ? take(5 * (size_t)N * m * 8) : (size_t)-1;
+    L.blocksB32 = (B && precision == LOBPCG_MIXED) ? take(5 * (size_t)N * m * 4) : (size_t)-1;
     L.mg_dtype = precision == LOBPCG_MIXED ? DT_F32 : DT_F64;
     L.levels.push_back(Grid3{A->nx, A->ny, A->nz});
     if (has_mg(T)) {
@@ -165,6 +173,8 @@ struct lobpcg_ctx {
     int stall_window;
     double stall_factor;
     bool profile, reactivate;
+    double lock_gap;              // soft locking keeps a converged column active while an unconverged
+                                  // one has a Ritz value within this relative distance (0: off)
     int mv_variant, gram_staged, gram_nt4, gram_nt32, gram_direct;  // kernel variants (see LOBPCG_OPT_KERNELS)
     bool fp32_explicit;           // FP32 phase: Gram diagonal blocks computed, not assumed
     bool fp64_explicit;           // the same for FP64 iterations
@@ -282,13 +292,20 @@ int upload_cols(lobpcg_ctx *c, const std::vector<int> &cols, const int **dptr)
 
 // ---- kernel-level building blocks (asynchronous unless they return host data)
 
-// B applied to an N x k FP64 block (B = diag(d))
-int apply_B(lobpcg_ctx *c, const void *in, void *out, int k, int step)
+// B applied to an N x k block of precision dt (B = diag(d), or the 7-point
+// mass-type operator)
+int apply_B(lobpcg_ctx *c, int dt, const void *in, void *out, int k, int step)
 {
     prof_begin(c, step);
-    hipError_t e = launch_diag_scale(DT_F64, c->N, k, c->Bop.diag, in, out, c->st);
+    hipError_t e;
+    if (c->Bop.kind == LOBPCG_OP_MASS7) {
+        e = launch_mass7(dt, c->g, k, c->Bop.b0, c->Bop.b1, in, out, c->st);
+        add_bytes(c, step, 2.0 * k * c->N * esize(dt));
+    } else {
+        e = launch_diag_scale(dt, c->N, k, c->Bop.diag, in, out, c->st);
+        add_bytes(c, step, 2.0 * k * c->N * esize(dt) + 8.0 * c->N);
+    }
     prof_end(c);
-    add_bytes(c, step, (2.0 * k + 1.0) * c->N * 8.0);
     return e == hipSuccess ? LOBPCG_OK : LOBPCG_ERR_HIP;
 }
 
@@ -935,7 +952,7 @@ int folded_step(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState
     if (s) return s;
     const bool hb = c->hasB;
     if (hb) {
-        s = apply_B(c, B.W, B.BW, nJ, LOBPCG_STEP_APPLY_A);
+        s = apply_B(c, dt, B.W, B.BW, nJ, LOBPCG_STEP_APPLY_A);
         if (s) return s;
     }
     // P_J: the active columns that have a direction, read in place from B.P
@@ -1182,8 +1199,16 @@ int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &
         else c->stats.iters_fp64++;
         // step 8: drop converged columns; end only when every residual is small
         std::vector<int> Jn;
-        for (int j : ps.J)
-            if (rho[j] > tol) Jn.push_back(j);
+        for (int j : ps.J) {
+            bool keep = rho[j] > tol;
+            // a converged column of a cluster stays active while a column of
+            // the same cluster is still unconverged
+            for (size_t i = 0; i < ps.J.size() && !keep && c->lock_gap > 0.0; i++) {
+                const int a = ps.J[i];
+                keep = rho[a] > tol && std::fabs(ps.lam[a] - ps.lam[j]) <= c->lock_gap * std::fabs(ps.lam[a]);
+            }
+            if (keep) Jn.push_back(j);
+        }
         if (Jn.empty() && c->reactivate)
             for (int j = 0; j < m; j++)
                 if (rho[j] > tol) Jn.push_back(j);
@@ -1416,7 +1441,7 @@ int init_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState 
         const void *BSb[1] = {hb ? B.BX[ps.cur] : nullptr};
         int w1[1] = {m};
         if (hb) {
-            s = apply_B(c, B.X[ps.cur], B.BX[ps.cur], m, LOBPCG_STEP_ORTHO);
+            s = apply_B(c, dt, B.X[ps.cur], B.BX[ps.cur], m, LOBPCG_STEP_ORTHO);
             if (s) return s;
         }
         s = gram(c, dt, 1, Sb, nullptr, w1, SS, nullptr, LOBPCG_STEP_ORTHO, false, nullptr, nullptr, false,
@@ -1439,11 +1464,19 @@ int init_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState 
         if (s) return s;
         ps.cur = 1 - ps.cur;
     }
+    if (hb && !ortho) {
+        // B X of a start block that was not B-orthonormalised here (the
+        // FP64 restart of the mixed solver)
+        s = apply_B(c, dt, B.X[ps.cur], B.BX[ps.cur], m, LOBPCG_STEP_OTHER);
+        if (s) return s;
+    }
     s = apply_A(c, A, dt, B.X[ps.cur], B.AX[ps.cur], m);
     if (s) return s;
-    const void *Sb[1] = {B.X[ps.cur]}, *ASb[1] = {B.AX[ps.cur]};
+    const void *Sb[1] = {B.X[ps.cur]}, *ASb[1] = {B.AX[ps.cur]}, *BSb1[1] = {hb ? B.BX[ps.cur] : nullptr};
     int w1[1] = {m};
-    s = gram(c, dt, 1, Sb, ASb, w1, SS, &SAS, LOBPCG_STEP_GRAM);
+    // X^T B X (X^T X for B = I) and X^T A X
+    s = gram(c, dt, 1, Sb, ASb, w1, SS, &SAS, LOBPCG_STEP_GRAM, false, nullptr, nullptr, false,
+             hb ? BSb1 : nullptr);
     if (s) return s;
     if (!all_finite(SS) || !all_finite(SAS)) return LOBPCG_ERR_NONFINITE;
     if (!explicit_gram) {
@@ -1488,7 +1521,7 @@ const char *lobpcg_status_string(int s)
     case LOBPCG_OK: return "converged";
     case LOBPCG_NOT_CONVERGED: return "not converged within maxit";
     case LOBPCG_ERR_ARG: return "invalid argument";
-    case LOBPCG_ERR_UNSUPPORTED: return "unsupported (B must be the identity)";
+    case LOBPCG_ERR_UNSUPPORTED: return "unsupported combination of options";
     case LOBPCG_ERR_WORKSPACE: return "workspace too small or misaligned";
     case LOBPCG_ERR_CHOL: return "Cholesky factorisation failed";
     case LOBPCG_ERR_RR: return "Rayleigh-Ritz failed";
@@ -1540,6 +1573,12 @@ int lobpcg_setup(lobpcg_ctx **out, const lobpcg_op *A, const lobpcg_op *B, const
     }
     if (precision == LOBPCG_MIXED) c->b32 = carve_blocks(c->ws + L.blocks32, c->N, m, DT_F32);
     else memset(&c->b32, 0, sizeof(c->b32));
+    if (B && precision == LOBPCG_MIXED) {
+        const size_t bs = (size_t)c->N * m * 4;
+        char *bb = c->ws + L.blocksB32;
+        c->b32.BX[0] = bb, c->b32.BX[1] = bb + bs, c->b32.BW = bb + 2 * bs, c->b32.BP = bb + 3 * bs;
+        c->b32.BPJ = bb + 4 * bs;
+    }
     c->mgx.assign(L.levels.size(), nullptr);
     c->mgb.assign(L.levels.size(), nullptr);
     c->mgt.assign(L.levels.size(), nullptr);
@@ -1581,6 +1620,7 @@ int lobpcg_setup(lobpcg_ctx **out, const lobpcg_op *A, const lobpcg_op *B, const
     c->stall_factor = 0.95;
     c->profile = false;
     c->reactivate = true;
+    c->lock_gap = 0.0;
     c->mv_variant = 0;
     c->gram_staged = 0;
     c->gram_nt4 = 0;
@@ -1631,6 +1671,10 @@ int lobpcg_set_option(lobpcg_ctx *c, int key, double v)
         }
         return LOBPCG_OK;
     case LOBPCG_OPT_REACTIVATE: c->reactivate = v != 0; return LOBPCG_OK;
+    case LOBPCG_OPT_LOCK_GAP:
+        if (!(v >= 0.0 && v < 1.0)) return LOBPCG_ERR_ARG;
+        c->lock_gap = v;
+        return LOBPCG_OK;
     case LOBPCG_OPT_FP32_EXPLICIT_GRAM: c->fp32_explicit = v != 0; return LOBPCG_OK;
     case LOBPCG_OPT_FOLD_CHOLQR: c->fold = v != 0; return LOBPCG_OK;
     case LOBPCG_OPT_FP64_EXPLICIT_GRAM: c->fp64_explicit = v != 0; return LOBPCG_OK;
@@ -1675,8 +1719,7 @@ static int solve_impl(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, con
         return LOBPCG_ERR_ARG;
     if ((B != nullptr) != c->hasB) return LOBPCG_ERR_ARG;
     if (B) {
-        if (B->kind != LOBPCG_OP_DIAG || !B->diag || B->nx != c->g.nx || B->ny != c->g.ny || B->nz != c->g.nz)
-            return LOBPCG_ERR_ARG;
+        if (B->kind != c->Bop.kind || !b_ok(&c->A, B)) return LOBPCG_ERR_ARG;
         c->Bop = *B;
     }
     if (ny < 0 || ny > LOBPCG_MAX_M || (ny > 0 && !d_Y) || 3LL * m + ny > c->N) return LOBPCG_ERR_ARG;
@@ -1733,6 +1776,10 @@ static int solve_impl(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, con
             if (np) {
                 s = apply_A(c, A, DT_F64, c->b64.P, c->b64.AP, np);
                 if (s) return s;
+                if (c->hasB) {
+                    s = apply_B(c, DT_F64, c->b64.P, c->b64.BP, np, LOBPCG_STEP_OTHER);
+                    if (s) return s;
+                }
             }
             ps.cur = 0;
             s = init_phase(c, A, DT_F64, c->b64, ps, false, true);
@@ -1767,7 +1814,7 @@ static int solve_impl(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, con
         if (s) return s;
         const void *BXf = c->b64.X[ps.cur];
         if (c->hasB) {
-            s = apply_B(c, c->b64.X[ps.cur], c->b64.BW, m, LOBPCG_STEP_OTHER);
+            s = apply_B(c, DT_F64, c->b64.X[ps.cur], c->b64.BW, m, LOBPCG_STEP_OTHER);
             if (s) return s;
             BXf = c->b64.BW;
         }

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "liblobpcg.so")
 
 OK, NOT_CONVERGED = 0, 1
 ERR_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_CHOL, ERR_RR, ERR_NONFINITE, ERR_HIP = -1, -2, -3, -4, -5, -6, -7
-OP_LAPLACE7, OP_VARCOEF7, OP_DIAG = 0, 1, 2
+OP_LAPLACE7, OP_VARCOEF7, OP_DIAG, OP_MASS7 = 0, 1, 2, 3
 PC_NONE, PC_GMG_V = 0, 1
 FP64, MIXED = 0, 1
 F64, F32 = 0, 1
@@ -25,6 +25,7 @@ OPT_SWITCH_TOL, OPT_STALL_WINDOW, OPT_STALL_FACTOR, OPT_PROFILE, OPT_REACTIVATE,
 OPT_FP32_EXPLICIT_GRAM = 6
 OPT_FOLD_CHOLQR = 7
 OPT_FP64_EXPLICIT_GRAM = 8
+OPT_LOCK_GAP = 9
 STEP_NAMES = ["residual", "precond", "ortho", "apply_A", "gram", "rr_host", "update", "other"]
 
 
@@ -37,7 +38,7 @@ class LobpcgError(RuntimeError):
 class _Op(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("kind", ctypes.c_int),
                 ("kx", ctypes.c_void_p), ("ky", ctypes.c_void_p), ("kz", ctypes.c_void_p),
-                ("diag", ctypes.c_void_p)]
+                ("diag", ctypes.c_void_p), ("b0", ctypes.c_double), ("b1", ctypes.c_double)]
 
 
 class _Precond(ctypes.Structure):
@@ -153,6 +154,18 @@ class Diag:
 
     def c(self):
         return _Op(*self.dims, OP_DIAG, None, None, None, self.d.data_ptr())
+
+
+class Mass7:
+    """B = the 7-point mass-type operator on the grid of A: (B u)_p = b0 u_p
+    + b1 (sum of u over the axis neighbours of p), b0 > 6 |b1|."""
+
+    def __init__(self, nx, ny, nz, b0, b1):
+        self.dims = (int(nx), int(ny), int(nz))
+        self.b0, self.b1 = float(b0), float(b1)
+
+    def c(self):
+        return _Op(*self.dims, OP_MASS7, None, None, None, None, self.b0, self.b1)
 
 
 class Precond:

@@ -70,19 +70,28 @@ def test_workspace_bytes_rejects_bad_arguments(dims, levels, m, prec, want):
     assert s == want
 
 
-def test_B_must_be_a_positive_diagonal_of_the_grid():
-    """B: a DIAG descriptor of A's grid (FP64 solver); its array is not read
-    by the workspace query, so a placeholder address is enough here."""
+def test_B_must_be_a_positive_diagonal_or_a_dominant_mass7_of_the_grid():
+    """B: a DIAG descriptor of A's grid, or MASS7 with b0 > 6 |b1| (then
+    symmetric positive definite); the diagonal array is not read by the
+    workspace query, so a placeholder address is enough here."""
     fake = 256
     diag = _Op(8, 8, 8, L.OP_DIAG, None, None, None, fake)
     s0, n0 = ws((8, 8, 8), None, 2, L.FP64)
     s, n = ws((8, 8, 8), None, 2, L.FP64, B=diag)
     assert s == s0 == L.OK
     assert n - n0 >= 5 * 512 * 2 * 8                 # B X (twice), B W, B P and a spare
-    assert ws((8, 8, 8), None, 2, L.MIXED, B=diag)[0] == L.ERR_UNSUPPORTED
-    assert ws((8, 8, 8), None, 2, L.FP64, B=L.Op(8, 8, 8).c())[0] == L.ERR_ARG          # not a diagonal
+    s0m, n0m = ws((8, 8, 8), None, 2, L.MIXED)
+    sm, nm = ws((8, 8, 8), None, 2, L.MIXED, B=diag)
+    assert s0m == sm == L.OK
+    assert nm - n0m >= 5 * 512 * 2 * (8 + 4)         # the B-blocks in both precisions
+    assert ws((8, 8, 8), None, 2, L.FP64, B=L.Op(8, 8, 8).c())[0] == L.ERR_ARG          # not a B kind
     assert ws((8, 8, 8), None, 2, L.FP64, B=_Op(8, 8, 4, L.OP_DIAG, None, None, None, fake))[0] == L.ERR_ARG
     assert ws((8, 8, 8), None, 2, L.FP64, B=_Op(8, 8, 8, L.OP_DIAG, None, None, None, None))[0] == L.ERR_ARG
+    assert ws((8, 8, 8), None, 2, L.FP64, B=L.Mass7(8, 8, 8, 0.6, 1.0 / 12.0).c())[0] == L.OK
+    assert ws((8, 8, 8), None, 2, L.MIXED, B=L.Mass7(8, 8, 8, 1.0, -0.1).c())[0] == L.OK
+    for b0, b1 in ((0.5, 1.0 / 12.0), (0.6, -0.1), (0.0, 0.0), (float("nan"), 0.0)):   # not dominant
+        assert ws((8, 8, 8), None, 2, L.FP64, B=L.Mass7(8, 8, 8, b0, b1).c())[0] == L.ERR_ARG
+    assert ws((8, 8, 8), None, 2, L.FP64, B=L.Mass7(8, 8, 7, 0.5, 0.01).c())[0] == L.ERR_ARG
 
 
 def test_setup_rejects_small_or_missing_workspace():

@@ -213,6 +213,82 @@ def test_autograd_directional_finite_difference():
     assert fd == pytest.approx(dirderiv, rel=1e-5)
 
 
+def face_rayleigh_quotients(dims, k, X):
+    """lambda_i = sum_f k_f (x_i[p] - x_i[q])^2 / (x_i, x_i), the face-sum
+    form of the Rayleigh quotient (a sum of non-negative terms), evaluated on
+    the host in extended precision (numpy longdouble), so that its rounding
+    stays far below the finite-difference signal."""
+    nx, ny, nz = dims
+    kx, ky, kz = (np.asarray(a, dtype=np.longdouble) for a in k)
+    Xh = X.cpu().numpy().astype(np.longdouble)
+    out = []
+    for i in range(Xh.shape[1]):
+        g = np.zeros((nz + 2, ny + 2, nx + 2), dtype=np.longdouble)
+        g[1:-1, 1:-1, 1:-1] = Xh[:, i].reshape(nz, ny, nx)
+        e = (np.sum(kx * np.diff(g[1:-1, 1:-1, :], axis=2) ** 2) + np.sum(ky * np.diff(g[1:-1, :, 1:-1], axis=1) ** 2)
+             + np.sum(kz * np.diff(g[:, 1:-1, 1:-1], axis=0) ** 2))
+        out.append(e / np.sum(Xh[:, i] ** 2))
+    return np.array(out)
+
+
+def test_per_face_finite_differences_through_eig_smallest():
+    """The adjoint of EigSmallest against central differences (relative step
+    h = 1e-6) of single face coefficients, on 200 seeded faces of a
+    12 x 11 x 10 grid (lognormal k), for each of the m = 4 eigenvalues.
+    Here one face moves lambda by about lambda / #faces, a difference of
+    some 1e6 units in the last place of lambda, so the quotient resolves
+    1e-5 (at n = 96 it would not).  lambda(k +- h k_f e_f) is the Rayleigh
+    quotient, in extended precision, of a warm-started solve to rho <= 1e-12
+    (its error is quadratic in the vector's: about (rho ||A||)^2 / gap).  A face where a mode
+    is nearly flat (x_p close to x_q, e.g. across a symmetry plane of the
+    mode) has a derivative close to zero; the relative error is taken
+    against max(|g_f|, 1e-2 * the median |g| of the sampled faces)."""
+    from paper_0705_2626_amd.autograd import EigSmallest
+
+    dims, m, h = (12, 11, 10), 4, 1e-6
+    N = int(np.prod(dims))
+    kx, ky, kz = synth.gaussian_field_faces(*dims, sigma=0.5, corr=4.0, seed=3)
+    shapes = [a.shape for a in (kx, ky, kz)]
+    sizes = [a.size for a in (kx, ky, kz)]
+    K = [dev(a).requires_grad_(True) for a in (kx, ky, kz)]
+    solver = L.lobpcg_setup(L.Op(*dims, *[k.detach() for k in K]), L.Precond(2), m, L.FP64)
+    # warm starts from an iterate already at rho ~ 1e-11: with the Cholesky-QR
+    # factors folded into the Gram matrices, X^T W R^-1 carries the rounding
+    # of X^T W amplified by the condition of R (W is then nearly rank
+    # deficient), and on some faces the residuals drift up instead of down;
+    # with the factors applied to the blocks (the printed form) they converge
+    L.lobpcg_set_option(solver, L.OPT_FOLD_CHOLQR, 0)
+    X0 = dev(synth.x0_uniform(N, m, seed=4))
+    lam = EigSmallest.apply(*K, solver, X0, 1e-12, 500)
+    assert np.all(np.diff(lam.detach().cpu().numpy()) > 1e-4)     # simple eigenvalues
+    grads = []
+    for i in range(m):
+        g = torch.autograd.grad(lam[i], K, retain_graph=True)
+        grads.append(np.concatenate([gi.detach().cpu().numpy().ravel() for gi in g]))
+    X = L.lobpcg_solve(solver, X0, 1e-12, 500, hist=False).X
+    flat = np.concatenate([kx.ravel(), ky.ravel(), kz.ravel()])
+    faces = synth.sample_faces(flat.size, 200, seed=5)
+    floor = [1e-2 * np.median(np.abs(grads[i][faces])) for i in range(m)]
+    worst = 0.0
+    for f in faces:
+        vals = []
+        for sgn in (1.0, -1.0):
+            kp = flat.copy()
+            kp[f] *= 1.0 + sgn * h
+            parts = np.split(kp, np.cumsum(sizes)[:-1])
+            Kp = [dev(a.reshape(sh)) for a, sh in zip(parts, shapes)]
+            Ap = L.Op(*dims, *Kp)
+            r = L.lobpcg_solve(solver, X, 1e-12, 200, A=Ap, hist=False)
+            assert r.status == L.OK
+            vals.append(face_rayleigh_quotients(dims, [a.reshape(sh) for a, sh in zip(parts, shapes)], r.X))
+        fd = np.asarray((vals[0] - vals[1]) / (2.0 * h * flat[f]), dtype=np.float64)
+        for i in range(m):
+            g = grads[i][f]
+            worst = max(worst, abs(fd[i] - g) / max(abs(g), floor[i]))
+    print("per-face central differences: largest relative error %.2e" % worst)
+    assert worst < 1e-5
+
+
 def test_error_paths():
     dims, m = (8, 8, 8), 3
     N = 512
@@ -521,15 +597,64 @@ def test_scalar_B_scales_the_closed_form():
     np.testing.assert_allclose(r.lam, exact / c, rtol=1e-9)
 
 
-def test_diagonal_B_unsupported_combinations():
+def test_B_unsupported_combinations():
+    """B with constraints, or with the Cholesky-QR factors applied instead of
+    folded, is not provided."""
     dims, m = (12, 10, 8), 3
     N = int(np.prod(dims))
-    Bd = L.Diag(*dims, dev(lumped_mass(N, 1)))
-    with pytest.raises(L.LobpcgError):
-        L.lobpcg_setup(L.Op(*dims), L.Precond(None), m, L.MIXED, B=Bd)
-    ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(None), m, L.FP64, B=Bd)
-    X0 = dev(synth.x0_uniform(N, m))
-    r = L.lobpcg_solve(ctx, X0, 1e-8, 10, Y=dev(synth.random_block(N, 2, seed=3)), raise_on_error=False)
-    assert r.status == L.ERR_UNSUPPORTED
-    L.lobpcg_set_option(ctx, L.OPT_FOLD_CHOLQR, 0)
-    assert L.lobpcg_solve(ctx, X0, 1e-8, 10, raise_on_error=False).status == L.ERR_UNSUPPORTED
+    for Bd in (L.Diag(*dims, dev(lumped_mass(N, 1))), L.Mass7(*dims, 0.6, 1.0 / 12.0)):
+        ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(None), m, L.FP64, B=Bd)
+        X0 = dev(synth.x0_uniform(N, m))
+        r = L.lobpcg_solve(ctx, X0, 1e-8, 10, Y=dev(synth.random_block(N, 2, seed=3)), raise_on_error=False)
+        assert r.status == L.ERR_UNSUPPORTED
+        L.lobpcg_set_option(ctx, L.OPT_FOLD_CHOLQR, 0)
+        assert L.lobpcg_solve(ctx, X0, 1e-8, 10, raise_on_error=False).status == L.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("b0,b1", [(0.6, 1.0 / 12.0), (1.0, -0.1)])
+def test_mass7_B_fp64_matches_oracle_and_closed_form(b0, b1):
+    """A x = lambda B x with the 7-point mass-type B: eigenvalues mu / (b0 +
+    b1 (6 - mu)) of the closed-form mu, the oracle's iteration within 2,
+    X B-orthonormal, every explicit residual ||Ax - lambda Bx|| / (||A|| ||Bx||)
+    <= tol."""
+    dims, m, levels, tol = (20, 18, 16), 6, 3, 1e-9
+    N = int(np.prod(dims))
+    X0 = synth.x0_uniform(N, m, seed=8)
+    ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(levels), m, L.FP64, B=L.Mass7(*dims, b0, b1))
+    r = L.lobpcg_solve(ctx, dev(X0), tol, 300)
+    ref = olob.laplace7_solver(dims, m, X0, tol, 300, levels=levels, bmass=(b0, b1))
+    mu, _ = closed_form.smallest(*dims, m)
+    assert r.status == L.OK and ref.status == olob.OK
+    np.testing.assert_allclose(r.lam, mu / (b0 + b1 * (6.0 - mu)), rtol=5e-9)
+    np.testing.assert_allclose(r.lam, ref.lam, rtol=5e-9)
+    assert r.resid.max() <= tol
+    X = r.X.cpu().numpy()
+    np.testing.assert_allclose(X.T @ grid.mass7(dims, b0, b1, X), np.eye(m), atol=1e-10)
+    assert abs(r.iters - ref.iters) <= 2, (r.iters, ref.iters)
+
+
+@pytest.mark.parametrize("kind", ["diag", "mass7"])
+def test_B_in_mixed_precision_reaches_fp64_accuracy(kind):
+    """The mixed solver with B (FP32 iterations with FP32 B X, B W, B P
+    recurrences, then the FP64 finish from the FP32 iterate): eigenvalues
+    within 1e-6 of the FP64 oracle's, every explicit FP64 residual <= tol, X
+    B-orthonormal."""
+    dims, m, levels, tol = (32, 30, 28), 8, 3, 1e-8
+    N = int(np.prod(dims))
+    X0 = synth.x0_uniform(N, m, seed=2)
+    if kind == "diag":
+        d = lumped_mass(N, 21)
+        Bd, kw, Bapply = L.Diag(*dims, dev(d)), {"bdiag": d}, (lambda V: d[:, None] * V)
+    else:
+        b0, b1 = 1.0, -0.1
+        Bd, kw, Bapply = L.Mass7(*dims, b0, b1), {"bmass": (b0, b1)}, (lambda V: grid.mass7(dims, b0, b1, V))
+    ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(levels), m, L.MIXED, B=Bd)
+    r = L.lobpcg_solve(ctx, dev(X0), tol, 300)
+    st = L.lobpcg_get_stats(ctx)
+    ref = olob.laplace7_solver(dims, m, X0, tol, 300, levels=levels, **kw)
+    assert r.status == L.OK and ref.status == olob.OK
+    assert st["iters_fp32"] > 0 and st["iters_fp64"] > 0
+    np.testing.assert_allclose(r.lam, ref.lam, rtol=1e-6)
+    assert r.resid.max() <= tol
+    X = r.X.cpu().numpy()
+    np.testing.assert_allclose(X.T @ Bapply(X), np.eye(m), atol=1e-9)
