@@ -84,7 +84,7 @@ def b_orthonormalize(V, BV, *others):
 
 
 def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactivate=True, Y=None, apply_B=None,
-           explicit_gram=False):
+           explicit_gram=False, lock_gap=0.0):
     """Smallest eigenpairs of A x = lambda B x (Section 2.1.1).
 
     apply_A, apply_T, apply_B: functions on (N, k) blocks (apply_B None: B = I).
@@ -100,6 +100,10 @@ def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactiva
     of gramB (X^T B X, W^T B W, P_J^T B P_J) instead of taking identities, and
     with it the X block of gramA (X^T A X instead of Lambda), so that the
     Rayleigh-Ritz procedure sees the basis as it is after rounding.
+    lock_gap: soft locking by clusters (a reading, off at 0): a column whose
+    residual is below tol stays in J while a column of J that is still above
+    tol has a Ritz value within the relative distance lock_gap of its own, so
+    that the members of a cluster leave J together.
     """
     X0 = np.asfortranarray(np.asarray(X0, dtype=np.float64))
     N, m = X0.shape
@@ -143,7 +147,13 @@ def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactiva
         if not np.all(np.isfinite(rho)):
             status = ERR_NONFINITE
             break
-        J = J[rho[J] > tol]                                    # step 8
+        above = rho[J] > tol                                   # step 8
+        if lock_gap > 0.0:
+            U = J[above]
+            for i, j in enumerate(J):
+                if not above[i] and np.any(np.abs(lam[U] - lam[j]) <= lock_gap * np.abs(lam[U])):
+                    above[i] = True
+        J = J[above]
         if J.size == 0 and reactivate:
             J = np.flatnonzero(rho > tol)
         if callback is not None:
@@ -222,7 +232,8 @@ def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactiva
 
 
 def laplace7_solver(dims, m, X0, tol, maxit, levels=None, nu_pre=2, nu_post=2, coarse_sweeps=20,
-                    omega=2.0 / 3.0, callback=None, Y=None, bdiag=None, explicit_gram=False, bmass=None):
+                    omega=2.0 / 3.0, callback=None, Y=None, bdiag=None, explicit_gram=False, bmass=None,
+                    lock_gap=0.0):
     """LOBPCG on the 7-point Laplacian with optional V-cycle preconditioning,
     constraints Y and B = diag(bdiag) (a lumped mass) or B = the 7-point
     mass-type operator with coefficients bmass = (b0, b1)."""
@@ -239,7 +250,7 @@ def laplace7_solver(dims, m, X0, tol, maxit, levels=None, nu_pre=2, nu_post=2, c
         b0, b1 = bmass
         Bop = lambda V: grid.mass7(dims, b0, b1, V)
     return lobpcg(A, X0, tol, maxit, grid.gershgorin_laplace7(), apply_T=T, callback=callback, Y=Y, apply_B=Bop,
-                  explicit_gram=explicit_gram)
+                  explicit_gram=explicit_gram, lock_gap=lock_gap)
 
 
 def varcoef_solver(dims, kx, ky, kz, m, X0, tol, maxit, levels=None, callback=None):

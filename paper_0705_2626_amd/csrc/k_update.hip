@@ -390,6 +390,18 @@ static const int KQ = MAXW / 4;    // most k-steps of one input
 
 __host__ __device__ inline size_t mvf_stage_offset(int nsteps, int NT, int K, size_t esz);
 
+// k-steps of one input in the fragment kernel: ceil(k/4), rounded up to whole
+// 16-byte vectors per lane when the rows load as vectors (no column list,
+// 16-byte aligned rows), so that each lane's quarter of a row is a run of
+// vectors; the extra steps multiply zeros
+__host__ __device__ inline int mvf_k4(int k, int ld, bool mapped, int esz)
+{
+    const int VE = 16 / esz;
+    int k4 = (k + 3) / 4;
+    if (!mapped && ld % VE == 0) k4 = (k4 + VE - 1) / VE * VE;
+    return k4;
+}
+
 template <typename T, int NT>
 struct MVFShared {
     T *Cf;                 // [sum k4][NT][64]
@@ -423,20 +435,30 @@ __host__ __device__ inline size_t mvf_stage_bytes(int NT, size_t esz) { return (
 // av[i] = column (l/16)*k4 + i of this lane's row (zero past k or the grid);
 // rowlen: columns of the row from base on, aligned: base is 16-byte aligned
 // for every row
-template <typename T>
+// WHOLE: rowlen is a multiple of the vector length whenever the rows are
+// aligned (whole stored rows), so a vector that starts before column k ends
+// inside the row
+template <typename T, bool WHOLE = false>
 __device__ __forceinline__ void frag_load(T (&av)[KQ], const T *__restrict__ base, int rowlen, bool aligned, int k,
                                           int k4, const int *__restrict__ cmap, bool mapped, bool pok, int kq)
 {
     const int VE = 16 / sizeof(T);
     const int j0 = kq * k4;
-    const bool vec_ok = !mapped && aligned && (k4 % VE) == 0 && j0 + k4 <= rowlen;
-    if (vec_ok) {
+    if (!mapped && aligned && (k4 % VE) == 0) {
 #pragma unroll
         for (int i = 0; i < KQ; i += VE) {
             if (i >= k4) break;
-            vec<T, VE> v = pok ? vload<T, VE>(base + j0 + i) : vzero<T, VE>();
+            const int col = j0 + i;
+            vec<T, VE> v;
+            if (WHOLE || col + VE <= rowlen) {
+                v = (pok && col < k) ? vload<T, VE>(base + col) : vzero<T, VE>();
+            } else {
+                // a vector would run past the stored row: element by element
 #pragma unroll
-            for (int q = 0; q < VE; q++) av[i + q] = (j0 + i + q < k) ? v.v[q] : T(0);
+                for (int q = 0; q < VE; q++) v.v[q] = (pok && col + q < k) ? base[col + q] : T(0);
+            }
+#pragma unroll
+            for (int q = 0; q < VE; q++) av[i + q] = (col + q < k) ? v.v[q] : T(0);
         }
     } else {
 #pragma unroll
@@ -461,7 +483,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     int k4[3], soff[3], roffs[3];
     int nsteps = 0, roff = 0;
     for (int b = 0; b < 3; b++) {
-        k4[b] = b < a.nin ? (a.k[b] + 3) / 4 : 0;
+        k4[b] = b < a.nin ? mvf_k4(a.k[b], a.ld[b], a.cols[b] != nullptr, sizeof(T)) : 0;
         soff[b] = nsteps;
         roffs[b] = roff;
         nsteps += k4[b];
@@ -515,7 +537,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
         }
     };
     auto load_in = [&](T(&av)[KQ], int s, int b, i64 prow, bool pok) {
-        frag_load<T>(av, a.in[s][b] + prow * a.ld[b], a.ld[b], (a.ld[b] % (16 / (int)sizeof(T))) == 0, a.k[b],
+        frag_load<T, true>(av, a.in[s][b] + prow * a.ld[b], a.ld[b], (a.ld[b] % (16 / (int)sizeof(T))) == 0, a.k[b],
                      k4[b], sh.cmap + roffs[b], a.cols[b] != nullptr, pok, kq);
     };
     const i64 ngroups = (a.N + 15) / 16, gstride = (i64)gridDim.x * 4;
@@ -942,7 +964,7 @@ static hipError_t run_mv(const MVArgs &h, hipStream_t st)
         hipLaunchKernelGGL((mvn_kernel<T>), dim3(nb), dim3(256), shm, st, a);
     } else if (h.variant == 0) {
         int nsteps = 0;
-        for (int b = 0; b < h.nin; b++) nsteps += (h.k[b] + 3) / 4;
+        for (int b = 0; b < h.nin; b++) nsteps += mvf_k4(h.k[b], h.ld[b], h.cols[b] != nullptr, sizeof(T));
         const size_t shm = mvf_stage_offset(nsteps, NT, a.K, sizeof(T)) + mvf_stage_bytes(NT, sizeof(T));
         hipLaunchKernelGGL((mvf_kernel<T, NT>), dim3(nb), dim3(256), shm, st, a);
     } else {

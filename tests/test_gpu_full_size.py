@@ -90,6 +90,33 @@ def test_n256_m32_mixed_and_fp64():
     release()
 
 
+def test_block_edge_inside_a_cluster_n128_m64():
+    """The block-size study's m = 64 on 128^3 (5-level V-cycle, tol 1e-8):
+    the block holds the triple lambda_61..63 and one member of the triple
+    lambda_64..66, 2.2e-4 (relative) above it.  With the paper's soft
+    locking the last column of the lower triple stalls near 1e-6 for 1000
+    iterations; with cluster locking (LOBPCG_OPT_LOCK_GAP 3e-4) and the
+    computed block diagonal of gramB it converges in a few hundred.
+    Eigenvalues within the a-posteriori bound of the closed form."""
+    n, m, tol = 128, 64, 1e-8
+    N = n ** 3
+    ctx = L.lobpcg_setup(L.Op(n, n, n), L.Precond(5), m, L.FP64)
+    L.lobpcg_set_option(ctx, L.OPT_LOCK_GAP, 3e-4)
+    L.lobpcg_set_option(ctx, L.OPT_FP64_EXPLICIT_GRAM, 1)
+    r = L.lobpcg_solve(ctx, dev(synth.x0_uniform(N, m, seed=2)), tol, 1000, hist=False)
+    exact, _ = closed_form.smallest(n, n, n, m + 3)
+    assert r.status == L.OK, r.iters
+    assert r.iters < 500
+    assert r.resid.max() <= tol
+    for j in range(m):
+        others = np.abs(exact - exact[j])
+        gap = others[others > 1e-12 * exact[j]].min()
+        assert abs(r.lam[j] - exact[j]) <= (12.0 * r.resid[j]) ** 2 / gap
+    check_orthonormal(r.X, 1e-10)
+    del ctx, r
+    release()
+
+
 @pytest.mark.parametrize("tol,rtol", [(1e-8, 1e-8), (1.5e-9, 1e-10)])
 def test_n128_m16_fp64_multigrid(tol, rtol):
     """FP64, n=128 (N=2,097,152), m=16, V(2,2) with 5 levels.  The block edge

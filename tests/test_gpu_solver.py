@@ -95,6 +95,51 @@ def test_fp64_unpreconditioned_n16_matches_oracle():
         assert lo - 2 <= r.iters <= hi + 2, (r.iters, ref.iters, counts, kd)
 
 
+def test_cluster_locking_matches_oracle():
+    """Soft locking by clusters (LOBPCG_OPT_LOCK_GAP) against the oracle's
+    lock_gap on 16^3 without preconditioner: the same active sets (the triple
+    lambda_2..4 leaves J in one iteration), histories per group at 1e-6 up
+    to the first lock (a locked column's residual is no longer reduced by
+    the iteration and drifts with rounding: the oracle run from X0 perturbed
+    by 1e-15 departs from its own history by 1e-6 some 30 iterations after
+    the first lock), eigenvalues at 1e-10."""
+    dims, m, tol, gap = (16, 16, 16), 4, 1e-8, 1e-3
+    N = 4096
+    X0 = synth.x0_uniform(N, m, seed=2)
+    ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(None), m, L.FP64)
+    L.lobpcg_set_option(ctx, L.OPT_LOCK_GAP, gap)
+    r = L.lobpcg_solve(ctx, dev(X0), tol, 500)
+    ref = olob.laplace7_solver(dims, m, X0, tol, 500, lock_gap=gap)
+    exact, _ = closed_form.smallest(*dims, m)
+    assert r.status == L.OK and ref.status == olob.OK
+    np.testing.assert_allclose(r.lam, exact, rtol=1e-10)
+    np.testing.assert_allclose(r.lam, ref.lam, rtol=1e-10)
+    assert r.resid.max() <= tol
+
+    def sets(hist):
+        J, out = np.arange(m), []
+        for rho in hist:
+            above = rho[J] > tol
+            for i, j in enumerate(J):
+                if not above[i] and np.any(rho[J] > tol):
+                    # the replay has no Ritz values: a converged column of the
+                    # triple stays while another column of the triple is above
+                    above[i] = j in (1, 2, 3) and np.any(rho[[a for a in J if a in (1, 2, 3)]] > tol)
+            J = J[above]
+            out.append(tuple(J.tolist()))
+        return out
+    Jg, Jo = sets(r.hist), sets(ref.hist)
+    k = min(len(Jg), len(Jo))
+    first_lock = next(i for i in range(k) if len(Jg[i]) < m or len(Jo[i]) < m)
+    groups = [[0], [1, 2, 3]]
+    np.testing.assert_allclose(group_histories(r.hist[:first_lock + 1], groups),
+                               group_histories(ref.hist[:first_lock + 1], groups), rtol=1e-6, atol=1e-14)
+    # the triple leaves J together in both runs
+    for Js in (Jg, Jo):
+        assert len({next(i for i, J in enumerate(Js) if j not in J) for j in (1, 2, 3)}) == 1
+    assert abs(r.iters - ref.iters) <= 2, (r.iters, ref.iters)
+
+
 @pytest.mark.parametrize("dims,m,levels", [((24, 20, 16), 6, 3), ((32, 32, 32), 8, 3), ((33, 31, 30), 10, 4)])
 def test_fp64_multigrid_matches_oracle(dims, m, levels):
     tol = 1e-9

@@ -600,3 +600,28 @@ def test_mass7_B_matches_dense_generalized_eigenproblem():
                       grid.gershgorin_varcoef7(dims, kx, ky, kz), apply_B=Bop)
     assert r.status == lobpcg.OK
     np.testing.assert_allclose(r.lam, mu[:m], rtol=1e-10)
+
+
+def test_cluster_locking_keeps_groups_together():
+    """Soft locking by clusters (lock_gap): on 16^3 without preconditioner
+    the triple lambda_2..4 leaves the active set in one iteration (with the
+    paper's rule its columns leave one by one), the eigenvalues still match
+    the closed form, and at lock_gap = 0 the run is the paper's."""
+    dims, m, tol = (16, 16, 16), 4, 1e-8
+    N = 4096
+    X0 = synth.x0_uniform(N, m, seed=2)
+    exact, _ = closed_form.smallest(*dims, m)
+    sets = {}
+    for gap in (0.0, 1e-3):
+        Js = []
+        r = lobpcg.laplace7_solver(dims, m, X0, tol, 500, lock_gap=gap,
+                                   callback=lambda k, lam, rho, J: Js.append(tuple(J.tolist())))
+        assert r.status == lobpcg.OK
+        np.testing.assert_allclose(r.lam, exact, rtol=1e-10)
+        sets[gap] = Js
+    def leave(Js, j):
+        return next(k for k, J in enumerate(Js) if j not in J)
+    assert len({leave(sets[1e-3], j) for j in (1, 2, 3)}) == 1
+    assert len({leave(sets[0.0], j) for j in (1, 2, 3)}) > 1
+    r0 = lobpcg.laplace7_solver(dims, m, X0, tol, 500)
+    assert r0.iters == len(sets[0.0])
