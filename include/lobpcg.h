@@ -140,8 +140,11 @@ int lobpcg_solve(lobpcg_ctx *ctx, const lobpcg_op *A, const lobpcg_op *B, const 
  * As printed, step 7 does not project the residual: it goes to zero only when
  * span(Y) is invariant under A, as for previously computed eigenvectors (the
  * intended use: repeated calls with the converged X appended to Y give the
- * next eigenpairs).  FP64 contexts only (MIXED: ERR_UNSUPPORTED); a
- * rank-deficient Y (Cholesky of Y^T Y fails) gives ERR_ARG.  Other arguments
+ * next eigenpairs).  In a MIXED context the FP32 iterations project their
+ * residual blocks in FP64 (up-cast, project, down-cast) and the FP64 finish
+ * applies step 2 again to the iterate it starts from.  Not with B (then
+ * ERR_UNSUPPORTED); a rank-deficient Y (Cholesky of Y^T Y fails) gives
+ * ERR_ARG.  Other arguments
  * and outputs as lobpcg_solve. */
 int lobpcg_solve_constrained(lobpcg_ctx *ctx, const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T,
                              const double *d_Y, int ny, const double *d_X0, int m, double tol, int maxit,

@@ -5,14 +5,15 @@
 // same kernel, with a different epilogue, gives the multigrid smoother and
 // residual (weighted Jacobi on the level operator s*L7, s = 4^-l).
 //
-// Mapping: one thread owns V consecutive columns of one (x, y) grid column (of
-// two adjacent y-rows for FP64 blocks) and marches in z, so the z-1 / z / z+1
-// values stay in registers and every element is fetched from HBM once.  The x-1 / x+1 neighbours are the centre
+// Mapping: one thread owns V consecutive columns of R adjacent y-rows of one
+// x position and marches in z, so the z-1 / z / z+1 values stay in registers
+// and every element is fetched from HBM once; the y-neighbours between its
+// rows come from registers too.  The x-1 / x+1 neighbours are the centre
 // values of lanes -L / +L of the same wave and are exchanged by cross-lane
-// shuffles (only lanes at a wave edge load them); the y neighbours are the
-// centre values of threads of the same or a nearby workgroup, fetched through
-// L1/L2.  Workgroups are remapped so that each XCD owns a contiguous range of
-// (x, y) tiles.
+// shuffles (only lanes at a wave edge load them); the y-neighbours beyond the
+// thread's rows are the centre values of threads of the same or a nearby
+// workgroup, fetched through L1/L2.  Workgroups are remapped so that each XCD
+// owns a contiguous range of (x, y) tiles.
 #include "common.h"
 #include "kernels.h"
 
@@ -37,8 +38,29 @@ __device__ __forceinline__ vec<T, V> lap(const vec<T, V> &c, const vec<T, V> &zm
 // consecutive (point, chunk) items of one row); lanes at a wave edge load
 // them, lanes at the grid's x faces take the Dirichlet zero.  Every lane of
 // the wave must call this (the shuffles are wave-wide).
-template <typename T, int V>
-__device__ __forceinline__ void x_neighbours(const vec<T, V> &cur, const T *__restrict__ u, i64 i, i64 sx,
+// V elements of type U at p, converted to T (a 16-byte load for U = T; two
+// for an FP64 row read by FP32 arithmetic)
+template <typename T, int V, typename U>
+__device__ __forceinline__ vec<T, V> vload_as(const U *p)
+{
+    const vec<U, V> a = vload<U, V>(p);
+    vec<T, V> r;
+#pragma unroll
+    for (int q = 0; q < V; q++) r.v[q] = (T)a.v[q];
+    return r;
+}
+
+template <typename T, int V, typename U>
+__device__ __forceinline__ void vstore_nt_as(U *p, const vec<T, V> &x)
+{
+    vec<U, V> a;
+#pragma unroll
+    for (int q = 0; q < V; q++) a.v[q] = (U)x.v[q];
+    vstore_nt<U, V>(p, a);
+}
+
+template <typename T, int V, typename TU = T>
+__device__ __forceinline__ void x_neighbours(const vec<T, V> &cur, const TU *__restrict__ u, i64 i, i64 sx,
                                              int x, int nx, int L, bool row_ok, vec<T, V> &xm, vec<T, V> &xp)
 {
     const int lane = threadIdx.x & 63;
@@ -51,9 +73,9 @@ __device__ __forceinline__ void x_neighbours(const vec<T, V> &cur, const T *__re
     // a row outside the grid (only the last rows of a thread's row block)
     // has no neighbours to load: its results are not stored
     if (x == 0 || !row_ok) xm = vzero<T, V>();
-    else if (!in_m) xm = vload<T, V>(u + i - sx);
+    else if (!in_m) xm = vload_as<T, V>(u + i - sx);
     if (x + 1 == nx || !row_ok) xp = vzero<T, V>();
-    else if (!in_p) xp = vload<T, V>(u + i + sx);
+    else if (!in_p) xp = vload_as<T, V>(u + i + sx);
 }
 
 // EPI_APPLY : out = s * L7 u
@@ -63,10 +85,14 @@ __device__ __forceinline__ void x_neighbours(const vec<T, V> &cur, const T *__re
 //             x1 = c1 u, out = x1 + c1 (u - s L7 x1)
 // EPI_MASS  : out = c1 u + s (sum of the six neighbours), the 7-point
 //             mass-type operator B with b0 = c1, b1 = s
-template <typename T, int V, int EPI, int R>
+// The arithmetic is in T.  u may be stored as TU and out as TO (FP64 blocks
+// around an FP32 multigrid: the first sweep reads the FP64 right-hand side
+// and, when ucopy is given, writes its FP32 copy for the later kernels of
+// the cycle; the last sweep writes the FP64 result).
+template <typename T, int V, int EPI, int R, typename TU = T, typename TO = T>
 __global__ void __launch_bounds__(256) stencil7_kernel(int nx, int ny, int nz, int L, int zchunk,
-                                                       const T *__restrict__ u, T *__restrict__ out,
-                                                       const T *__restrict__ b, T s, T c1)
+                                                       const TU *__restrict__ u, TO *__restrict__ out,
+                                                       const T *__restrict__ b, T s, T c1, T *__restrict__ ucopy)
 {
     const unsigned nbx = gridDim.x;
     const unsigned bx = xcd_remap(blockIdx.x, nbx);
@@ -95,21 +121,22 @@ __global__ void __launch_bounds__(256) stencil7_kernel(int nx, int ny, int nz, i
     for (int r = 0; r < R; r++) {
         rok[r] = y0 + r < ny;
         const i64 br = base + r * sy;
-        prev[r] = (rok[r] && z0 > 0) ? vload<T, V>(u + br + (z0 - 1) * sz) : zero;
-        cur[r] = rok[r] ? vload<T, V>(u + br + z0 * sz) : zero;
+        prev[r] = (rok[r] && z0 > 0) ? vload_as<T, V>(u + br + (z0 - 1) * sz) : zero;
+        cur[r] = rok[r] ? vload_as<T, V>(u + br + z0 * sz) : zero;
     }
     for (int z = z0; z < z1; z++) {
         const i64 i = base + z * sz;
         vec<T, V> next[R];
 #pragma unroll
-        for (int r = 0; r < R; r++) next[r] = (rok[r] && z + 1 < nz) ? vload<T, V>(u + i + r * sy + sz) : zero;
-        const vec<T, V> ybelow = y0 > 0 ? vload<T, V>(u + i - sy) : zero;
-        const vec<T, V> yabove = (y0 + R < ny) ? vload<T, V>(u + i + R * sy) : zero;
+        for (int r = 0; r < R; r++) next[r] = (rok[r] && z + 1 < nz) ? vload_as<T, V>(u + i + r * sy + sz) : zero;
+        const vec<T, V> ybelow = y0 > 0 ? vload_as<T, V>(u + i - sy) : zero;
+        const vec<T, V> yabove = (y0 + R < ny) ? vload_as<T, V>(u + i + R * sy) : zero;
 #pragma unroll
         for (int r = 0; r < R; r++) {
             const i64 ir = i + r * sy;
             vec<T, V> xm, xp;
-            x_neighbours<T, V>(cur[r], u, ir, sx, x, nx, L, rok[r], xm, xp);
+            x_neighbours<T, V, TU>(cur[r], u, ir, sx, x, nx, L, rok[r], xm, xp);
+            if (ucopy && active && rok[r]) vstore<T, V>(ucopy + ir, cur[r]);
             const vec<T, V> ym = r == 0 ? ybelow : cur[r - 1];
             const vec<T, V> yp = r == R - 1 ? yabove : cur[r + 1];
             vec<T, V> o;
@@ -118,7 +145,7 @@ __global__ void __launch_bounds__(256) stencil7_kernel(int nx, int ny, int nz, i
                 for (int q = 0; q < V; q++)
                     o.v[q] = c1 * cur[r].v[q] +
                              s * (prev[r].v[q] + next[r].v[q] + xm.v[q] + xp.v[q] + ym.v[q] + yp.v[q]);
-                if (active && rok[r]) vstore_nt<T, V>(out + ir, o);
+                if (active && rok[r]) vstore_nt_as<T, V>(out + ir, o);
                 continue;
             }
             vec<T, V> au = lap<T, V>(cur[r], prev[r], next[r], xm, xp, ym, yp);
@@ -136,7 +163,7 @@ __global__ void __launch_bounds__(256) stencil7_kernel(int nx, int ny, int nz, i
                     o.v[q] = (EPI == EPI_JACOBI) ? cur[r].v[q] + c1 * rr : rr;
                 }
             }
-            if (active && rok[r]) vstore_nt<T, V>(out + ir, o);
+            if (active && rok[r]) vstore_nt_as<T, V>(out + ir, o);
         }
 #pragma unroll
         for (int r = 0; r < R; r++) {
@@ -198,14 +225,15 @@ __global__ void __launch_bounds__(256) varcoef7_kernel(int nx, int ny, int nz, i
 }
 
 // Launch geometry: 256 threads over the (x, y, column-chunk) plane, z split
-// into chunks only when the plane alone gives too few workgroups.
-static void geometry(int nx, int ny, int nz, int L, dim3 &grid, int &zchunk)
+// into chunks until there are about zmin workgroups (a chunk re-reads the
+// two planes at its ends; on small grids they come from the caches)
+static void geometry(int nx, int ny, int nz, int L, dim3 &grid, int &zchunk, int zmin = 2048)
 {
     const i64 plane = (i64)nx * ny * L;
     const unsigned pb = (unsigned)((plane + 255) / 256);
-    int zc = (int)((2048 + pb - 1) / pb);
-    if (zc < 1) zc = 1;
+    int zc = (int)((zmin + pb - 1) / pb);
     if (zc > nz) zc = nz;
+    if (zc < 1) zc = 1;
     zchunk = (nz + zc - 1) / zc;
     grid = dim3(pb, (nz + zchunk - 1) / zchunk, 1);
 }
@@ -219,24 +247,33 @@ static int pick_vec(int k)
     return 1;
 }
 
-// y-rows per thread: two for FP64 blocks (one y-neighbour row fewer to fetch
-// per output: measured faster), one for FP32 blocks (there the second row's
-// registers cost occupancy, 8 -> 6 waves per SIMD, and the kernel was slower)
+// y-rows per thread and workgroup target, measured on 256^3 blocks of 8-32
+// columns: rows held in registers save the y-neighbour loads of the rows
+// between them, but cost registers (waves in flight).  FP32 products: two
+// rows (4.4 -> 5.0 TB/s at 32 columns); FP32 sweeps and residuals, which
+// also stream b, are fastest with one row (5.1 TB/s); FP64: four rows
+// (products 3.8 -> 4.8 TB/s, sweeps 4.1 -> 5.2 TB/s), two for narrow
+// products.
 template <typename T, int V, int EPI>
 static hipError_t run_stencil(const Grid3 &g, int k, const void *u, void *out, const void *b, double s, double c1,
                               hipStream_t st)
 {
     const int L = k / V;
+    const bool product = EPI == EPI_APPLY || EPI == EPI_MASS;
     dim3 grid;
     int zchunk;
-    if (sizeof(T) == 8 && g.ny >= 2) {
-        geometry(g.nx, (g.ny + 1) / 2, g.nz, L, grid, zchunk);
-        hipLaunchKernelGGL((stencil7_kernel<T, V, EPI, 2>), grid, dim3(256), 0, st, g.nx, g.ny, g.nz, L, zchunk,
-                           (const T *)u, (T *)out, (const T *)b, (T)s, (T)c1);
+    auto launch = [&](auto Rc, int zmin) {
+        constexpr int R = decltype(Rc)::value;
+        geometry(g.nx, (g.ny + R - 1) / R, g.nz, L, grid, zchunk, zmin);
+        hipLaunchKernelGGL((stencil7_kernel<T, V, EPI, R>), grid, dim3(256), 0, st, g.nx, g.ny, g.nz, L, zchunk,
+                           (const T *)u, (T *)out, (const T *)b, (T)s, (T)c1, (T *)nullptr);
+    };
+    if (sizeof(T) == 8) {
+        if (product && k < 16) launch(std::integral_constant<int, 2>(), 8192);
+        else launch(std::integral_constant<int, 4>(), product ? 4096 : 8192);
     } else {
-        geometry(g.nx, g.ny, g.nz, L, grid, zchunk);
-        hipLaunchKernelGGL((stencil7_kernel<T, V, EPI, 1>), grid, dim3(256), 0, st, g.nx, g.ny, g.nz, L, zchunk,
-                           (const T *)u, (T *)out, (const T *)b, (T)s, (T)c1);
+        if (product) launch(std::integral_constant<int, 2>(), 8192);
+        else launch(std::integral_constant<int, 1>(), 2048);
     }
     return hipGetLastError();
 }
@@ -299,6 +336,43 @@ hipError_t launch_resid7(int dtype, const Grid3 &g, int k, const void *x, const 
 {
     if (dtype == DT_F32) return dispatch_epi<float>(EPI_RESID, g, k, x, out, b, s, 0.0, st);
     return dispatch_epi<double>(EPI_RESID, g, k, x, out, b, s, 0.0, st);
+}
+
+// FP32 sweeps at the edges of an FP32 cycle on FP64 blocks (one row per
+// thread, as the FP32 sweeps above)
+template <int V, int EPI, typename TU, typename TO>
+static hipError_t run_sweep_cast(const Grid3 &g, int k, const void *u, void *out, const void *b, float *ucopy,
+                                 double s, double c1, hipStream_t st)
+{
+    const int L = k / V;
+    dim3 grid;
+    int zchunk;
+    geometry(g.nx, g.ny, g.nz, L, grid, zchunk);
+    hipLaunchKernelGGL((stencil7_kernel<float, V, EPI, 1, TU, TO>), grid, dim3(256), 0, st, g.nx, g.ny, g.nz, L,
+                       zchunk, (const TU *)u, (TO *)out, (const float *)b, (float)s, (float)c1, ucopy);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi2_zero_from64(const Grid3 &g, int k, const double *b64, float *x, float *b32, double s,
+                                      double omega, hipStream_t st)
+{
+    const double c1 = omega / (6.0 * s);
+    switch (pick_vec<float>(k)) {
+    case 4: return run_sweep_cast<4, EPI_JACOBI2, double, float>(g, k, b64, x, nullptr, b32, s, c1, st);
+    case 2: return run_sweep_cast<2, EPI_JACOBI2, double, float>(g, k, b64, x, nullptr, b32, s, c1, st);
+    default: return run_sweep_cast<1, EPI_JACOBI2, double, float>(g, k, b64, x, nullptr, b32, s, c1, st);
+    }
+}
+
+hipError_t launch_jacobi_to64(const Grid3 &g, int k, const float *x, const float *b, double *out, double s,
+                              double omega, hipStream_t st)
+{
+    const double c1 = omega / (6.0 * s);
+    switch (pick_vec<float>(k)) {
+    case 4: return run_sweep_cast<4, EPI_JACOBI, float, double>(g, k, x, out, b, nullptr, s, c1, st);
+    case 2: return run_sweep_cast<2, EPI_JACOBI, float, double>(g, k, x, out, b, nullptr, s, c1, st);
+    default: return run_sweep_cast<1, EPI_JACOBI, float, double>(g, k, x, out, b, nullptr, s, c1, st);
+    }
 }
 
 template <typename T, int V>

@@ -708,7 +708,12 @@ int residual(lobpcg_ctx *c, int dt, const void *X, const void *AX, const std::ve
 
 // V-cycle on N x k blocks of the multigrid precision.  b: right-hand side at
 // level l; xa, xb: two buffers of that level; returns the buffer holding T b.
-void *vcycle(lobpcg_ctx *c, int l, const void *b, void *xa, void *xb, int k, hipError_t &err)
+// FP64 blocks around an FP32 cycle (the FP64 phase of the mixed solver):
+// with b64 given, the fine level's first sweep reads the FP64 right-hand
+// side and writes its FP32 copy into b (then used by the rest of the cycle),
+// and with out64 given the last sweep writes T b there in FP64 (returned).
+void *vcycle(lobpcg_ctx *c, int l, const void *b, void *xa, void *xb, int k, hipError_t &err,
+             const double *b64 = nullptr, double *out64 = nullptr)
 {
     const int dt = c->L.mg_dtype;
     const Grid3 &g = c->L.levels[l];
@@ -738,13 +743,24 @@ void *vcycle(lobpcg_ctx *c, int l, const void *b, void *xa, void *xb, int k, hip
     }
     void *cur = xa, *oth = xb;
     int pre = 1;
-    if (c->T.nu_pre >= 2) {
-        chk(launch_jacobi2_zero(dt, g, k, b, cur, s, om, c->st));
+    if (b64 && c->T.nu_pre >= 2) {
+        // reads the FP64 right-hand side once, writes x and the FP32 copy
+        chk(launch_jacobi2_zero_from64(g, k, b64, (float *)cur, (float *)b, s, om, c->st));
         pre = 2;
+        passes(4.0);
     } else {
-        chk(launch_scale(dt, g.n() * k, b, cur, c->T.nu_pre > 0 ? om / (6.0 * s) : 0.0, c->st));
+        if (b64) {
+            chk(launch_cast(DT_F64, DT_F32, g.n() * k, b64, (void *)b, c->st));
+            passes(3.0);
+        }
+        if (c->T.nu_pre >= 2) {
+            chk(launch_jacobi2_zero(dt, g, k, b, cur, s, om, c->st));
+            pre = 2;
+        } else {
+            chk(launch_scale(dt, g.n() * k, b, cur, c->T.nu_pre > 0 ? om / (6.0 * s) : 0.0, c->st));
+        }
+        passes(2.0);
     }
-    passes(2.0);
     for (int i = pre; i < c->T.nu_pre; i++) {
         chk(launch_jacobi(dt, g, k, cur, b, oth, s, om, c->st));
         passes(3.0);
@@ -760,9 +776,20 @@ void *vcycle(lobpcg_ctx *c, int l, const void *b, void *xa, void *xb, int k, hip
     chk(launch_prolong_add(dt, g, gc, k, e, cur, c->st));
     passes(2.0 + ratio);
     for (int i = 0; i < c->T.nu_post; i++) {
+        if (out64 && i + 1 == c->T.nu_post) {
+            // the last sweep writes the FP64 result
+            chk(launch_jacobi_to64(g, k, (const float *)cur, (const float *)b, out64, s, om, c->st));
+            passes(4.0);
+            return out64;
+        }
         chk(launch_jacobi(dt, g, k, cur, b, oth, s, om, c->st));
         passes(3.0);
         std::swap(cur, oth);
+    }
+    if (out64) {
+        chk(launch_cast(DT_F32, DT_F64, g.n() * k, cur, out64, c->st));
+        passes(3.0);
+        return out64;
     }
     return cur;
 }
@@ -778,14 +805,20 @@ int apply_T(lobpcg_ctx *c, int dt, const void *in, void *fa, void *fb, int k, vo
     if (dt == mdt) {
         *result = vcycle(c, 0, in, fa, fb, k, err);
     } else {
-        // mixed solver, FP64 phase: b32 buffers are free; T in FP32
+        // mixed solver, FP64 phase: b32 buffers are free; T in FP32 on FP64
+        // blocks, the precision changes taken in the cycle's first and last
+        // sweeps (a one-level cycle only: casts around it)
         const long long n = c->N * k;
         void *bin = c->b32.W, *xa = c->b32.AW, *xb = c->b32.T0;
-        if (launch_cast(dt, mdt, n, in, bin, c->st) != hipSuccess) err = hipErrorUnknown;
-        void *r = vcycle(c, 0, bin, xa, xb, k, err);
-        if (launch_cast(mdt, dt, n, r, fa, c->st) != hipSuccess) err = hipErrorUnknown;
-        add_bytes(c, LOBPCG_STEP_PRECOND, 2.0 * n * (esize(dt) + esize(mdt)));
-        *result = fa;
+        if (c->L.levels.size() > 1) {
+            *result = vcycle(c, 0, bin, xa, xb, k, err, (const double *)in, (double *)fa);
+        } else {
+            if (launch_cast(dt, mdt, n, in, bin, c->st) != hipSuccess) err = hipErrorUnknown;
+            void *r = vcycle(c, 0, bin, xa, xb, k, err);
+            if (launch_cast(mdt, dt, n, r, fa, c->st) != hipSuccess) err = hipErrorUnknown;
+            add_bytes(c, LOBPCG_STEP_PRECOND, 2.0 * n * (esize(dt) + esize(mdt)));
+            *result = fa;
+        }
     }
     prof_end(c);
     return err == hipSuccess ? LOBPCG_OK : LOBPCG_ERR_HIP;
@@ -859,7 +892,32 @@ std::vector<int> positions(const std::vector<int> &sub, const std::vector<int> &
 // block V (FP64).  Y^T V comes from the Gram kernel (Lm = Y, Rm = V), the
 // small solve runs on the host with the Cholesky factor of Y^T Y, and the
 // update is one multivector product [V Y] [I; -C].
-int constrain(lobpcg_ctx *c, const void *V, int k, void *dst, int step)
+int constrain64(lobpcg_ctx *c, const void *V, int k, void *dst, int step);
+
+// Steps 2 and 10 on a block of precision dt.  An FP32 block (the FP32 phase
+// of the mixed solver) is projected in FP64 against the FP64 constraints: it
+// is up-cast into FP64 scratch blocks (unused during that phase), projected
+// there and cast back into dst.
+int constrain(lobpcg_ctx *c, int dt, const void *V, int k, void *dst, int step)
+{
+    if (dt == DT_F64) return constrain64(c, V, k, dst, step);
+    const size_t n = (size_t)c->N * k;
+    void *v64 = c->b64.W, *p64 = c->b64.T0;
+    prof_begin(c, step);
+    hipError_t e = launch_cast(DT_F32, DT_F64, (long long)n, V, v64, c->st);
+    prof_end(c);
+    add_bytes(c, step, 12.0 * n);
+    if (e != hipSuccess) return LOBPCG_ERR_HIP;
+    int s = constrain64(c, v64, k, p64, step);
+    if (s) return s;
+    prof_begin(c, step);
+    e = launch_cast(DT_F64, DT_F32, (long long)n, p64, dst, c->st);
+    prof_end(c);
+    add_bytes(c, step, 12.0 * n);
+    return e == hipSuccess ? LOBPCG_OK : LOBPCG_ERR_HIP;
+}
+
+int constrain64(lobpcg_ctx *c, const void *V, int k, void *dst, int step)
 {
     const int ny = c->ny;
     // Y^T V (ny x k) in launches of at most GX_MAX_L rows
@@ -1255,7 +1313,7 @@ int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &
         // step 10: W_J = W_J - Y (Y^T Y)^-1 (Y^T W_J)
         if (c->ny) {
             void *dst = (Wt == B.T0) ? B.AW : B.T0;
-            s = constrain(c, Wt, nJ, dst, LOBPCG_STEP_PRECOND);
+            s = constrain(c, dt, Wt, nJ, dst, LOBPCG_STEP_PRECOND);
             if (s) return s;
             Wt = dst;
         }
@@ -1723,7 +1781,6 @@ static int solve_impl(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, con
         c->Bop = *B;
     }
     if (ny < 0 || ny > LOBPCG_MAX_M || (ny > 0 && !d_Y) || 3LL * m + ny > c->N) return LOBPCG_ERR_ARG;
-    if (ny > 0 && c->precision != LOBPCG_FP64) return LOBPCG_ERR_UNSUPPORTED;
     // B != I: the folded form only, without constraints
     if (B && (ny > 0 || !c->fold)) return LOBPCG_ERR_UNSUPPORTED;
     auto t0 = std::chrono::steady_clock::now();
@@ -1752,9 +1809,15 @@ static int solve_impl(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, con
     ps.cur = 0;
     ps.have_res = false;
     if (c->precision == LOBPCG_MIXED) {
-        // FP32 phase
+        // FP32 phase (step 2 in FP64 first)
+        const void *x0 = d_X0;
+        if (ny) {
+            s = constrain(c, DT_F64, d_X0, m, c->b64.X[0], LOBPCG_STEP_OTHER);
+            if (s) return s;
+            x0 = c->b64.X[0];
+        }
         prof_begin(c, LOBPCG_STEP_OTHER);
-        if (launch_cast(DT_F64, DT_F32, nm, d_X0, c->b32.X[0], c->st) != hipSuccess) return LOBPCG_ERR_HIP;
+        if (launch_cast(DT_F64, DT_F32, nm, x0, c->b32.X[0], c->st) != hipSuccess) return LOBPCG_ERR_HIP;
         prof_end(c);
         add_bytes(c, LOBPCG_STEP_OTHER, 12.0 * nm);
         s = init_phase(c, A, DT_F32, c->b32, ps, true, true);
@@ -1773,6 +1836,19 @@ static int solve_impl(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, con
                 return LOBPCG_ERR_HIP;
             prof_end(c);
             add_bytes(c, LOBPCG_STEP_OTHER, 12.0 * (nm + (double)c->N * np));
+            ps.cur = 0;
+            if (ny) {
+                // FP32 rounding leaves components along span(Y) in X and P:
+                // step 2 again, in FP64, on both; X is orthonormalised again
+                s = constrain(c, DT_F64, c->b64.X[0], m, c->b64.X[1], LOBPCG_STEP_OTHER);
+                if (s) return s;
+                ps.cur = 1;
+                if (np) {
+                    s = constrain(c, DT_F64, c->b64.P, np, c->b64.PJ, LOBPCG_STEP_OTHER);
+                    if (s) return s;
+                    std::swap(c->b64.P, c->b64.PJ);
+                }
+            }
             if (np) {
                 s = apply_A(c, A, DT_F64, c->b64.P, c->b64.AP, np);
                 if (s) return s;
@@ -1781,8 +1857,7 @@ static int solve_impl(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, con
                     if (s) return s;
                 }
             }
-            ps.cur = 0;
-            s = init_phase(c, A, DT_F64, c->b64, ps, false, true);
+            s = init_phase(c, A, DT_F64, c->b64, ps, ny > 0, true);
             if (s == LOBPCG_OK)
                 s = run_phase(c, A, DT_F64, c->b64, ps, tol, normA, maxit, iters, h_hist, c->fp64_explicit, false,
                               outcome);
@@ -1790,7 +1865,7 @@ static int solve_impl(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, con
     } else {
         if (ny) {
             // step 2: X0 - Y (Y^T Y)^-1 (Y^T X0)
-            s = constrain(c, d_X0, m, c->b64.X[0], LOBPCG_STEP_OTHER);
+            s = constrain(c, DT_F64, d_X0, m, c->b64.X[0], LOBPCG_STEP_OTHER);
             if (s) return s;
         } else {
             HIPCHK(hipMemcpyAsync(c->b64.X[0], d_X0, nm * 8, hipMemcpyDeviceToDevice, c->st));

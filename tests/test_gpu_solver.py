@@ -574,6 +574,31 @@ def test_constraints_match_oracle(mix):
     assert abs(r.iters - ref.iters) <= 2, (r.iters, ref.iters)
 
 
+@pytest.mark.parametrize("mix", [False, True])
+def test_constraints_in_mixed_precision(mix):
+    """Constraints in the mixed solver: Y = the exact eigenvectors of the 6
+    smallest eigenvalues (or a random basis of their span); eigenvalues 7..12
+    within 1e-6 of the FP64 oracle's and of the closed form, every explicit
+    FP64 residual <= tol, X orthogonal to Y."""
+    dims, m, levels, tol = (24, 20, 16), 6, 3, 1e-8
+    N = int(np.prod(dims))
+    lam, ijk = closed_form.smallest(*dims, 2 * m)
+    Y = sine_block(dims, ijk[:m])
+    if mix:
+        Y = Y @ np.random.default_rng(7).standard_normal((m, m))
+    X0 = synth.x0_uniform(N, m, seed=5)
+    ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(levels), m, L.MIXED)
+    r = L.lobpcg_solve(ctx, dev(X0), tol, 300, Y=dev(Y))
+    st = L.lobpcg_get_stats(ctx)
+    ref = olob.laplace7_solver(dims, m, X0, tol, 300, levels=levels, Y=Y)
+    assert r.status == L.OK and ref.status == olob.OK
+    assert st["iters_fp32"] > 0 and st["iters_fp64"] > 0
+    np.testing.assert_allclose(r.lam, ref.lam, rtol=1e-6)
+    np.testing.assert_allclose(r.lam, lam[m:], rtol=1e-6)
+    assert r.resid.max() <= tol
+    assert np.abs(Y.T @ r.X.cpu().numpy()).max() < 1e-10 * np.abs(Y).max() * np.sqrt(N)
+
+
 def test_constraints_repeated_calls_give_successive_eigenpairs():
     """Hard locking as intended: each call appends its converged vectors to Y
     and the next call finds the next block of the spectrum."""
@@ -598,9 +623,6 @@ def test_constraints_error_paths():
     N = int(np.prod(dims))
     X0 = dev(synth.x0_uniform(N, m))
     Y = synth.random_block(N, 2, seed=1)
-    ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(None), m, L.MIXED)
-    r = L.lobpcg_solve(ctx, X0, 1e-8, 10, Y=dev(Y), raise_on_error=False)
-    assert r.status == L.ERR_UNSUPPORTED
     ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(None), m, L.FP64)
     r = L.lobpcg_solve(ctx, X0, 1e-8, 10, Y=dev(np.hstack([Y, Y[:, :1]])), raise_on_error=False)
     assert r.status == L.ERR_ARG          # rank-deficient constraints
