@@ -273,6 +273,29 @@ int lobpcg_residual(lobpcg_ctx *ctx, int dtype, const void *d_X, const void *d_A
                     const double *h_lambda, const int *h_J, int nJ, double norm_A, void *d_W,
                     double *h_rho);
 
+/* lobpcg_residual without a context, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): it calls no allocating routine, takes every input and output
+ * in device memory, synchronises nothing and only enqueues kernels on
+ * `stream` (a hipStream_t, NULL = the default stream).  Its kernels' scratch
+ * (per-workgroup partial sums and their reduction, 2 MiB + 2 KiB) is a
+ * fixed array in the library's device memory, one per GPU, kept until the
+ * process ends; calls that overlap on one GPU race on it (serialise them,
+ * e.g. on one stream).  Nothing in the scratch needs clearing between calls.
+ *   dtype      LOBPCG_F64 or LOBPCG_F32 for X, AX and W
+ *   N, m       N x m point-major blocks d_X, d_AX (16-byte aligned), 1 <= m <= 128
+ *   d_lambda   [m] FP64 Ritz values
+ *   d_jpos     [m] packed column of j in W, or -1 (column not written)
+ *   nJ, d_W    W (N x nJ) receives AX_j - lambda_j X_j in column d_jpos[j]
+ *              (d_W may be NULL when nJ = 0)
+ *   d_rho      [m] FP64 out: ||AX_j - lambda_j X_j|| / (norm_A ||X_j||)
+ * Errors (checked before anything is enqueued): ARG for a bad type, size,
+ * pointer or m > 128; HIP when a launch fails.  Results are valid once the
+ * stream has reached the call. */
+int lobpcg_residual_noalloc(int dtype, long long N, const void *d_X, const void *d_AX, int m,
+                            const double *d_lambda, const int *d_jpos, int nJ, double norm_A, void *d_W,
+                            double *d_rho, void *stream);
+
 /* Host FP64 dense kernels (no GPU needed). */
 /* Scale-invariant Cholesky G = R^T R (Section 2.2: the factorisation must be
  * invariant under column scaling): R = Rh D, D = diag(G)^(1/2), Rh^T Rh =

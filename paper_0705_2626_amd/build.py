@@ -14,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblobpcg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["lobpcg.cpp", "dense.cpp", "k_stencil.hip", "k_mg.hip", "k_block.hip", "k_gram.hip", "k_update.hip"]
+SOURCES = ["lobpcg.cpp", "dense.cpp", "k_stencil.hip", "k_mg.hip", "k_block.hip", "k_gram.hip", "k_update.hip",
+           "k_noalloc.hip"]
 # packed-FP32 instructions stay disabled: hipcc -O3 otherwise emits
 # v_pk_{add,mul,fma}_f32 on its own.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",

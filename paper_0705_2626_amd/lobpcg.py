@@ -84,6 +84,7 @@ def lib():
             "lobpcg_gram": (i, [p, i, i, p, p, p, i, p, p]),
             "lobpcg_combine": (i, [p, i, i, p, p, p, p, p, i, p, p]),
             "lobpcg_residual": (i, [p, i, p, p, i, p, p, i, d, p, p]),
+            "lobpcg_residual_noalloc": (i, [i, ctypes.c_longlong, p, p, i, p, p, i, d, p, p, p]),
             "lobpcg_dense_chol": (i, [i, p, p]),
             "lobpcg_dense_rr": (i, [i, i, p, p, p, p]),
         }
