@@ -54,8 +54,8 @@ HBM_PEAK_GBPS = 8000.0
 # two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy;
 # valid only while the kernel source is the one the counters were taken with.
 TRAFFIC = {
-    "update": {"bytes_per_launch": 17.150e9, "source": "paper_0705_2626_amd/csrc/k_update.hip",
-               "sha1": "3acfe28281926840000789ead4f41dcc61ad7a58", "profile": "profiles/lobpcg_mixed_n256_m32_hbm_traffic.md"},
+    "update": {"bytes_per_launch": 17.112e9, "source": "paper_0705_2626_amd/csrc/k_update.hip",
+               "sha1": "cb6bce0c76390938ce6e1d3a81f584e8f885f576", "profile": "profiles/lobpcg_mixed_n256_m32_hbm_traffic.md"},
 }
 
 
