@@ -27,15 +27,22 @@ static unsigned stride_blocks(i64 total, unsigned cap = 8192)
 
 // ---------------------------------------------------------------- column gather
 
-template <typename T>
+static const int MV_MAX_GATHER = 256;   // widest gathered block (m <= 128 columns, twice for safety)
+
+// one thread per output element; the column map in LDS, and 32-bit index
+// arithmetic while the block has fewer than 2^31 elements (IDX = unsigned)
+template <typename T, typename IDX>
 __global__ void __launch_bounds__(256) gather_cols_kernel(i64 N, const T *__restrict__ in, int ld,
                                                           const int *__restrict__ map, int nout, T *__restrict__ out)
 {
-    const i64 total = N * nout;
-    for (i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (i64)gridDim.x * blockDim.x) {
-        const i64 p = t / nout;
-        const int j = (int)(t - p * nout);
-        out[t] = in[p * ld + map[j]];
+    __shared__ int smap[MV_MAX_GATHER];
+    for (int j = threadIdx.x; j < nout; j += blockDim.x) smap[j] = map[j];
+    __syncthreads();
+    const IDX total = (IDX)(N * nout), step = (IDX)gridDim.x * blockDim.x;
+    for (IDX t = (IDX)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += step) {
+        const IDX p = t / (IDX)nout;
+        const int j = (int)(t - p * (IDX)nout);
+        out[t] = in[(i64)p * ld + smap[j]];
     }
 }
 
@@ -44,12 +51,24 @@ hipError_t launch_gather_cols(int dtype, long long N, const void *in, int ld, co
 {
     const i64 total = (i64)N * nout;
     if (total == 0) return hipSuccess;
-    if (dtype == DT_F32)
-        hipLaunchKernelGGL(gather_cols_kernel<float>, dim3(stride_blocks(total, 65536)), dim3(256), 0, st, (i64)N,
-                           (const float *)in, ld, map, nout, (float *)out);
-    else
-        hipLaunchKernelGGL(gather_cols_kernel<double>, dim3(stride_blocks(total, 65536)), dim3(256), 0, st, (i64)N,
-                           (const double *)in, ld, map, nout, (double *)out);
+    if (nout > MV_MAX_GATHER) return hipErrorInvalidValue;
+    const dim3 g(stride_blocks(total, 65536));
+    const bool small = total < ((i64)1 << 31);
+    if (dtype == DT_F32) {
+        if (small)
+            hipLaunchKernelGGL((gather_cols_kernel<float, unsigned>), g, dim3(256), 0, st, (i64)N, (const float *)in,
+                               ld, map, nout, (float *)out);
+        else
+            hipLaunchKernelGGL((gather_cols_kernel<float, i64>), g, dim3(256), 0, st, (i64)N, (const float *)in, ld,
+                               map, nout, (float *)out);
+    } else {
+        if (small)
+            hipLaunchKernelGGL((gather_cols_kernel<double, unsigned>), g, dim3(256), 0, st, (i64)N,
+                               (const double *)in, ld, map, nout, (double *)out);
+        else
+            hipLaunchKernelGGL((gather_cols_kernel<double, i64>), g, dim3(256), 0, st, (i64)N, (const double *)in,
+                               ld, map, nout, (double *)out);
+    }
     return hipGetLastError();
 }
 
