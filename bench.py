@@ -266,8 +266,8 @@ def main():
         out["mixed"]["steps"] = steps_mixed
         # the dominant step class of the headline (mixed) solve
         kern = {"precond": "V-cycle kernels (stencil7 Jacobi/residual, restrict, prolong_add)",
-                "gram": "gram_kernel / gram_rows_kernel (steps 17-23)",
-                "update": "mvf_kernel / mvn_kernel, fused Ritz update + residual (steps 25-33, 7)",
+                "gram": "gramy_kernel / gram_rows_kernel (steps 17-23)",
+                "update": "mvl_kernel (FP32) / mvf_kernel (FP64), fused Ritz update + residual (steps 25-33, 7)",
                 "ortho": "Cholesky-QR Grams and multivector products (steps 11, 14-15)",
                 "apply_A": "stencil7 A*W (step 12)", "residual": "residual_kernel (step 7)"}
         name = max(kern, key=lambda k: steps_mixed[k]["ms"])

@@ -176,9 +176,10 @@ enum {
     LOBPCG_OPT_PROFILE = 3,         /* 1: time each step class with HIP events          */
     LOBPCG_OPT_REACTIVATE = 4,      /* 1 (default): see lobpcg_solve's stopping rule    */
     LOBPCG_OPT_KERNELS = 5,         /* kernel variants, 0 = default; results agree to  */
-                                    /* rounding.  Bits 0-1, multivector products:      */
-                                    /* 1 = per-element fragment loads, 2 = tiles       */
-                                    /* staged through LDS (3 is invalid); bit 2: the   */
+                                    /* rounding.  Bit 0: the FP32 update of steps      */
+                                    /* 25-33 on the fragment kernel (register loads)   */
+                                    /* instead of the LDS-pipelined one; bit 1 is      */
+                                    /* reserved and must be 0 (ERR_ARG); bit 2: the    */
                                     /* multi-column-tile Gram kernel also for narrow   */
                                     /* single-block Grams; bit 3: up to four Gram      */
                                     /* tiles per wave (default two); bit 4: the same   */
@@ -264,6 +265,22 @@ int lobpcg_gram(lobpcg_ctx *ctx, int dtype, int n, const void *const *d_S, const
 int lobpcg_combine(lobpcg_ctx *ctx, int dtype, int n, const void *const *d_in, const int *ld,
                    const int *const *cols, const int *k, const double *h_C, int kout,
                    const void *d_add, void *d_out);
+
+/* Steps 25-33 fused with step 7 of the next iteration (the solver's update):
+ * with C = [C_X; C_W; C_P] ((m + nW + nP) x m row-major FP64 on the host),
+ *   P'  = W C_W + P C_P,    AP' = AW C_W + AP C_P       (step 27-30 form)
+ *   X'  = X C_X + P',       AX' = AX C_X + AP'          (steps 31-33)
+ *   W'  = AX'_j - theta_j X'_j for j in J               (step 7)
+ * for d_X, d_AX (N x m), d_W, d_AW (N x nW), d_P, d_AP (N x nP; nP = 0 drops
+ * the P terms and they may be NULL).  d_Xn, d_AXn (N x m) receive X', AX';
+ * d_Pn, d_APn, d_Wn (N x nJ) receive the columns h_J[0..nJ) of P', AP', W'
+ * packed (column jj = column h_J[jj]); h_rho[j] = ||AX'_j - theta_j X'_j|| /
+ * (norm_A ||X'_j||) for all m columns.  Outputs must not alias inputs
+ * (ARG).  1 <= nW, nJ <= m, 0 <= nP <= m, h_J distinct in [0, m). */
+int lobpcg_update(lobpcg_ctx *ctx, int dtype, const void *d_X, const void *d_AX, const void *d_W,
+                  const void *d_AW, int nW, const void *d_P, const void *d_AP, int nP, const double *h_C,
+                  const double *h_theta, const int *h_J, int nJ, double norm_A, void *d_Xn, void *d_AXn,
+                  void *d_Pn, void *d_APn, void *d_Wn, double *h_rho);
 
 /* Step 7 and the norms of step 8: for the m columns of d_X, d_AX (N x m)
  * and Ritz values h_lambda, writes W_J = AX_J - X_J Lambda_J packed as

@@ -14,12 +14,10 @@
 // A workgroup (4 waves) walks tiles of 64 grid points; each wave multiplies
 // its 16 points by the coefficients (kept in LDS) with 16x16x4 MFMA, NT
 // 16-column output tiles at a time.  The MFMA A-fragment of a k-step is 16
-// rows x 4 columns of an input.  Four kernels share this scheme:
-//   mvf_kernel  (default) fragments loaded straight from global memory with
-//               16-byte loads, the k-sum split in contiguous quarters;
+// rows x 4 columns of an input.  Three kernels share this scheme:
+//   mvf_kernel  fragments loaded straight from global memory with 16-byte
+//               loads, the k-sum split in contiguous quarters;
 //   mvn_kernel  at most 8 columns in and out: one point per thread, plain FMA;
-//   mv_kernel / mvd_kernel  (kernel variants 2 / 1) wide inputs staged through
-//               LDS one stage ahead / per-element fragment loads;
 //   mvw_kernel  blocks wider than 32 columns: up to 12 input pieces of at most
 //               32 columns, 16, 32 or 64 output columns per launch.
 // Per-workgroup partial sums of the norms are added in a fixed order by a
@@ -32,8 +30,7 @@ namespace lobpcg {
 
 static const int TP = 64;          // grid points per tile (4 waves x 16)
 static const int MAXW = 32;        // widest input (stored columns)
-static const int NARROW = 8;       // inputs up to this width are not staged
-static const int LDT = MAXW + 1;   // LDS row stride: odd, so the 16 rows of an A fragment hit 16 banks
+static const int NARROW = 8;       // blocks up to this width: one point per thread (mvn_kernel)
 static const int MV_MAX_BLOCKS = 4096;
 
 template <typename T>
@@ -42,7 +39,7 @@ struct MVDev {
     int ld[MV_MAX_IN], k[MV_MAX_IN];
     const int *cols[MV_MAX_IN];
     int coff[MV_MAX_IN];
-    int nin, nside, kout, K, Kp;
+    int nin, nside, kout, K;
     int n0, ld2;
     const T *C;
     const T *add;
@@ -57,138 +54,6 @@ struct MVDev {
     double *partials;
     i64 N;
 };
-
-template <typename T>
-struct StageRegs {
-    static const int VE = 16 / sizeof(T);
-    static const int NV = TP * MAXW / VE / 256;
-    vec<T, VE> v[NV];
-};
-
-template <typename T>
-__device__ __forceinline__ void stage_load(StageRegs<T> &R, const T *__restrict__ src, int ld, i64 p0, i64 N)
-{
-    const int VE = StageRegs<T>::VE;
-    const i64 rows = (N - p0) < TP ? (N - p0) : TP;
-    const int nvec = TP * ld / VE, nvalid = (int)(rows * ld);
-    const T *s = src + p0 * ld;
-#pragma unroll
-    for (int i = 0; i < StageRegs<T>::NV; i++) {
-        const int vi = threadIdx.x + 256 * i;
-        if (vi >= nvec) break;
-        const int e0 = vi * VE;
-        if (e0 + VE <= nvalid) {
-            R.v[i] = vload<T, VE>(s + e0);
-        } else {
-#pragma unroll
-            for (int q = 0; q < VE; q++) R.v[i].v[q] = (e0 + q < nvalid) ? s[e0 + q] : T(0);
-        }
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void stage_store(T *tile, const StageRegs<T> &R, int ld)
-{
-    const int VE = StageRegs<T>::VE;
-    const int nvec = TP * ld / VE;
-    const float inv = 1.0f / (float)ld;
-#pragma unroll
-    for (int i = 0; i < StageRegs<T>::NV; i++) {
-        const int vi = threadIdx.x + 256 * i;
-        if (vi >= nvec) break;
-#pragma unroll
-        for (int q = 0; q < VE; q++) {
-            const int e = vi * VE + q;
-            // e < 64*32: the float quotient is within 2e-4 of e/ld, and
-            // (e + 0.5)/ld is at least 0.5/32 away from an integer
-            const int row = (int)(((float)e + 0.5f) * inv);
-            tile[row * LDT + e - row * ld] = R.v[i].v[q];
-        }
-    }
-}
-
-// acc[nt] += A C[roff .. roff+k-1] with A-fragments from a staged LDS row
-template <typename T, int NT>
-__device__ __forceinline__ void mma_lds(typename Mfma<T>::acc (&acc)[NT], const T *arow, const T *Cs, const int *cmap,
-                                        int roff, int k, int lane)
-{
-    const int NC = NT * 16;
-    for (int k0 = 0; k0 < k; k0 += 4) {
-        const int kr = k0 + (lane >> 4);
-        const bool ok = kr < k;
-        const T av = ok ? arow[cmap[roff + kr]] : T(0);
-        const T *crow = Cs + (roff + kr) * NC + (lane & 15);
-#pragma unroll
-        for (int nt = 0; nt < NT; nt++) {
-            const T bv = ok ? crow[16 * nt] : T(0);
-            acc[nt] = Mfma<T>::mma(av, bv, acc[nt]);
-        }
-    }
-}
-
-// the same with A-fragments straight from global memory (row `src` of this
-// lane, or zero past the grid); all loads of the input are issued first
-template <typename T, int NT>
-__device__ __forceinline__ void mma_global(typename Mfma<T>::acc (&acc)[NT], const T *__restrict__ src, bool pok,
-                                           const T *Cs, const int *cmap, int roff, int k, int lane)
-{
-    const int NC = NT * 16, kq = lane >> 4, lc = lane & 15;
-    T av[MAXW / 4];
-#pragma unroll
-    for (int i = 0; i < MAXW / 4; i++) {
-        const int kr = 4 * i + kq;
-        av[i] = (pok && kr < k) ? src[cmap[roff + kr]] : T(0);
-    }
-#pragma unroll
-    for (int i = 0; i < MAXW / 4; i++) {
-        if (4 * i >= k) break;
-        const int kr = 4 * i + kq;
-        const T *crow = Cs + (roff + kr) * NC + lc;
-        const bool ok = kr < k;
-#pragma unroll
-        for (int nt = 0; nt < NT; nt++) acc[nt] = Mfma<T>::mma(av[i], ok ? crow[16 * nt] : T(0), acc[nt]);
-    }
-}
-
-// Shared-memory layout of both kernels
-template <typename T, int NT>
-struct MVShared {
-    T *tile, *Cs;
-    double *theta, *red;
-    int *cmap, *opos, *wpos;
-    __device__ MVShared(unsigned char *smem, const MVDev<T> &a, bool staged)
-    {
-        const int NC = NT * 16;
-        tile = reinterpret_cast<T *>(smem);
-        Cs = tile + (staged ? TP * LDT : 0);
-        theta = reinterpret_cast<double *>(Cs + (a.Kp + 4) * NC);
-        red = theta + NC;                                    // [16 slots][2][NC]
-        cmap = reinterpret_cast<int *>(red + 16 * 2 * NC);   // [K + 4]
-        opos = cmap + a.K + 4;
-        wpos = opos + NC;
-    }
-};
-
-template <typename T, int NT>
-__device__ __forceinline__ void mv_setup(const MVShared<T, NT> &sh, const MVDev<T> &a)
-{
-    const int NC = NT * 16, tid = threadIdx.x;
-    for (int i = tid; i < (a.Kp + 4) * NC; i += blockDim.x) {
-        const int r = i / NC, c = i % NC;
-        sh.Cs[i] = (r < a.K && c < a.kout) ? a.C[r * a.kout + c] : T(0);
-    }
-    int roff = 0;
-    for (int b = 0; b < a.nin; b++) {
-        for (int r = tid; r < a.k[b]; r += blockDim.x) sh.cmap[roff + r] = a.cols[b] ? a.cols[b][r] : r;
-        roff += a.k[b];
-    }
-    for (int r = tid; r < 4; r += blockDim.x) sh.cmap[a.K + r] = 0;
-    for (int c = tid; c < NC; c += blockDim.x) {
-        sh.opos[c] = c < a.kout ? (a.opos ? a.opos[c] : c) : -1;
-        sh.wpos[c] = (c < a.kout && a.wpos) ? a.wpos[c] : -1;
-        sh.theta[c] = (c < a.kout && a.theta) ? a.theta[c] : 0.0;
-    }
-}
 
 // write the outputs of side s for the 16 points of this wave
 // LDSACC: the residual sums of squares accumulate in this lane's own entries
@@ -255,126 +120,6 @@ __device__ __forceinline__ void mv_norms(const MVDev<T> &a, const SH &sh, const 
         for (int sl = 0; sl < 16; sl++) sum += sh.red[(sl * 2 + which) * NC + c];
         a.partials[(i64)blockIdx.x * 2 * a.kout + e] = sum;
     }
-}
-
-// Staged kernel: wide inputs through LDS (prefetched one stage ahead), narrow
-// inputs straight from global memory.
-template <typename T, int NT>
-__global__ void __launch_bounds__(256) mv_kernel(MVDev<T> a)
-{
-    typedef typename Mfma<T>::acc accT;
-    extern __shared__ unsigned char smem[];
-    MVShared<T, NT> sh(smem, a, true);
-    mv_setup<T, NT>(sh, a);
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int roffs[3] = {0, a.k[0], a.k[0] + a.k[1]};
-    __syncthreads();
-
-    const bool has2 = a.out2[0] != nullptr;
-    // processing order within a side: with a second output, inputs 1.. first
-    // (they form out), then input 0 on top (out2)
-    int order[3];
-    for (int q = 0; q < a.nin; q++) order[q] = has2 ? (q + 1) % a.nin : q;
-    // the staged (wide) inputs of one tile, in order: stage k is (side, input)
-    int st_s[6], st_b[6], nst = 0;
-    for (int s = 0; s < a.nside; s++)
-        for (int q = 0; q < a.nin; q++)
-            if (a.ld[order[q]] > NARROW) st_s[nst] = s, st_b[nst] = order[q], nst++;
-
-    double sr[NT], sx[NT];
-#pragma unroll
-    for (int nt = 0; nt < NT; nt++) sr[nt] = sx[nt] = 0.0;
-    const T *arow = sh.tile + (16 * wave + (lane & 15)) * LDT;
-
-    const i64 ntiles = (a.N + TP - 1) / TP;
-    StageRegs<T> R;
-    if ((i64)blockIdx.x < ntiles)
-        stage_load<T>(R, a.in[st_s[0]][st_b[0]], a.ld[st_b[0]], (i64)blockIdx.x * TP, a.N);
-    for (i64 t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const i64 p0 = t * TP, p0w = p0 + 16 * wave, prow = p0w + (lane & 15);
-        const bool pok = prow < a.N;
-        int k = 0;   // next stage of this tile
-        accT keepX[NT];
-        for (int s = 0; s < a.nside; s++) {
-            accT acc[NT], acc2[NT];
-#pragma unroll
-            for (int nt = 0; nt < NT; nt++) acc[nt] = acc_zero<T>(), acc2[nt] = acc_zero<T>();
-            // one input into a fixed accumulator array (a runtime choice of
-            // array would force the accumulators out of registers)
-            auto input = [&](accT(&tgt)[NT], int b) {
-                if (a.ld[b] > NARROW) {
-                    __syncthreads();
-                    stage_store<T>(sh.tile, R, a.ld[b]);
-                    // prefetch the next stage: of this tile, or the first of the next tile
-                    const int kn = k + 1 < nst ? k + 1 : 0;
-                    const i64 tn = k + 1 < nst ? t : t + gridDim.x;
-                    if (tn < ntiles) stage_load<T>(R, a.in[st_s[kn]][st_b[kn]], a.ld[st_b[kn]], tn * TP, a.N);
-                    k++;
-                    __syncthreads();
-                    mma_lds<T, NT>(tgt, arow, sh.Cs, sh.cmap, roffs[b], a.k[b], lane);
-                } else {
-                    mma_global<T, NT>(tgt, a.in[s][b] + prow * a.ld[b], pok, sh.Cs, sh.cmap, roffs[b], a.k[b],
-                                      lane);
-                }
-            };
-            for (int b = has2 ? 1 : 0; b < a.nin; b++) input(acc, b);
-            if (has2) {
-#pragma unroll
-                for (int nt = 0; nt < NT; nt++) acc2[nt] = acc[nt];
-                input(acc2, 0);
-            }
-            mv_outputs<T, NT>(a, sh, s, p0w, acc, acc2, keepX, sr, sx, lane);
-            if (s == 0) {
-#pragma unroll
-                for (int nt = 0; nt < NT; nt++) keepX[nt] = acc2[nt];
-            }
-        }
-    }
-    if (a.partials) mv_norms<T, NT>(a, sh, sr, sx, wave, lane);
-}
-
-// All inputs straight from global memory: each wave owns groups of 16 grid
-// points and runs without workgroup barriers.
-template <typename T, int NT>
-__global__ void __launch_bounds__(256) mvd_kernel(MVDev<T> a)
-{
-    typedef typename Mfma<T>::acc accT;
-    extern __shared__ unsigned char smem[];
-    MVShared<T, NT> sh(smem, a, false);
-    mv_setup<T, NT>(sh, a);
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int roffs[3] = {0, a.k[0], a.k[0] + a.k[1]};
-    __syncthreads();
-
-    const bool has2 = a.out2[0] != nullptr;
-    double sr[NT], sx[NT];
-#pragma unroll
-    for (int nt = 0; nt < NT; nt++) sr[nt] = sx[nt] = 0.0;
-
-    const i64 ngroups = (a.N + 15) / 16;
-    for (i64 g = (i64)blockIdx.x * 4 + wave; g < ngroups; g += (i64)gridDim.x * 4) {
-        const i64 p0w = g * 16, prow = p0w + (lane & 15);
-        const bool pok = prow < a.N;
-        accT keepX[NT];
-        for (int s = 0; s < a.nside; s++) {
-            accT acc[NT], acc2[NT];
-#pragma unroll
-            for (int nt = 0; nt < NT; nt++) acc[nt] = acc_zero<T>(), acc2[nt] = acc_zero<T>();
-            for (int b = has2 ? 1 : 0; b < a.nin; b++)
-                mma_global<T, NT>(acc, a.in[s][b] + prow * a.ld[b], pok, sh.Cs, sh.cmap, roffs[b], a.k[b], lane);
-            if (has2) {
-#pragma unroll
-                for (int nt = 0; nt < NT; nt++) acc2[nt] = acc[nt];
-                mma_global<T, NT>(acc2, a.in[s][0] + prow * a.ld[0], pok, sh.Cs, sh.cmap, 0, a.k[0], lane);
-            }
-            mv_outputs<T, NT>(a, sh, s, p0w, acc, acc2, keepX, sr, sx, lane);
-            if (s == 0) {
-#pragma unroll
-                for (int nt = 0; nt < NT; nt++) keepX[nt] = acc2[nt];
-            }
-        }
-    }
-    if (a.partials) mv_norms<T, NT>(a, sh, sr, sx, wave, lane);
 }
 
 // Fragment kernel: A-fragments loaded straight from global memory with
@@ -647,6 +392,302 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     if (a.partials) mv_norms<T, NT, MVFShared<T, NT>, true>(a, sh, sr, sx, wave, lane);
 }
 
+// ---------------------------------------------------------------- LDS-pipelined update (FP32)
+//
+// The fused update of steps 25-33 and 7 for FP32 blocks (mvf_kernel's case
+// with X', AX', the residual and two or three inputs of at most 32 columns
+// without column lists) with its inputs moved by the buffer loads' LDS path:
+// global memory straight into LDS, no registers held while in flight.  Each
+// wave walks its 16-point groups one side at a time (side 0: X, W, P; side
+// 1: AX, AW, AP) and keeps the loads of the next two sides in flight in a
+// two-slot ring while it multiplies the current one, so that the bytes in
+// flight no longer depend on the registers (the FP32 fragment kernel holds
+// half as many bytes per register as the FP64 one).  The loads and stores
+// are inline assembly, so that the number of vector-memory operations issued
+// between two sides is fixed and one vmcnt wait per side suffices; loads
+// past N and stores of rows past N or of inactive columns use offsets past
+// the buffer's range, which the hardware drops (loads return zero).
+typedef int mvl_v4i __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void mvl_lds_t;
+static const unsigned MVL_OOB = 0x80000000u;   // a buffer offset past every range: the access is dropped
+
+// buffer resource of `bytes` bytes from base (raw: no stride, no format)
+__device__ __forceinline__ mvl_v4i mvl_rsrc(const void *base, unsigned bytes)
+{
+    const unsigned long long p = (unsigned long long)base;
+    mvl_v4i r;
+    r.x = __builtin_amdgcn_readfirstlane((int)(unsigned)p);
+    r.y = __builtin_amdgcn_readfirstlane((int)((unsigned)(p >> 32) & 0xffffu));
+    r.z = __builtin_amdgcn_readfirstlane((int)bytes);
+    r.w = 0x00020000;
+    return r;
+}
+// stores at byte offset off of buffer r (dropped when off is past its range)
+__device__ __forceinline__ void mvl_st1(mvl_v4i r, unsigned off, float v)
+{
+    asm volatile("buffer_store_dword %0, %1, %2, 0 offen" ::"v"(v), "v"(off), "s"(r) : "memory");
+}
+__device__ __forceinline__ void mvl_st4(mvl_v4i r, unsigned off, floatx4 v)
+{
+    asm volatile("buffer_store_dwordx4 %0, %1, %2, 0 offen" ::"v"(v), "v"(off), "s"(r) : "memory");
+}
+// 16 bytes per lane from global memory (buffer r, byte offset voff) straight
+// into LDS at byte address lds + 16 * lane.  Written as inline assembly, so
+// that the compiler, which does not see these loads, adds no waits of its own
+// before the LDS reads; the kernel waits for them itself (mvl_wait_vm).  The
+// kernel uses m0 for nothing else.
+__device__ __forceinline__ void mvl_dma16(mvl_v4i r, unsigned lds, unsigned voff)
+{
+    asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, 0 offen lds" ::"s"(lds), "v"(voff), "s"(r)
+                 : "memory");
+}
+// wait until at most N vector-memory operations of this wave are outstanding
+// (they complete in issue order)
+template <int N>
+__device__ __forceinline__ void mvl_wait_vm()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt");
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+__device__ __forceinline__ void mvl_wait_lds() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+static const int MVL_SLOT = 16 * 32;   // floats of one input's 16 rows (at most 32 columns)
+static const int MVL_ST0 = 10;         // store instructions per side: P (8) and X' (2)
+static const int MVL_ST1 = 18;         // AP (8), W (8) and AX' (2)
+
+template <int NIN>
+__global__ void __launch_bounds__(256) mvl_kernel(MVDev<float> a)
+{
+    typedef float T;
+    typedef floatx4 accT;
+    const int NT = 2, NC = 32;
+    extern __shared__ unsigned char smem[];
+    const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, kq = lane >> 4,
+              lr = lane & 15;
+    int k4[NIN], soff[NIN], roffs[NIN];
+    int nsteps = 0, roff = 0;
+#pragma unroll
+    for (int b = 0; b < NIN; b++) {
+        k4[b] = mvf_k4(a.k[b], a.ld[b], false, 4);
+        soff[b] = nsteps;
+        roffs[b] = roff;
+        nsteps += k4[b];
+        roff += a.k[b];
+    }
+    T *Cf = reinterpret_cast<T *>(smem);
+    double *theta = reinterpret_cast<double *>(Cf + nsteps * NT * 64);
+    int *opos = reinterpret_cast<int *>(theta + NC), *wpos = opos + NC;
+    T *stage = reinterpret_cast<T *>(wpos + NC);                 // [4 waves][16][NC + 4]
+    T *ring = stage + 4 * 16 * (NC + 4);                         // [4 waves][2][NIN][MVL_SLOT]
+    for (int e = tid; e < nsteps * NT * 64; e += blockDim.x) {
+        const int l = e & 63, nt = (e >> 6) % NT, st = (e >> 6) / NT;
+        // the input of k-step st, without indexing the arrays by a runtime value
+        int i = st, kb = a.k[0], k4b = k4[0], rb = 0;
+#pragma unroll
+        for (int b = 1; b < NIN; b++)
+            if (st >= soff[b]) i = st - soff[b], kb = a.k[b], k4b = k4[b], rb = roffs[b];
+        const int j = (l >> 4) * k4b + i, c = 16 * nt + (l & 15);
+        Cf[e] = (j < kb && c < a.kout) ? a.C[(rb + j) * a.kout + c] : T(0);
+    }
+    for (int c = tid; c < NC; c += blockDim.x) {
+        opos[c] = c < a.kout ? a.opos[c] : -1;
+        wpos[c] = c < a.kout ? a.wpos[c] : -1;
+        theta[c] = c < a.kout ? a.theta[c] : 0.0;
+    }
+    __syncthreads();
+
+    // per input: the byte offset each lane fetches for DMA instruction j (two
+    // per input, 64 lanes x 16 bytes each).  Rows of a multiple of 4 columns
+    // go to LDS rotated by their row index, chunk c of row r at chunk
+    // (c + r) mod cpr, so that the 16 rows of a fragment read hit distinct banks.
+    unsigned voff[NIN][2];
+    bool aligned[NIN];
+#pragma unroll
+    for (int b = 0; b < NIN; b++) {
+        const int ld = a.ld[b];
+        aligned[b] = (ld % 4) == 0;
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            const int P = 64 * j + lane;
+            unsigned off = MVL_OOB;
+            if (P < 4 * ld) {
+                if (aligned[b]) {
+                    const int cpr = ld / 4, r = P / cpr, cpos = P - r * cpr;
+                    const int c = (cpos - r % cpr + cpr) % cpr;
+                    off = (unsigned)((r * cpr + c) * 16);
+                } else {
+                    off = (unsigned)(P * 16);
+                }
+            }
+            voff[b][j] = off;
+        }
+    }
+    T *myring = ring + wave * 2 * NIN * MVL_SLOT;
+    const unsigned ring_lds = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(uintptr_t)myring);
+    const i64 ngroups = (a.N + 15) / 16, gstride = (i64)gridDim.x * 4, g0 = (i64)blockIdx.x * 4 + wave;
+    const int G = g0 < ngroups ? (int)((ngroups - 1 - g0) / gstride + 1) : 0;
+    const int Tn = 2 * G;
+    auto issue = [&](int t) {
+        const i64 p0 = (g0 + (i64)(t >> 1) * gstride) * 16;
+        const int s = t & 1;
+        const int nrows = (int)min((i64)16, a.N - p0);
+#pragma unroll
+        for (int b = 0; b < NIN; b++) {
+            const mvl_v4i r = mvl_rsrc(a.in[s][b] + p0 * a.ld[b], (unsigned)(nrows * a.ld[b] * 4));
+            const unsigned slot = ring_lds + (unsigned)(((t & 1) * NIN + b) * MVL_SLOT * 4);
+#pragma unroll
+            for (int j = 0; j < 2; j++) mvl_dma16(r, slot + 1024 * j, voff[b][j]);
+        }
+    };
+    // fragments of input b from its LDS slot: av[i] = column kq*k4 + i of row lr
+    auto frag = [&](T(&av)[KQ], const T *slot, int b) {
+        const int k = a.k[b], ld = a.ld[b], j0 = kq * k4[b];
+        if (aligned[b]) {
+            const int cpr = ld / 4;
+#pragma unroll
+            for (int i = 0; i < KQ; i += 4) {
+                if (i >= k4[b]) break;
+                const int c = (j0 + i) >> 2;
+                int cpos = c + lr % cpr;
+                cpos = cpos >= cpr ? cpos - cpr : cpos;
+                // always read (a chunk past the row is some other chunk of the
+                // slot), then keep the columns below k
+                const floatx4 v = *reinterpret_cast<const floatx4 *>(slot + ((lr * cpr + cpos) & (MVL_SLOT / 4 - 1)) * 4);
+#pragma unroll
+                for (int q = 0; q < 4; q++) av[i + q] = (4 * c + q < k) ? v[q] : T(0);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < KQ; i++) {
+                if (i >= k4[b]) break;
+                const int j = j0 + i;
+                const T v = slot[(lr * ld + j) & (MVL_SLOT - 1)];
+                av[i] = j < k ? v : T(0);
+            }
+        }
+    };
+    auto mma_in = [&](accT(&tgt)[NT], const T(&av)[KQ], int b) {
+        const T *cf = Cf + soff[b] * NT * 64 + lane;
+#pragma unroll
+        for (int i = 0; i < KQ; i++) {
+            if (i >= k4[b]) break;
+#pragma unroll
+            for (int nt = 0; nt < NT; nt++) tgt[nt] = Mfma<T>::mma(av[i], cf[(i * NT + nt) * 64], tgt[nt]);
+        }
+    };
+    double sr[NT], sx[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; nt++) sr[nt] = sx[nt] = 0.0;
+    accT keepX[NT];
+    T *st = stage + wave * 16 * (NC + 4);
+    if (Tn > 0) issue(0);
+    if (Tn > 1) issue(1);
+    for (int t = 0; t < Tn; t++) {
+        // Stage t has arrived once no more than the operations issued after
+        // its loads are outstanding: the loads of stage t+1 (2 NIN) and the
+        // stores of stages t-2 and t-1 (MVL_ST0 on side 0, MVL_ST1 on side
+        // 1); in the last stage, all of them
+        if (t + 1 >= Tn) mvl_wait_vm<0>();
+        else if (t == 0) mvl_wait_vm<2 * NIN>();
+        else if (t == 1) mvl_wait_vm<2 * NIN + MVL_ST0>();
+        else mvl_wait_vm<2 * NIN + MVL_ST0 + MVL_ST1>();
+        const T *slots = myring + (t & 1) * NIN * MVL_SLOT;
+        T av[NIN][KQ];
+#pragma unroll
+        for (int b = 0; b < NIN; b++) frag(av[b], slots + b * MVL_SLOT, b);
+        mvl_wait_lds();   // the reads of slot t&1 are done before it is refilled
+        if (t + 2 < Tn) issue(t + 2);
+        const int s = t & 1;
+        const i64 p0 = (g0 + (i64)(t >> 1) * gstride) * 16;
+        const int nrows = (int)min((i64)16, a.N - p0);
+        accT acc[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) acc[nt] = acc_zero<T>();
+#pragma unroll
+        for (int b = 1; b < NIN; b++) mma_in(acc, av[b], b);
+        // P (side 0) or AP (side 1) in the active columns
+        {
+            const mvl_v4i r = mvl_rsrc(a.out[s] + p0 * a.nout, (unsigned)(nrows * a.nout * 4));
+#pragma unroll
+            for (int rr = 0; rr < 4; rr++)
+#pragma unroll
+                for (int nt = 0; nt < NT; nt++) {
+                    const int q = opos[16 * nt + lr];
+                    const int row = Mfma<T>::row(lane, rr);
+                    mvl_st1(r, q >= 0 ? (unsigned)((row * a.nout + q) * 4) : MVL_OOB, acc[nt][rr]);
+                }
+        }
+        mma_in(acc, av[0], 0);
+        // side 1: the residual W = AX' - X' Theta in the active columns and
+        // the column sums of squares of step 8
+        if (s == 1) {
+            const mvl_v4i r = mvl_rsrc(a.Wout + p0 * a.nW, (unsigned)(nrows * a.nW * 4));
+#pragma unroll
+            for (int rr = 0; rr < 4; rr++)
+#pragma unroll
+                for (int nt = 0; nt < NT; nt++) {
+                    const int c = 16 * nt + lr, row = Mfma<T>::row(lane, rr);
+                    const double x = (double)keepX[nt][rr];
+                    const double rv = (double)acc[nt][rr] - theta[c] * x;
+                    if (row < nrows && c < a.kout) {
+                        sr[nt] += rv * rv;
+                        sx[nt] += x * x;
+                    }
+                    const int w = wpos[c];
+                    mvl_st1(r, w >= 0 ? (unsigned)((row * a.nW + w) * 4) : MVL_OOB, (T)rv);
+                }
+        } else {
+#pragma unroll
+            for (int nt = 0; nt < NT; nt++) keepX[nt] = acc[nt];
+        }
+        // X' or AX' through this wave's LDS tile: after the transpose each
+        // lane holds four consecutive columns of one row and stores 16 bytes
+        {
+#pragma unroll
+            for (int rr = 0; rr < 4; rr++)
+#pragma unroll
+                for (int nt = 0; nt < NT; nt++) st[Mfma<T>::row(lane, rr) * (NC + 4) + 16 * nt + lr] = acc[nt][rr];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            const mvl_v4i r = mvl_rsrc(a.out2[s] + p0 * a.ld2, (unsigned)(nrows * a.ld2 * 4));
+            const int row = lane >> 2;
+#pragma unroll
+            for (int h = 0; h < NT; h++) {
+                const int c0 = 4 * ((lane & 3) + 4 * h);
+                const floatx4 v = *reinterpret_cast<const floatx4 *>(st + row * (NC + 4) + c0);
+                mvl_st4(r, c0 < a.kout ? (unsigned)((row * a.ld2 + c0) * 4) : MVL_OOB, v);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        }
+    }
+    mvl_wait_vm<0>();
+    // per-workgroup column sums, reduced over the 16 lane groups in LDS (the
+    // ring is free now)
+    __syncthreads();
+    double *red = reinterpret_cast<double *>(ring);
+    {
+        const int slot = wave * 4 + kq;
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+            red[(slot * 2 + 0) * NC + 16 * nt + lr] = sr[nt];
+            red[(slot * 2 + 1) * NC + 16 * nt + lr] = sx[nt];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < 2 * a.kout; e += blockDim.x) {
+        const int which = e / a.kout, c = e % a.kout;
+        double sum = 0.0;
+        for (int sl = 0; sl < 16; sl++) sum += red[(sl * 2 + which) * NC + c];
+        a.partials[(i64)blockIdx.x * 2 * a.kout + e] = sum;
+    }
+}
+
+// dynamic LDS of mvl_kernel: coefficients, theta, opos, wpos, the output
+// tiles and the input rings
+static size_t mvl_lds_bytes(int nin, int nsteps)
+{
+    return (size_t)nsteps * 2 * 64 * 4 + 32 * 8 + 2 * 32 * 4 + 4 * 16 * 36 * 4 + (size_t)4 * 2 * nin * MVL_SLOT * 4;
+}
+
 // Wide kernel: blocks of more than MAXW columns, given as up to MV_MAX_IN
 // pieces of at most MAXW columns each (a piece is a column range or a column
 // list of one block).  The products are those of the fragment kernel's FP64
@@ -886,11 +927,10 @@ int mv_wide_chunk(int dtype, int nin, const int *k)
 }
 
 template <typename T>
-static MVDev<T> make_dev(const MVArgs &h, bool &any_wide)
+static MVDev<T> make_dev(const MVArgs &h)
 {
     MVDev<T> a;
     a.K = 0;
-    any_wide = false;
     for (int b = 0; b < MV_MAX_IN; b++) {
         const bool used = b < h.nin;
         for (int s = 0; s < 2; s++) a.in[s][b] = used ? (const T *)h.in[s][b] : nullptr;
@@ -899,14 +939,12 @@ static MVDev<T> make_dev(const MVArgs &h, bool &any_wide)
         a.cols[b] = used ? h.cols[b] : nullptr;
         a.coff[b] = used ? h.coff[b] : 0;
         a.K += a.k[b];
-        if (used && h.ld[b] > NARROW) any_wide = true;
     }
     a.nin = h.nin;
     a.n0 = h.n0;
     a.ld2 = h.ld2 > 0 ? h.ld2 : h.kout;
     a.nside = h.nside;
     a.kout = h.kout;
-    a.Kp = (a.K + 3) / 4 * 4;
     a.C = (const T *)h.C;
     a.add = (const T *)h.add;
     for (int s = 0; s < 2; s++) {
@@ -938,8 +976,7 @@ static hipError_t mv_reduce(const MVArgs &h, int nb, hipStream_t st)
 template <typename T, int NT>
 static hipError_t run_mvw(const MVArgs &h, hipStream_t st)
 {
-    bool any_wide;
-    MVDev<T> a = make_dev<T>(h, any_wide);
+    MVDev<T> a = make_dev<T>(h);
     const int nb = mv_blocks(h.N);
     int nsteps = 0;
     for (int b = 0; b < h.nin; b++) nsteps += (h.k[b] + 3) / 4;
@@ -948,33 +985,54 @@ static hipError_t run_mvw(const MVArgs &h, hipStream_t st)
     return mv_reduce(h, nb, st);
 }
 
+// the fused FP32 update that mvl_kernel takes
+static bool mvl_fits(const MVArgs &h)
+{
+    if (h.nside != 2 || h.nin < 2 || h.nin > 3 || h.n0 != 1 || h.add || !h.partials || !h.theta || !h.opos ||
+        !h.wpos || !h.Wout)
+        return false;
+    for (int s = 0; s < 2; s++)
+        if (!h.out[s] || !h.out2[s]) return false;
+    if (h.kout > MAXW || h.kout % 4 || (h.ld2 > 0 && h.ld2 != h.kout) || (h.sums_ld > 0 && h.sums_ld != h.kout))
+        return false;
+    bool narrow = h.kout <= NARROW;
+    for (int b = 0; b < h.nin; b++) {
+        if (h.cols[b] || h.coff[b] || h.ld[b] > MAXW || h.k[b] > h.ld[b]) return false;
+        narrow = narrow && h.ld[b] <= NARROW;
+    }
+    return !narrow;
+}
+
+static hipError_t run_mvl(const MVArgs &h, hipStream_t st)
+{
+    MVDev<float> a = make_dev<float>(h);
+    const int nb = mv_blocks(h.N);
+    int nsteps = 0;
+    for (int b = 0; b < h.nin; b++) nsteps += mvf_k4(h.k[b], h.ld[b], false, 4);
+    const size_t shm = mvl_lds_bytes(h.nin, nsteps);
+    if (h.nin == 3)
+        hipLaunchKernelGGL((mvl_kernel<3>), dim3(nb), dim3(256), shm, st, a);
+    else
+        hipLaunchKernelGGL((mvl_kernel<2>), dim3(nb), dim3(256), shm, st, a);
+    return mv_reduce(h, nb, st);
+}
+
 template <typename T, int NT>
 static hipError_t run_mv(const MVArgs &h, hipStream_t st)
 {
-    bool any_wide;
-    MVDev<T> a = make_dev<T>(h, any_wide);
-    const int NC = NT * 16;
+    MVDev<T> a = make_dev<T>(h);
     const int nb = mv_blocks(h.N);
     bool narrow = h.kout <= NARROW;
     for (int b = 0; b < h.nin; b++) narrow = narrow && h.ld[b] <= NARROW;
-    const size_t tail = (size_t)NC * 8 + (size_t)16 * 2 * NC * 8 + (size_t)(a.K + 4 + 2 * NC) * sizeof(int);
-    if (h.variant == 0 && narrow) {
+    if (narrow) {
         const size_t shm = (size_t)NARROW * 8 + (size_t)2 * NARROW * 256 * 8 + (size_t)a.K * NARROW * sizeof(T) +
                            (size_t)(a.K + 2 * NARROW) * sizeof(int);
         hipLaunchKernelGGL((mvn_kernel<T>), dim3(nb), dim3(256), shm, st, a);
-    } else if (h.variant == 0) {
+    } else {
         int nsteps = 0;
         for (int b = 0; b < h.nin; b++) nsteps += mvf_k4(h.k[b], h.ld[b], h.cols[b] != nullptr, sizeof(T));
         const size_t shm = mvf_stage_offset(nsteps, NT, a.K, sizeof(T)) + mvf_stage_bytes(NT, sizeof(T));
         hipLaunchKernelGGL((mvf_kernel<T, NT>), dim3(nb), dim3(256), shm, st, a);
-    } else {
-        const bool staged = any_wide && h.variant == 2;
-        size_t shm = (staged ? (size_t)TP * LDT * sizeof(T) : 0) + (size_t)(a.Kp + 4) * NC * sizeof(T);
-        shm = (shm + 7) / 8 * 8 + tail;
-        if (staged)
-            hipLaunchKernelGGL((mv_kernel<T, NT>), dim3(nb), dim3(256), shm, st, a);
-        else
-            hipLaunchKernelGGL((mvd_kernel<T, NT>), dim3(nb), dim3(256), shm, st, a);
     }
     return mv_reduce(h, nb, st);
 }
@@ -1003,6 +1061,7 @@ hipError_t launch_mv(int dtype, const MVArgs &a, hipStream_t st)
         return nt == 4 ? run_mvw<double, 4>(a, st) : nt == 2 ? run_mvw<double, 2>(a, st) : run_mvw<double, 1>(a, st);
     }
     const bool two = a.kout > 16;
+    if (dtype == DT_F32 && !a.frag_only && mvl_fits(a)) return run_mvl(a, st);
     if (dtype == DT_F32) return two ? run_mv<float, 2>(a, st) : run_mv<float, 1>(a, st);
     return two ? run_mv<double, 2>(a, st) : run_mv<double, 1>(a, st);
 }

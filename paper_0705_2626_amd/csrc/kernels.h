@@ -95,8 +95,7 @@ struct MVArgs {
     double *partials;       // [mv_blocks(N)][2 kout]
     double *sums;           // [2 kout]
     long long N;
-    int variant;            // 0: by shape (narrow: one point per thread; else 16-byte fragment loads),
-                            // 1: per-element fragment loads, 2: tiles staged through LDS
+    int frag_only = 0;      // 1: the FP32 update on mvf_kernel even where the LDS-pipelined kernel applies
 };
 int mv_blocks(long long N);
 hipError_t launch_mv(int dtype, const MVArgs &a, hipStream_t st);

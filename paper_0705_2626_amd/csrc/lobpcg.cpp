@@ -175,7 +175,7 @@ struct lobpcg_ctx {
     bool profile, reactivate;
     double lock_gap;              // soft locking keeps a converged column active while an unconverged
                                   // one has a Ritz value within this relative distance (0: off)
-    int mv_variant, gram_staged, gram_nt4, gram_nt32, gram_direct;  // kernel variants (see LOBPCG_OPT_KERNELS)
+    int mv_frag, gram_staged, gram_nt4, gram_nt32, gram_direct;  // kernel variants (see LOBPCG_OPT_KERNELS)
     bool fp32_explicit;           // FP32 phase: Gram diagonal blocks computed, not assumed
     bool fp64_explicit;           // the same for FP64 iterations
     bool fold;                    // Cholesky-QR factors of W_J, P_J folded into Gram and coefficients
@@ -562,9 +562,9 @@ int mv(lobpcg_ctx *c, int dt, const MV &q, const double *C, int step)
         add_bytes(c, step, cols * c->N * esize(dt));
     };
     MVArgs a;
+    a.frag_only = c->mv_frag;
     a.nside = q.nside;
     a.N = c->N;
-    a.variant = c->mv_variant;
     a.partials = q.resid ? c->d_mv_part : nullptr;
     a.sums = q.resid ? c->d_res_out : nullptr;
     a.theta = q.theta;
@@ -1679,7 +1679,7 @@ int lobpcg_setup(lobpcg_ctx **out, const lobpcg_op *A, const lobpcg_op *B, const
     c->profile = false;
     c->reactivate = true;
     c->lock_gap = 0.0;
-    c->mv_variant = 0;
+    c->mv_frag = 0;
     c->gram_staged = 0;
     c->gram_nt4 = 0;
     c->gram_nt32 = 2;
@@ -1737,8 +1737,8 @@ int lobpcg_set_option(lobpcg_ctx *c, int key, double v)
     case LOBPCG_OPT_FOLD_CHOLQR: c->fold = v != 0; return LOBPCG_OK;
     case LOBPCG_OPT_FP64_EXPLICIT_GRAM: c->fp64_explicit = v != 0; return LOBPCG_OK;
     case LOBPCG_OPT_KERNELS:
-        if (v < 0 || v > 63 || ((int)v & 3) == 3) return LOBPCG_ERR_ARG;
-        c->mv_variant = (int)v & 3;
+        if (v < 0 || v > 63 || ((int)v & 2) != 0) return LOBPCG_ERR_ARG;
+        c->mv_frag = ((int)v & 1) != 0;
         c->gram_staged = ((int)v & 4) != 0;
         c->gram_nt4 = ((int)v & 8) != 0;
         c->gram_nt32 = ((int)v & 16) ? 4 : 2;
@@ -2036,6 +2036,61 @@ int lobpcg_combine(lobpcg_ctx *c, int dt, int n, const void *const *in, const in
     int s = mv(c, dt == LOBPCG_F32 ? DT_F32 : DT_F64, q, h_C, LOBPCG_STEP_UPDATE);
     if (s) return s;
     return sync(c);
+}
+
+int lobpcg_update(lobpcg_ctx *c, int dt, const void *d_X, const void *d_AX, const void *d_W, const void *d_AW,
+                  int nW, const void *d_P, const void *d_AP, int nP, const double *h_C, const double *h_theta,
+                  const int *h_J, int nJ, double norm_A, void *d_Xn, void *d_AXn, void *d_Pn, void *d_APn,
+                  void *d_Wn, double *h_rho)
+{
+    if (!c || !dtype_ok(c, dt)) return LOBPCG_ERR_ARG;
+    const int m = c->m;
+    if (!d_X || !d_AX || !d_W || !d_AW || nW < 1 || nW > m || nP < 0 || nP > m || (nP && (!d_P || !d_AP)) ||
+        !h_C || !h_theta || !h_J || nJ < 1 || nJ > m || !(norm_A > 0) || !d_Xn || !d_AXn || !d_Pn || !d_APn ||
+        !d_Wn || !h_rho)
+        return LOBPCG_ERR_ARG;
+    const void *ins[6] = {d_X, d_AX, d_W, d_AW, d_P, d_AP};
+    const void *outs[5] = {d_Xn, d_AXn, d_Pn, d_APn, d_Wn};
+    for (const void *o : outs)
+        for (const void *i : ins)
+            if (o && o == i) return LOBPCG_ERR_ARG;
+    std::vector<int> jpos(m, -1);
+    for (int i = 0; i < nJ; i++) {
+        const int j = h_J[i];
+        if (j < 0 || j >= m || jpos[j] >= 0) return LOBPCG_ERR_ARG;
+        jpos[j] = i;
+    }
+    const int *djpos;
+    const double *dtheta;
+    int s = upload_cols(c, jpos, &djpos);
+    if (s) return s;
+    s = upload_doubles(c, std::vector<double>(h_theta, h_theta + m), &dtheta);
+    if (s) return s;
+    MV q;
+    q.nside = 2;
+    q.input(0, d_X, d_AX, m, m);
+    q.input(1, d_W, d_AW, nW, nW);
+    if (nP) q.input(2, d_P, d_AP, nP, nP);
+    q.kout = m;
+    q.out[0] = d_Pn;
+    q.out[1] = d_APn;
+    q.opos = djpos;
+    q.nout = nJ;
+    q.out2[0] = d_Xn;
+    q.out2[1] = d_AXn;
+    q.resid = true;
+    q.theta = dtheta;
+    q.wpos = djpos;
+    q.Wout = d_Wn;
+    q.nW = nJ;
+    s = mv(c, dt == LOBPCG_F32 ? DT_F32 : DT_F64, q, h_C, LOBPCG_STEP_UPDATE);
+    if (s) return s;
+    double *h = (double *)(c->h_pin + c->h_res_off);
+    HIPCHK(hipMemcpyAsync(h, c->d_res_out, 2 * m * 8, hipMemcpyDeviceToHost, c->st));
+    s = sync(c);
+    if (s) return s;
+    for (int j = 0; j < m; j++) h_rho[j] = std::sqrt(h[j]) / (norm_A * std::sqrt(h[m + j]));
+    return LOBPCG_OK;
 }
 
 int lobpcg_residual(lobpcg_ctx *c, int dt, const void *X, const void *AX, int m, const double *h_lambda,

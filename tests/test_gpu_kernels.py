@@ -237,10 +237,8 @@ def test_gram_is_deterministic():
                                                 (9999, (7,), 7, True), (3001, (5, 2), 3, True), (3, (1,), 1, False),
                                                 (777, (30, 9), 17, False), (2049, (12, 4), 12, True)])
 @pytest.mark.parametrize("prec", [L.FP64, L.MIXED])
-@pytest.mark.parametrize("variant", [0, 1, 2])
-def test_combine(N, ks, kout, use_cols, prec, variant):
+def test_combine(N, ks, kout, use_cols, prec):
     ctx = ctx_for((N, 1, 1), min(32, N // 3), None, L.MIXED)
-    L.lobpcg_set_option(ctx, L.OPT_KERNELS, variant)
     dtype = torch.float64 if prec == L.FP64 else torch.float32
     rng = np.random.default_rng(N + kout)
     ld = [k + (3 if use_cols else 0) for k in ks]
@@ -309,6 +307,82 @@ def test_gram_wide(N, widths, prec, paper):
     assert np.all(np.abs(SAS - Sf.T @ ASf)[iu] <= tolA[iu])
     np.testing.assert_array_equal(SAS[~wantA], 0.0)
     np.testing.assert_array_equal(SAS, SAS.T)
+
+
+# ---------------------------------------------------------------- the fused update (steps 25-33 and 7)
+
+def update_reference(X, AX, W, AW, P, AP, C, theta, J, norm_A):
+    """Steps 25-33 and 7 as plain FP64 matrix algebra."""
+    m, nW = X.shape[1], W.shape[1]
+    CX, CW, CP = C[:m], C[m:m + nW], C[m + nW:]
+    Pn = W @ CW + (P @ CP if P is not None else 0.0)
+    APn = AW @ CW + (AP @ CP if P is not None else 0.0)
+    Xn, AXn = X @ CX + Pn, AX @ CX + APn
+    R = AXn - Xn * theta[None, :]
+    rho = np.linalg.norm(R, axis=0) / (norm_A * np.linalg.norm(Xn, axis=0))
+    return Xn, AXn, Pn[:, J], APn[:, J], R[:, J], rho
+
+
+# shapes: the LDS-pipelined FP32 kernel (m a multiple of 4, at most 32
+# columns: W and P widths that are and are not multiples of 4, with and
+# without P, ragged last groups of 16 points, a grid of fewer points than one
+# workgroup pass), the fragment kernel (m = 30), the narrow kernel (m = 8) and
+# the wide kernel (m = 48)
+UPDATE_SHAPES = [(5003, 32, 32, 32, 32), (70001, 32, 20, 20, 20), (4099, 32, 23, 23, 21), (777, 32, 32, 0, 32),
+                 (3001, 12, 7, 5, 7), (37, 12, 5, 5, 4), (2049, 30, 17, 17, 15), (1000, 8, 5, 3, 5),
+                 (3000, 48, 40, 40, 33)]
+
+
+def update_inputs(N, m, nW, nP, nJ, npdt):
+    rng = np.random.default_rng(N + 7 * m + nW)
+    blk = lambda w, s: synth.random_block(N, w, seed=s).astype(npdt)
+    X, AX, W, AW = blk(m, 1), blk(m, 2), blk(nW, 3), blk(nW, 4)
+    P, AP = (blk(nP, 5), blk(nP, 6)) if nP else (None, None)
+    C = rng.standard_normal((m + nW + nP, m)) / np.sqrt(m)
+    theta = np.sort(rng.uniform(0.01, 2.0, m))
+    J = np.sort(rng.choice(m, size=nJ, replace=False))
+    return X, AX, W, AW, P, AP, C, theta, J
+
+
+@pytest.mark.parametrize("N,m,nW,nP,nJ", UPDATE_SHAPES)
+@pytest.mark.parametrize("prec", [L.FP64, L.MIXED])
+def test_update(N, m, nW, nP, nJ, prec):
+    ctx = ctx_for((N, 1, 1), m, None, L.MIXED)
+    npdt = np.float64 if prec == L.FP64 else np.float32
+    dtype = torch.float64 if prec == L.FP64 else torch.float32
+    X, AX, W, AW, P, AP, C, theta, J = update_inputs(N, m, nW, nP, nJ, npdt)
+    d = lambda a: dev(a, dtype) if a is not None else None
+    got = L.lobpcg_update(ctx, d(X), d(AX), d(W), d(AW), d(P), d(AP), C, theta, J, 12.0)
+    f64 = lambda a: a.astype(np.float64) if a is not None else None
+    # the FP32 kernels multiply by the coefficients rounded to FP32
+    Cr = C.astype(np.float32).astype(np.float64) if prec == L.MIXED else C
+    ref = update_reference(f64(X), f64(AX), f64(W), f64(AW), f64(P), f64(AP), Cr, theta, J, 12.0)
+    K = C.shape[0]
+    S = np.hstack([f64(X), f64(W)] + ([f64(P)] if nP else []))
+    scale = (np.abs(S) @ np.abs(Cr)).max()
+    tol = (1e-14 if prec == L.FP64 else 4 * K * EPS32) * scale
+    names = ["X'", "AX'", "P'_J", "AP'_J", "W'_J"]
+    for name, g, r in zip(names, got[:5], ref[:5]):
+        assert g.shape == r.shape, name
+        # W' = AX' - theta X' adds the error of X' times theta <= 2
+        np.testing.assert_allclose(host(g), r, rtol=0, atol=3 * tol, err_msg=name)
+    np.testing.assert_allclose(got[5], ref[5], rtol=1e-12 if prec == L.FP64 else 1e-4)
+
+
+@pytest.mark.parametrize("N,m,nW,nP,nJ", [s for s in UPDATE_SHAPES if s[1] % 4 == 0 and 8 < s[1] <= 32])
+def test_update_kernels_agree(N, m, nW, nP, nJ):
+    """The LDS-pipelined FP32 update and the fragment kernel (kernel variant
+    bit 0) take the same products in the same order: identical blocks."""
+    X, AX, W, AW, P, AP, C, theta, J = update_inputs(N, m, nW, nP, nJ, np.float32)
+    d = lambda a: dev(a, torch.float32) if a is not None else None
+    res = []
+    for v in (0, 1):
+        ctx = L.lobpcg_setup(L.Op(N, 1, 1), L.Precond(None), m, L.MIXED)
+        L.lobpcg_set_option(ctx, L.OPT_KERNELS, v)
+        res.append(L.lobpcg_update(ctx, d(X), d(AX), d(W), d(AW), d(P), d(AP), C, theta, J, 12.0))
+    for a, b in zip(res[0][:5], res[1][:5]):
+        assert torch.equal(a, b)
+    np.testing.assert_allclose(res[0][5], res[1][5], rtol=1e-13)
 
 
 # ---------------------------------------------------------------- residual and norms (steps 7-8)

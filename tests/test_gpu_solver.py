@@ -350,18 +350,21 @@ def test_error_paths():
     assert r.status == L.NOT_CONVERGED and r.iters == 2
     with pytest.raises(L.LobpcgError):
         L.lobpcg_solve(ctx, dev(synth.x0_uniform(N, m)), -1.0, 10)
+    for v in (2, 3, 64, -4):        # reserved bit, out of range
+        with pytest.raises(L.LobpcgError):
+            L.lobpcg_set_option(ctx, L.OPT_KERNELS, v)
 
 
-@pytest.mark.parametrize("variant", [1, 2, 4, 8, 32])
+@pytest.mark.parametrize("variant,prec", [(4, L.FP64), (8, L.FP64), (32, L.FP64), (1, L.MIXED)])
 @pytest.mark.parametrize("m", [6, 12])
-def test_kernel_variants_give_the_same_solution(variant, m):
-    """The default multivector / Gram kernels and the other variants agree."""
+def test_kernel_variants_give_the_same_solution(variant, prec, m):
+    """The default Gram and update kernels and the other variants agree."""
     dims = (20, 18, 16)
     N = int(np.prod(dims))
     X0 = dev(synth.x0_uniform(N, m))
     res = []
     for v in (0, variant):
-        ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(3), m, L.FP64)
+        ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(3), m, prec)
         L.lobpcg_set_option(ctx, L.OPT_KERNELS, v)
         res.append(L.lobpcg_solve(ctx, X0, 1e-9, 200))
     assert res[0].status == res[1].status == L.OK
