@@ -178,12 +178,13 @@ enum {
     LOBPCG_OPT_KERNELS = 5,         /* kernel variants, 0 = default; results agree to  */
                                     /* rounding.  Bit 0: the FP32 update of steps      */
                                     /* 25-33 on the fragment kernel (register loads)   */
-                                    /* instead of the LDS-pipelined one; bit 1 is      */
-                                    /* reserved and must be 0 (ERR_ARG); bit 2: the    */
-                                    /* multi-column-tile Gram kernel also for narrow   */
-                                    /* single-block Grams; bit 3: up to four Gram      */
-                                    /* tiles per wave (default two); bit 4: the same   */
-                                    /* for FP32 blocks only; bit 5: Gram operands      */
+                                    /* instead of the LDS-pipelined one; bit 1: the    */
+                                    /* V-cycle on the active columns as stored, not    */
+                                    /* rounded up to the 16-byte vector width; bit 2:  */
+                                    /* the multi-column-tile Gram kernel also for      */
+                                    /* narrow single-block Grams; bit 3: up to four    */
+                                    /* Gram tiles per wave (default two); bit 4: the   */
+                                    /* same for FP32 blocks only; bit 5: Gram operands */
                                     /* loaded per tile group rather than staged once   */
                                     /* per row chunk through LDS (bits 3-4 apply to    */
                                     /* that kernel and to products with more operand   */

@@ -50,6 +50,30 @@ __device__ __forceinline__ vec<T, V> vload_as(const U *p)
     return r;
 }
 
+// The same at an address aligned to one element only (rows of a block whose
+// column count is not a multiple of V)
+template <typename U, int V>
+struct uvec {
+    typedef U type __attribute__((ext_vector_type(V), aligned(sizeof(U))));
+};
+template <typename T, int V, typename U>
+__device__ __forceinline__ vec<T, V> vload_as_u(const U *p)
+{
+    const typename uvec<U, V>::type a = *reinterpret_cast<const typename uvec<U, V>::type *>(p);
+    vec<T, V> r;
+#pragma unroll
+    for (int q = 0; q < V; q++) r.v[q] = (T)a[q];
+    return r;
+}
+template <typename T, int V, typename U>
+__device__ __forceinline__ void vstore_as_u(U *p, const vec<T, V> &x)
+{
+    typename uvec<U, V>::type a;
+#pragma unroll
+    for (int q = 0; q < V; q++) a[q] = (U)x.v[q];
+    *reinterpret_cast<typename uvec<U, V>::type *>(p) = a;
+}
+
 template <typename T, int V, typename U>
 __device__ __forceinline__ void vstore_nt_as(U *p, const vec<T, V> &x)
 {
@@ -59,9 +83,11 @@ __device__ __forceinline__ void vstore_nt_as(U *p, const vec<T, V> &x)
     vstore_nt<U, V>(p, a);
 }
 
-template <typename T, int V, typename TU = T>
-__device__ __forceinline__ void x_neighbours(const vec<T, V> &cur, const TU *__restrict__ u, i64 i, i64 sx,
-                                             int x, int nx, int L, bool row_ok, vec<T, V> &xm, vec<T, V> &xp)
+// The x-1 / x+1 neighbours of lane-edge items come from ldu(i -/+ sx): the
+// loader of the kernel's input layout.
+template <typename T, int V, typename LD>
+__device__ __forceinline__ void x_neighbours(const vec<T, V> &cur, const LD &ldu, i64 i, i64 sx, int x, int nx,
+                                             int L, bool row_ok, vec<T, V> &xm, vec<T, V> &xp)
 {
     const int lane = threadIdx.x & 63;
     const bool in_m = lane >= L, in_p = lane + L < 64;
@@ -73,9 +99,9 @@ __device__ __forceinline__ void x_neighbours(const vec<T, V> &cur, const TU *__r
     // a row outside the grid (only the last rows of a thread's row block)
     // has no neighbours to load: its results are not stored
     if (x == 0 || !row_ok) xm = vzero<T, V>();
-    else if (!in_m) xm = vload_as<T, V>(u + i - sx);
+    else if (!in_m) xm = ldu(i - sx);
     if (x + 1 == nx || !row_ok) xp = vzero<T, V>();
-    else if (!in_p) xp = vload_as<T, V>(u + i + sx);
+    else if (!in_p) xp = ldu(i + sx);
 }
 
 // EPI_APPLY : out = s * L7 u
@@ -88,11 +114,15 @@ __device__ __forceinline__ void x_neighbours(const vec<T, V> &cur, const TU *__r
 // The arithmetic is in T.  u may be stored as TU and out as TO (FP64 blocks
 // around an FP32 multigrid: the first sweep reads the FP64 right-hand side
 // and, when ucopy is given, writes its FP32 copy for the later kernels of
-// the cycle; the last sweep writes the FP64 result).
-template <typename T, int V, int EPI, int R, typename TU = T, typename TO = T>
+// the cycle; the last sweep writes the FP64 result).  CIN / COUT: u / out
+// are stored with kc <= L V columns per point (a block whose column count is
+// not a multiple of V, run through a cycle on L V columns: the columns past
+// kc read as zero and are not stored).
+template <typename T, int V, int EPI, int R, typename TU = T, typename TO = T, bool CIN = false, bool COUT = false>
 __global__ void __launch_bounds__(256) stencil7_kernel(int nx, int ny, int nz, int L, int zchunk,
                                                        const TU *__restrict__ u, TO *__restrict__ out,
-                                                       const T *__restrict__ b, T s, T c1, T *__restrict__ ucopy)
+                                                       const T *__restrict__ b, T s, T c1, T *__restrict__ ucopy,
+                                                       int kc)
 {
     const unsigned nbx = gridDim.x;
     const unsigned bx = xcd_remap(blockIdx.x, nbx);
@@ -112,6 +142,39 @@ __global__ void __launch_bounds__(256) stencil7_kernel(int nx, int ny, int nz, i
     const i64 sx = (i64)L * V, sy = (i64)nx * L * V, sz = (i64)nx * ny * L * V;   // element strides
     const i64 base = (((i64)y0 * nx + x) * L + c) * V;                           // row y0
     const vec<T, V> zero = vzero<T, V>();
+    // u's layout (kc columns per point with CIN) and its loader
+    const i64 ku = CIN ? (i64)kc : sx;
+    const i64 sxu = ku, syu = (i64)nx * ku, szu = (i64)nx * ny * ku;
+    const i64 baseu = ((i64)y0 * nx + x) * ku + (i64)c * V;
+    const bool whole = !(CIN || COUT) || c * V + V <= kc;   // this thread's chunk lies inside the stored row
+    auto ldu = [&](i64 iu) -> vec<T, V> {
+        if constexpr (CIN) {
+            if (whole) return vload_as_u<T, V>(u + iu);
+            vec<T, V> r;
+#pragma unroll
+            for (int q = 0; q < V; q++) r.v[q] = c * V + q < kc ? (T)u[iu + q] : T(0);
+            return r;
+        } else {
+            return vload_as<T, V>(u + iu);
+        }
+    };
+    // out's layout (kc columns per point with COUT)
+    const i64 ko = COUT ? (i64)kc : sx;
+    const i64 syo = (i64)nx * ko, szo = (i64)nx * ny * ko;
+    const i64 baseo = ((i64)y0 * nx + x) * ko + (i64)c * V;
+    auto sto = [&](i64 io, const vec<T, V> &o) {
+        if constexpr (COUT) {
+            if (whole) {
+                vstore_as_u<T, V>(out + io, o);
+            } else {
+#pragma unroll
+                for (int q = 0; q < V; q++)
+                    if (c * V + q < kc) out[io + q] = (TO)o.v[q];
+            }
+        } else {
+            vstore_nt_as<T, V>(out + io, o);
+        }
+    };
     // rows y0 .. y0+R-1 (those inside the grid) marched in z together: the
     // y-neighbours between them come from registers, only rows y0-1 and
     // y0+R are loaded
@@ -120,22 +183,22 @@ __global__ void __launch_bounds__(256) stencil7_kernel(int nx, int ny, int nz, i
 #pragma unroll
     for (int r = 0; r < R; r++) {
         rok[r] = y0 + r < ny;
-        const i64 br = base + r * sy;
-        prev[r] = (rok[r] && z0 > 0) ? vload_as<T, V>(u + br + (z0 - 1) * sz) : zero;
-        cur[r] = rok[r] ? vload_as<T, V>(u + br + z0 * sz) : zero;
+        const i64 br = baseu + r * syu;
+        prev[r] = (rok[r] && z0 > 0) ? ldu(br + (z0 - 1) * szu) : zero;
+        cur[r] = rok[r] ? ldu(br + z0 * szu) : zero;
     }
     for (int z = z0; z < z1; z++) {
-        const i64 i = base + z * sz;
+        const i64 i = base + z * sz, iu = baseu + z * szu, io = baseo + z * szo;
         vec<T, V> next[R];
 #pragma unroll
-        for (int r = 0; r < R; r++) next[r] = (rok[r] && z + 1 < nz) ? vload_as<T, V>(u + i + r * sy + sz) : zero;
-        const vec<T, V> ybelow = y0 > 0 ? vload_as<T, V>(u + i - sy) : zero;
-        const vec<T, V> yabove = (y0 + R < ny) ? vload_as<T, V>(u + i + R * sy) : zero;
+        for (int r = 0; r < R; r++) next[r] = (rok[r] && z + 1 < nz) ? ldu(iu + r * syu + szu) : zero;
+        const vec<T, V> ybelow = y0 > 0 ? ldu(iu - syu) : zero;
+        const vec<T, V> yabove = (y0 + R < ny) ? ldu(iu + R * syu) : zero;
 #pragma unroll
         for (int r = 0; r < R; r++) {
             const i64 ir = i + r * sy;
             vec<T, V> xm, xp;
-            x_neighbours<T, V, TU>(cur[r], u, ir, sx, x, nx, L, rok[r], xm, xp);
+            x_neighbours<T, V>(cur[r], ldu, iu + r * syu, sxu, x, nx, L, rok[r], xm, xp);
             if (ucopy && active && rok[r]) vstore<T, V>(ucopy + ir, cur[r]);
             const vec<T, V> ym = r == 0 ? ybelow : cur[r - 1];
             const vec<T, V> yp = r == R - 1 ? yabove : cur[r + 1];
@@ -145,7 +208,7 @@ __global__ void __launch_bounds__(256) stencil7_kernel(int nx, int ny, int nz, i
                 for (int q = 0; q < V; q++)
                     o.v[q] = c1 * cur[r].v[q] +
                              s * (prev[r].v[q] + next[r].v[q] + xm.v[q] + xp.v[q] + ym.v[q] + yp.v[q]);
-                if (active && rok[r]) vstore_nt_as<T, V>(out + ir, o);
+                if (active && rok[r]) sto(io + r * syo, o);
                 continue;
             }
             vec<T, V> au = lap<T, V>(cur[r], prev[r], next[r], xm, xp, ym, yp);
@@ -163,7 +226,7 @@ __global__ void __launch_bounds__(256) stencil7_kernel(int nx, int ny, int nz, i
                     o.v[q] = (EPI == EPI_JACOBI) ? cur[r].v[q] + c1 * rr : rr;
                 }
             }
-            if (active && rok[r]) vstore_nt_as<T, V>(out + ir, o);
+            if (active && rok[r]) sto(io + r * syo, o);
         }
 #pragma unroll
         for (int r = 0; r < R; r++) {
@@ -202,7 +265,7 @@ __global__ void __launch_bounds__(256) varcoef7_kernel(int nx, int ny, int nz, i
         const i64 i = base + z * sz;
         vec<T, V> next = (z + 1 < nz) ? vload<T, V>(u + i + sz) : zero;
         vec<T, V> xm, xp;
-        x_neighbours<T, V>(cur, u, i, sx, x, nx, L, true, xm, xp);
+        x_neighbours<T, V>(cur, [&](i64 j) { return vload<T, V>(u + j); }, i, sx, x, nx, L, true, xm, xp);
         vec<T, V> ym = y > 0 ? vload<T, V>(u + i - sy) : zero;
         vec<T, V> yp = y + 1 < ny ? vload<T, V>(u + i + sy) : zero;
         const i64 fxi = ((i64)z * ny + y) * (nx + 1) + x;
@@ -266,7 +329,7 @@ static hipError_t run_stencil(const Grid3 &g, int k, const void *u, void *out, c
         constexpr int R = decltype(Rc)::value;
         geometry(g.nx, (g.ny + R - 1) / R, g.nz, L, grid, zchunk, zmin);
         hipLaunchKernelGGL((stencil7_kernel<T, V, EPI, R>), grid, dim3(256), 0, st, g.nx, g.ny, g.nz, L, zchunk,
-                           (const T *)u, (T *)out, (const T *)b, (T)s, (T)c1, (T *)nullptr);
+                           (const T *)u, (T *)out, (const T *)b, (T)s, (T)c1, (T *)nullptr, 0);
     };
     if (sizeof(T) == 8) {
         if (product && k < 16) launch(std::integral_constant<int, 2>(), 8192);
@@ -338,41 +401,78 @@ hipError_t launch_resid7(int dtype, const Grid3 &g, int k, const void *x, const 
     return dispatch_epi<double>(EPI_RESID, g, k, x, out, b, s, 0.0, st);
 }
 
-// FP32 sweeps at the edges of an FP32 cycle on FP64 blocks (one row per
-// thread, as the FP32 sweeps above)
-template <int V, int EPI, typename TU, typename TO>
-static hipError_t run_sweep_cast(const Grid3 &g, int k, const void *u, void *out, const void *b, float *ucopy,
+// The first and last sweeps of a cycle whose blocks differ from the cycle's
+// (precision T, k = L V columns per point): the right-hand side u is read
+// as stored (type TU, kc <= k columns) and its copy in the cycle's layout
+// written to ucopy; the result is written as stored (type TO, kc columns).
+// Shapes of the sweeps above: one row per thread for FP32, four for FP64.
+template <typename T, int V, int EPI, typename TU, typename TO, bool CIN, bool COUT>
+static hipError_t run_edge_sweep(const Grid3 &g, int kc, int k, const void *u, void *out, const void *b, T *ucopy,
                                  double s, double c1, hipStream_t st)
 {
     const int L = k / V;
+    constexpr int R = sizeof(T) == 4 ? 1 : 4;
     dim3 grid;
     int zchunk;
-    geometry(g.nx, g.ny, g.nz, L, grid, zchunk);
-    hipLaunchKernelGGL((stencil7_kernel<float, V, EPI, 1, TU, TO>), grid, dim3(256), 0, st, g.nx, g.ny, g.nz, L,
-                       zchunk, (const TU *)u, (TO *)out, (const float *)b, (float)s, (float)c1, ucopy);
+    geometry(g.nx, (g.ny + R - 1) / R, g.nz, L, grid, zchunk, sizeof(T) == 4 ? 2048 : 8192);
+    hipLaunchKernelGGL((stencil7_kernel<T, V, EPI, R, TU, TO, CIN, COUT>), grid, dim3(256), 0, st, g.nx, g.ny, g.nz,
+                       L, zchunk, (const TU *)u, (TO *)out, (const T *)b, (T)s, (T)c1, ucopy, kc);
     return hipGetLastError();
 }
 
-hipError_t launch_jacobi2_zero_from64(const Grid3 &g, int k, const double *b64, float *x, float *b32, double s,
-                                      double omega, hipStream_t st)
+// V for a cycle on k columns of T: the widest 16-byte vector that divides k
+template <typename T, int EPI, typename TU, typename TO, bool CIN, bool COUT>
+static hipError_t edge_sweep_v(const Grid3 &g, int kc, int k, const void *u, void *out, const void *b, T *ucopy,
+                               double s, double c1, hipStream_t st)
 {
-    const double c1 = omega / (6.0 * s);
-    switch (pick_vec<float>(k)) {
-    case 4: return run_sweep_cast<4, EPI_JACOBI2, double, float>(g, k, b64, x, nullptr, b32, s, c1, st);
-    case 2: return run_sweep_cast<2, EPI_JACOBI2, double, float>(g, k, b64, x, nullptr, b32, s, c1, st);
-    default: return run_sweep_cast<1, EPI_JACOBI2, double, float>(g, k, b64, x, nullptr, b32, s, c1, st);
+    if constexpr (sizeof(T) == 4) {
+        switch (pick_vec<T>(k)) {
+        case 4: return run_edge_sweep<T, 4, EPI, TU, TO, CIN, COUT>(g, kc, k, u, out, b, ucopy, s, c1, st);
+        case 2: return run_edge_sweep<T, 2, EPI, TU, TO, CIN, COUT>(g, kc, k, u, out, b, ucopy, s, c1, st);
+        default: return run_edge_sweep<T, 1, EPI, TU, TO, CIN, COUT>(g, kc, k, u, out, b, ucopy, s, c1, st);
+        }
+    } else {
+        if (pick_vec<T>(k) == 2) return run_edge_sweep<T, 2, EPI, TU, TO, CIN, COUT>(g, kc, k, u, out, b, ucopy, s, c1, st);
+        return run_edge_sweep<T, 1, EPI, TU, TO, CIN, COUT>(g, kc, k, u, out, b, ucopy, s, c1, st);
     }
 }
 
-hipError_t launch_jacobi_to64(const Grid3 &g, int k, const float *x, const float *b, double *out, double s,
-                              double omega, hipStream_t st)
+hipError_t launch_jacobi2_zero_in(int dt_in, int dtype, const Grid3 &g, int kc, int k, const void *bsrc, void *x,
+                                  void *bcopy, double s, double omega, hipStream_t st)
 {
+    if (kc < 1 || kc > k) return hipErrorInvalidValue;
     const double c1 = omega / (6.0 * s);
-    switch (pick_vec<float>(k)) {
-    case 4: return run_sweep_cast<4, EPI_JACOBI, float, double>(g, k, x, out, b, nullptr, s, c1, st);
-    case 2: return run_sweep_cast<2, EPI_JACOBI, float, double>(g, k, x, out, b, nullptr, s, c1, st);
-    default: return run_sweep_cast<1, EPI_JACOBI, float, double>(g, k, x, out, b, nullptr, s, c1, st);
+    const bool cin = kc < k;
+    if (dtype == DT_F32) {
+        float *bc = (float *)bcopy;
+        if (dt_in == DT_F64)
+            return cin ? edge_sweep_v<float, EPI_JACOBI2, double, float, true, false>(g, kc, k, bsrc, x, nullptr, bc, s, c1, st)
+                       : edge_sweep_v<float, EPI_JACOBI2, double, float, false, false>(g, kc, k, bsrc, x, nullptr, bc, s, c1, st);
+        return cin ? edge_sweep_v<float, EPI_JACOBI2, float, float, true, false>(g, kc, k, bsrc, x, nullptr, bc, s, c1, st)
+                   : edge_sweep_v<float, EPI_JACOBI2, float, float, false, false>(g, kc, k, bsrc, x, nullptr, bc, s, c1, st);
     }
+    if (dt_in != DT_F64) return hipErrorInvalidValue;
+    double *bc = (double *)bcopy;
+    return cin ? edge_sweep_v<double, EPI_JACOBI2, double, double, true, false>(g, kc, k, bsrc, x, nullptr, bc, s, c1, st)
+               : edge_sweep_v<double, EPI_JACOBI2, double, double, false, false>(g, kc, k, bsrc, x, nullptr, bc, s, c1, st);
+}
+
+hipError_t launch_jacobi_out(int dtype, int dt_out, const Grid3 &g, int kc, int k, const void *x, const void *b,
+                             void *out, double s, double omega, hipStream_t st)
+{
+    if (kc < 1 || kc > k) return hipErrorInvalidValue;
+    const double c1 = omega / (6.0 * s);
+    const bool cout = kc < k;
+    if (dtype == DT_F32) {
+        if (dt_out == DT_F64)
+            return cout ? edge_sweep_v<float, EPI_JACOBI, float, double, false, true>(g, kc, k, x, out, b, nullptr, s, c1, st)
+                        : edge_sweep_v<float, EPI_JACOBI, float, double, false, false>(g, kc, k, x, out, b, nullptr, s, c1, st);
+        return cout ? edge_sweep_v<float, EPI_JACOBI, float, float, false, true>(g, kc, k, x, out, b, nullptr, s, c1, st)
+                    : edge_sweep_v<float, EPI_JACOBI, float, float, false, false>(g, kc, k, x, out, b, nullptr, s, c1, st);
+    }
+    if (dt_out != DT_F64) return hipErrorInvalidValue;
+    return cout ? edge_sweep_v<double, EPI_JACOBI, double, double, false, true>(g, kc, k, x, out, b, nullptr, s, c1, st)
+                : edge_sweep_v<double, EPI_JACOBI, double, double, false, false>(g, kc, k, x, out, b, nullptr, s, c1, st);
 }
 
 template <typename T, int V>

@@ -26,13 +26,17 @@ hipError_t launch_jacobi(int dtype, const Grid3 &g, int k, const void *x, const 
 // out = two weighted-Jacobi sweeps on s*L7 from x = 0 with right-hand side b
 hipError_t launch_jacobi2_zero(int dtype, const Grid3 &g, int k, const void *b, void *out, double s, double omega,
                                hipStream_t st);
-// The same two sweeps on an FP32 cycle whose right-hand side is an FP64
-// block: b64 is read once, x (FP32) written, and b32 receives b64 in FP32
-hipError_t launch_jacobi2_zero_from64(const Grid3 &g, int k, const double *b64, float *x, float *b32, double s,
-                                      double omega, hipStream_t st);
-// One FP32 sweep (as launch_jacobi) that writes its result as FP64
-hipError_t launch_jacobi_to64(const Grid3 &g, int k, const float *x, const float *b, double *out, double s,
-                              double omega, hipStream_t st);
+// The first and last sweeps of a cycle (precision dtype, k columns per
+// point) on a block stored differently: as FP64 around an FP32 cycle, or
+// with kc < k columns (k rounded up to the cycle's vector width; the columns
+// past kc are zero in the cycle).  The two sweeps from zero read the
+// right-hand side bsrc (dt_in, kc columns) once, write x and the
+// right-hand side's copy bcopy in the cycle's layout; the sweep of
+// launch_jacobi writes its result to out (dt_out, kc columns).
+hipError_t launch_jacobi2_zero_in(int dt_in, int dtype, const Grid3 &g, int kc, int k, const void *bsrc, void *x,
+                                  void *bcopy, double s, double omega, hipStream_t st);
+hipError_t launch_jacobi_out(int dtype, int dt_out, const Grid3 &g, int kc, int k, const void *x, const void *b,
+                             void *out, double s, double omega, hipStream_t st);
 // out = b - s L7 x
 hipError_t launch_resid7(int dtype, const Grid3 &g, int k, const void *x, const void *b, void *out, double s,
                          hipStream_t st);

@@ -175,7 +175,7 @@ struct lobpcg_ctx {
     bool profile, reactivate;
     double lock_gap;              // soft locking keeps a converged column active while an unconverged
                                   // one has a Ritz value within this relative distance (0: off)
-    int mv_frag, gram_staged, gram_nt4, gram_nt32, gram_direct;  // kernel variants (see LOBPCG_OPT_KERNELS)
+    int mv_frag, mg_unpadded, gram_staged, gram_nt4, gram_nt32, gram_direct;  // kernel variants (see LOBPCG_OPT_KERNELS)
     bool fp32_explicit;           // FP32 phase: Gram diagonal blocks computed, not assumed
     bool fp64_explicit;           // the same for FP64 iterations
     bool fold;                    // Cholesky-QR factors of W_J, P_J folded into Gram and coefficients
@@ -706,14 +706,27 @@ int residual(lobpcg_ctx *c, int dt, const void *X, const void *AX, const std::ve
     return LOBPCG_OK;
 }
 
+// The fine-level blocks of a V-cycle when they are stored differently from
+// the cycle: FP64 blocks around an FP32 cycle (the FP64 phase of the mixed
+// solver), or kc columns where the cycle runs on kc rounded up to its vector
+// width (the extra columns are zero throughout and never stored).
+struct CycleEdge {
+    const void *src = nullptr;   // right-hand side as stored (type dt_src, kc columns)
+    int dt_src = 0;
+    void *dst = nullptr;         // T b as stored (type dt_dst, kc columns) ...
+    bool dst_other = false;      // ... or in the fine-level buffer the last sweep does not read
+    int dt_dst = 0;
+    int kc = 0;
+};
+
 // V-cycle on N x k blocks of the multigrid precision.  b: right-hand side at
 // level l; xa, xb: two buffers of that level; returns the buffer holding T b.
-// FP64 blocks around an FP32 cycle (the FP64 phase of the mixed solver):
-// with b64 given, the fine level's first sweep reads the FP64 right-hand
-// side and writes its FP32 copy into b (then used by the rest of the cycle),
-// and with out64 given the last sweep writes T b there in FP64 (returned).
+// With an edge, the fine level's first sweeps read the right-hand side from
+// edge->src and write the cycle's copy of it into b (then used by the rest
+// of the cycle), and the last sweep writes T b to the edge's destination
+// (returned).
 void *vcycle(lobpcg_ctx *c, int l, const void *b, void *xa, void *xb, int k, hipError_t &err,
-             const double *b64 = nullptr, double *out64 = nullptr)
+             const CycleEdge *edge = nullptr)
 {
     const int dt = c->L.mg_dtype;
     const Grid3 &g = c->L.levels[l];
@@ -743,15 +756,17 @@ void *vcycle(lobpcg_ctx *c, int l, const void *b, void *xa, void *xb, int k, hip
     }
     void *cur = xa, *oth = xb;
     int pre = 1;
-    if (b64 && c->T.nu_pre >= 2) {
-        // reads the FP64 right-hand side once, writes x and the FP32 copy
-        chk(launch_jacobi2_zero_from64(g, k, b64, (float *)cur, (float *)b, s, om, c->st));
+    const bool src = edge && edge->src;
+    if (src && c->T.nu_pre >= 2) {
+        // reads the right-hand side as stored once, writes x and the cycle's copy
+        chk(launch_jacobi2_zero_in(edge->dt_src, dt, g, edge->kc, k, edge->src, cur, (void *)b, s, om, c->st));
         pre = 2;
-        passes(4.0);
+        add_bytes(c, LOBPCG_STEP_PRECOND, (double)g.n() * (edge->kc * esize(edge->dt_src) + 2.0 * k * esize(dt)));
     } else {
-        if (b64) {
-            chk(launch_cast(DT_F64, DT_F32, g.n() * k, b64, (void *)b, c->st));
-            passes(3.0);
+        if (src) {
+            // (edges with kc < k need the two sweeps above)
+            chk(launch_cast(edge->dt_src, dt, g.n() * k, edge->src, (void *)b, c->st));
+            passes(1.0 + (double)esize(edge->dt_src) / esize(dt));
         }
         if (c->T.nu_pre >= 2) {
             chk(launch_jacobi2_zero(dt, g, k, b, cur, s, om, c->st));
@@ -775,43 +790,77 @@ void *vcycle(lobpcg_ctx *c, int l, const void *b, void *xa, void *xb, int k, hip
     void *e = vcycle(c, l + 1, bc, xc, tc, k, err);
     chk(launch_prolong_add(dt, g, gc, k, e, cur, c->st));
     passes(2.0 + ratio);
+    const bool dst = edge && (edge->dst || edge->dst_other);
     for (int i = 0; i < c->T.nu_post; i++) {
-        if (out64 && i + 1 == c->T.nu_post) {
-            // the last sweep writes the FP64 result
-            chk(launch_jacobi_to64(g, k, (const float *)cur, (const float *)b, out64, s, om, c->st));
-            passes(4.0);
-            return out64;
+        if (dst && i + 1 == c->T.nu_post) {
+            // the last sweep writes the result as stored
+            void *to = edge->dst_other ? oth : edge->dst;
+            chk(launch_jacobi_out(dt, edge->dt_dst, g, edge->kc, k, cur, b, to, s, om, c->st));
+            add_bytes(c, LOBPCG_STEP_PRECOND, (double)g.n() * (2.0 * k * esize(dt) + edge->kc * esize(edge->dt_dst)));
+            return to;
         }
         chk(launch_jacobi(dt, g, k, cur, b, oth, s, om, c->st));
         passes(3.0);
         std::swap(cur, oth);
     }
-    if (out64) {
-        chk(launch_cast(DT_F32, DT_F64, g.n() * k, cur, out64, c->st));
-        passes(3.0);
-        return out64;
+    if (dst) {
+        // (edges with kc < k need a post-smoothing sweep)
+        void *to = edge->dst_other ? oth : edge->dst;
+        chk(launch_cast(dt, edge->dt_dst, g.n() * k, cur, to, c->st));
+        passes(1.0 + (double)esize(edge->dt_dst) / esize(dt));
+        return to;
     }
     return cur;
 }
 
 // T applied to the N x k block `in` (precision dt); result in one of the two
 // fine-level buffers fa / fb of precision dt, returned.  In the FP64 phase of
-// the mixed solver the FP32 multigrid runs on a down-cast copy.
-int apply_T(lobpcg_ctx *c, int dt, const void *in, void *fa, void *fb, int k, void **result)
+// the mixed solver the FP32 multigrid runs on a down-cast copy.  An FP32
+// cycle on k >= 3 columns, k not a multiple of 4, runs on k rounded up to a
+// multiple of 4 (kp), so that every kernel moves 16-byte vectors: kernels on
+// such counts move 4 or 8 bytes per lane and measured up to 1.25x slower
+// per cycle at 256^3 (31 columns: 11.2 -> 9.4 ms rounded up, 13: 5.4 ->
+// 4.5 ms); the extra columns are zero and cost kp/k of the traffic, which
+// does not pay for 1 or 2 columns, nor for FP64 cycles (2 columns per 16
+// bytes: no faster).  This needs the buffers to hold kp <= m columns, pre-
+// and post-smoothing, and a free block `scratch` (N x m of precision dt)
+// for the right-hand side's copy.
+int apply_T(lobpcg_ctx *c, int dt, const void *in, void *fa, void *fb, int k, void **result, void *scratch)
 {
     prof_begin(c, LOBPCG_STEP_PRECOND);
     hipError_t err = hipSuccess;
     const int mdt = c->L.mg_dtype;
+    const int vw = 16 / (int)esize(mdt);
+    const int kp = (k + vw - 1) / vw * vw;
+    const bool multi = c->L.levels.size() > 1;
+    const bool pad = kp != k && k >= 3 && mdt == DT_F32 && kp <= c->m && multi && c->T.nu_pre >= 2 &&
+                     c->T.nu_post >= 1 && !c->mg_unpadded;
     if (dt == mdt) {
-        *result = vcycle(c, 0, in, fa, fb, k, err);
+        if (pad && scratch) {
+            CycleEdge e;
+            e.src = in;
+            e.dt_src = dt;
+            e.dst_other = true;
+            e.dt_dst = dt;
+            e.kc = k;
+            *result = vcycle(c, 0, scratch, fa, fb, kp, err, &e);
+        } else {
+            *result = vcycle(c, 0, in, fa, fb, k, err);
+        }
     } else {
         // mixed solver, FP64 phase: b32 buffers are free; T in FP32 on FP64
         // blocks, the precision changes taken in the cycle's first and last
         // sweeps (a one-level cycle only: casts around it)
         const long long n = c->N * k;
         void *bin = c->b32.W, *xa = c->b32.AW, *xb = c->b32.T0;
-        if (c->L.levels.size() > 1) {
-            *result = vcycle(c, 0, bin, xa, xb, k, err, (const double *)in, (double *)fa);
+        if (multi) {
+            CycleEdge e;
+            e.src = in;
+            e.dt_src = dt;
+            e.dst = fa;
+            e.dt_dst = dt;
+            e.kc = k;
+            *result = vcycle(c, 0, bin, xa, xb, pad ? kp : k, err, &e);
         } else {
             if (launch_cast(dt, mdt, n, in, bin, c->st) != hipSuccess) err = hipErrorUnknown;
             void *r = vcycle(c, 0, bin, xa, xb, k, err);
@@ -1307,7 +1356,7 @@ int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &
         // step 9: W_J = T W_J
         void *Wt = B.W;
         if (c->mg) {
-            s = apply_T(c, dt, B.W, B.AW, B.T0, nJ, &Wt);
+            s = apply_T(c, dt, B.W, B.AW, B.T0, nJ, &Wt, B.X[1 - ps.cur]);
             if (s) return s;
         }
         // step 10: W_J = W_J - Y (Y^T Y)^-1 (Y^T W_J)
@@ -1680,6 +1729,7 @@ int lobpcg_setup(lobpcg_ctx **out, const lobpcg_op *A, const lobpcg_op *B, const
     c->reactivate = true;
     c->lock_gap = 0.0;
     c->mv_frag = 0;
+    c->mg_unpadded = 0;
     c->gram_staged = 0;
     c->gram_nt4 = 0;
     c->gram_nt32 = 2;
@@ -1737,8 +1787,9 @@ int lobpcg_set_option(lobpcg_ctx *c, int key, double v)
     case LOBPCG_OPT_FOLD_CHOLQR: c->fold = v != 0; return LOBPCG_OK;
     case LOBPCG_OPT_FP64_EXPLICIT_GRAM: c->fp64_explicit = v != 0; return LOBPCG_OK;
     case LOBPCG_OPT_KERNELS:
-        if (v < 0 || v > 63 || ((int)v & 2) != 0) return LOBPCG_ERR_ARG;
+        if (v < 0 || v > 63) return LOBPCG_ERR_ARG;
         c->mv_frag = ((int)v & 1) != 0;
+        c->mg_unpadded = ((int)v & 2) != 0;
         c->gram_staged = ((int)v & 4) != 0;
         c->gram_nt4 = ((int)v & 8) != 0;
         c->gram_nt32 = ((int)v & 16) ? 4 : 2;
@@ -1980,7 +2031,7 @@ int lobpcg_apply_T(lobpcg_ctx *c, int dt, const void *in, void *out, int k)
     }
     Blocks &B = d == DT_F32 ? c->b32 : c->b64;
     void *r = nullptr;
-    int s = apply_T(c, d, in, B.AW, B.T0, k, &r);
+    int s = apply_T(c, d, in, B.AW, B.T0, k, &r, B.X[1]);
     if (s) return s;
     HIPCHK(hipMemcpyAsync(out, r, bytes, hipMemcpyDeviceToDevice, c->st));
     return sync(c);

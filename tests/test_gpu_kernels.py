@@ -128,6 +128,32 @@ def test_vcycle_fp32(dims, levels, k):
     np.testing.assert_allclose(out, ref, rtol=0, atol=2e-5 * np.abs(ref).max())
 
 
+# An FP32 cycle on 3 or more columns, not a multiple of 4, runs on the count
+# rounded up to a multiple of 4 (the extra columns zero); each column's
+# arithmetic is the same either way, so the results are identical to the
+# cycle on the columns as stored (kernel variant bit 1).  FP64 blocks in a
+# mixed context take the FP32 cycle with the precision changes in its first
+# and last sweeps; FP64 cycles and 1-2 columns are not rounded up.
+@pytest.mark.parametrize("prec,blk", [(L.FP64, torch.float64), (L.MIXED, torch.float32),
+                                      (L.MIXED, torch.float64)])
+@pytest.mark.parametrize("k", [1, 3, 5, 7, 21, 23])
+def test_vcycle_rounded_up_columns(prec, blk, k):
+    dims, levels = (26, 19, 21), 3
+    N = int(np.prod(dims))
+    B = synth.random_block(N, k, seed=16 + k)
+    if blk == torch.float32:
+        B = B.astype(np.float32)
+    outs = []
+    for v in (0, 2):
+        ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(levels), 24, prec)
+        L.lobpcg_set_option(ctx, L.OPT_KERNELS, v)
+        outs.append(L.lobpcg_apply_T(ctx, dev(B, blk)))
+    assert torch.equal(outs[0], outs[1])
+    ref = mg.VCycle(dims, levels)(B.astype(np.float64))
+    tol = 1e-13 if prec == L.FP64 else 2e-5
+    np.testing.assert_allclose(host(outs[0]), ref, rtol=0, atol=tol * np.abs(ref).max())
+
+
 def test_vcycle_large_coarsest_grid_uses_global_sweeps():
     """A coarsest level too big for one workgroup's LDS (20^3 > 2048 points)."""
     dims, levels, k = (40, 40, 40), 2, 3
