@@ -54,7 +54,9 @@ def test_laplace7_fp64(dims, k):
     np.testing.assert_allclose(out, ref, rtol=0, atol=1e-14 * 12)
 
 
-@pytest.mark.parametrize("dims,k", [((16, 16, 16), 32), ((13, 11, 9), 5), ((40, 7, 5), 8), ((9, 9, 9), 2)])
+# column counts that are and are not multiples of the 16-byte vector width
+@pytest.mark.parametrize("dims,k", [((16, 16, 16), 32), ((13, 11, 9), 5), ((40, 7, 5), 8), ((9, 9, 9), 2),
+                                    ((17, 15, 13), 23), ((16, 9, 11), 31), ((8, 8, 8), 3), ((13, 11, 9), 7)])
 def test_laplace7_fp32(dims, k):
     N = int(np.prod(dims))
     ctx = ctx_for(dims, min(32, N // 3), prec=L.MIXED)
