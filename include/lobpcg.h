@@ -272,16 +272,19 @@ int lobpcg_combine(lobpcg_ctx *ctx, int dtype, int n, const void *const *d_in, c
  *   P'  = W C_W + P C_P,    AP' = AW C_W + AP C_P       (step 27-30 form)
  *   X'  = X C_X + P',       AX' = AX C_X + AP'          (steps 31-33)
  *   W'  = AX'_j - theta_j X'_j for j in J               (step 7)
- * for d_X, d_AX (N x m), d_W, d_AW (N x nW), d_P, d_AP (N x nP; nP = 0 drops
- * the P terms and they may be NULL).  d_Xn, d_AXn (N x m) receive X', AX';
+ * for d_X, d_AX (N x m), d_W, d_AW (N x nW), and P, AP: the columns
+ * h_Pcols[0..nP) of d_P, d_AP (N x ldP), or with h_Pcols NULL all of them
+ * (ldP = nP); nP = 0 drops the P terms (d_P, d_AP may then be NULL).  d_Xn,
+ * d_AXn (N x m) receive X', AX';
  * d_Pn, d_APn, d_Wn (N x nJ) receive the columns h_J[0..nJ) of P', AP', W'
  * packed (column jj = column h_J[jj]); h_rho[j] = ||AX'_j - theta_j X'_j|| /
  * (norm_A ||X'_j||) for all m columns.  Outputs must not alias inputs
- * (ARG).  1 <= nW, nJ <= m, 0 <= nP <= m, h_J distinct in [0, m). */
+ * (ARG).  1 <= nW, nJ <= m, 0 <= nP <= m, nP <= ldP <= m, h_J distinct in
+ * [0, m), h_Pcols in [0, ldP). */
 int lobpcg_update(lobpcg_ctx *ctx, int dtype, const void *d_X, const void *d_AX, const void *d_W,
-                  const void *d_AW, int nW, const void *d_P, const void *d_AP, int nP, const double *h_C,
-                  const double *h_theta, const int *h_J, int nJ, double norm_A, void *d_Xn, void *d_AXn,
-                  void *d_Pn, void *d_APn, void *d_Wn, double *h_rho);
+                  const void *d_AW, int nW, const void *d_P, const void *d_AP, int ldP, const int *h_Pcols, int nP,
+                  const double *h_C, const double *h_theta, const int *h_J, int nJ, double norm_A, void *d_Xn,
+                  void *d_AXn, void *d_Pn, void *d_APn, void *d_Wn, double *h_rho);
 
 /* Step 7 and the norms of step 8: for the m columns of d_X, d_AX (N x m)
  * and Ritz values h_lambda, writes W_J = AX_J - X_J Lambda_J packed as

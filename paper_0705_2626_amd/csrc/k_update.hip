@@ -395,8 +395,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
 // ---------------------------------------------------------------- LDS-pipelined update (FP32)
 //
 // The fused update of steps 25-33 and 7 for FP32 blocks (mvf_kernel's case
-// with X', AX', the residual and two or three inputs of at most 32 columns
-// without column lists) with its inputs moved by the buffer loads' LDS path:
+// with X', AX', the residual and two or three inputs of at most 32 stored
+// columns; an input given by a column list is loaded whole and its columns
+// picked in LDS) with its inputs moved by the buffer loads' LDS path:
 // global memory straight into LDS, no registers held while in flight.  Each
 // wave walks its 16-point groups one side at a time (side 0: X, W, P; side
 // 1: AX, AW, AP) and keeps the loads of the next two sides in flight in a
@@ -453,6 +454,7 @@ __device__ __forceinline__ void mvl_wait_lds() { asm volatile("s_waitcnt lgkmcnt
 
 static const int MVL_SLOT = 16 * 32;   // floats of one input's 16 rows (at most 32 columns)
 static const int MVL_ST0 = 10;         // store instructions per side: P (8) and X' (2)
+static const int MVL_CMAP = 128;       // column-list entries (3 inputs of at most 32 columns, 16-byte multiple)
 static const int MVL_ST1 = 18;         // AP (8), W (8) and AX' (2)
 
 template <int NIN>
@@ -468,7 +470,7 @@ __global__ void __launch_bounds__(256) mvl_kernel(MVDev<float> a)
     int nsteps = 0, roff = 0;
 #pragma unroll
     for (int b = 0; b < NIN; b++) {
-        k4[b] = mvf_k4(a.k[b], a.ld[b], false, 4);
+        k4[b] = mvf_k4(a.k[b], a.ld[b], a.cols[b] != nullptr, 4);
         soff[b] = nsteps;
         roffs[b] = roff;
         nsteps += k4[b];
@@ -477,7 +479,8 @@ __global__ void __launch_bounds__(256) mvl_kernel(MVDev<float> a)
     T *Cf = reinterpret_cast<T *>(smem);
     double *theta = reinterpret_cast<double *>(Cf + nsteps * NT * 64);
     int *opos = reinterpret_cast<int *>(theta + NC), *wpos = opos + NC;
-    T *stage = reinterpret_cast<T *>(wpos + NC);                 // [4 waves][16][NC + 4]
+    int *cmap = wpos + NC;                                       // [MVL_CMAP]: the inputs' column lists
+    T *stage = reinterpret_cast<T *>(cmap + MVL_CMAP);           // [4 waves][16][NC + 4]
     T *ring = stage + 4 * 16 * (NC + 4);                         // [4 waves][2][NIN][MVL_SLOT]
     for (int e = tid; e < nsteps * NT * 64; e += blockDim.x) {
         const int l = e & 63, nt = (e >> 6) % NT, st = (e >> 6) / NT;
@@ -494,6 +497,10 @@ __global__ void __launch_bounds__(256) mvl_kernel(MVDev<float> a)
         wpos[c] = c < a.kout ? a.wpos[c] : -1;
         theta[c] = c < a.kout ? a.theta[c] : 0.0;
     }
+#pragma unroll
+    for (int b = 0; b < NIN; b++)
+        if (a.cols[b])
+            for (int r = tid; r < a.k[b]; r += blockDim.x) cmap[roffs[b] + r] = a.cols[b][r];
     __syncthreads();
 
     // per input: the byte offset each lane fetches for DMA instruction j (two
@@ -505,7 +512,7 @@ __global__ void __launch_bounds__(256) mvl_kernel(MVDev<float> a)
 #pragma unroll
     for (int b = 0; b < NIN; b++) {
         const int ld = a.ld[b];
-        aligned[b] = (ld % 4) == 0;
+        aligned[b] = (ld % 4) == 0 && !a.cols[b];   // rows rotated in LDS (read as 16-byte chunks)
 #pragma unroll
         for (int j = 0; j < 2; j++) {
             const int P = 64 * j + lane;
@@ -555,6 +562,16 @@ __global__ void __launch_bounds__(256) mvl_kernel(MVDev<float> a)
                 const floatx4 v = *reinterpret_cast<const floatx4 *>(slot + ((lr * cpr + cpos) & (MVL_SLOT / 4 - 1)) * 4);
 #pragma unroll
                 for (int q = 0; q < 4; q++) av[i + q] = (4 * c + q < k) ? v[q] : T(0);
+            }
+        } else if (a.cols[b]) {
+            // a column list (the active columns of a wider block)
+            const int *cm = cmap + roffs[b];
+#pragma unroll
+            for (int i = 0; i < KQ; i++) {
+                if (i >= k4[b]) break;
+                const int j = j0 + i;
+                const T v = slot[(lr * ld + cm[j < k ? j : 0]) & (MVL_SLOT - 1)];
+                av[i] = j < k ? v : T(0);
             }
         } else {
 #pragma unroll
@@ -685,7 +702,8 @@ __global__ void __launch_bounds__(256) mvl_kernel(MVDev<float> a)
 // tiles and the input rings
 static size_t mvl_lds_bytes(int nin, int nsteps)
 {
-    return (size_t)nsteps * 2 * 64 * 4 + 32 * 8 + 2 * 32 * 4 + 4 * 16 * 36 * 4 + (size_t)4 * 2 * nin * MVL_SLOT * 4;
+    return (size_t)nsteps * 2 * 64 * 4 + 32 * 8 + 2 * 32 * 4 + MVL_CMAP * 4 + 4 * 16 * 36 * 4 +
+           (size_t)4 * 2 * nin * MVL_SLOT * 4;
 }
 
 // Wide kernel: blocks of more than MAXW columns, given as up to MV_MAX_IN
@@ -997,7 +1015,7 @@ static bool mvl_fits(const MVArgs &h)
         return false;
     bool narrow = h.kout <= NARROW;
     for (int b = 0; b < h.nin; b++) {
-        if (h.cols[b] || h.coff[b] || h.ld[b] > MAXW || h.k[b] > h.ld[b]) return false;
+        if (h.coff[b] || h.ld[b] > MAXW || h.k[b] > h.ld[b]) return false;
         narrow = narrow && h.ld[b] <= NARROW;
     }
     return !narrow;
@@ -1008,7 +1026,7 @@ static hipError_t run_mvl(const MVArgs &h, hipStream_t st)
     MVDev<float> a = make_dev<float>(h);
     const int nb = mv_blocks(h.N);
     int nsteps = 0;
-    for (int b = 0; b < h.nin; b++) nsteps += mvf_k4(h.k[b], h.ld[b], false, 4);
+    for (int b = 0; b < h.nin; b++) nsteps += mvf_k4(h.k[b], h.ld[b], h.cols[b] != nullptr, 4);
     const size_t shm = mvl_lds_bytes(h.nin, nsteps);
     if (h.nin == 3)
         hipLaunchKernelGGL((mvl_kernel<3>), dim3(nb), dim3(256), shm, st, a);

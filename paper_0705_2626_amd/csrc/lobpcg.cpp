@@ -2090,9 +2090,9 @@ int lobpcg_combine(lobpcg_ctx *c, int dt, int n, const void *const *in, const in
 }
 
 int lobpcg_update(lobpcg_ctx *c, int dt, const void *d_X, const void *d_AX, const void *d_W, const void *d_AW,
-                  int nW, const void *d_P, const void *d_AP, int nP, const double *h_C, const double *h_theta,
-                  const int *h_J, int nJ, double norm_A, void *d_Xn, void *d_AXn, void *d_Pn, void *d_APn,
-                  void *d_Wn, double *h_rho)
+                  int nW, const void *d_P, const void *d_AP, int ldP, const int *h_Pcols, int nP, const double *h_C,
+                  const double *h_theta, const int *h_J, int nJ, double norm_A, void *d_Xn, void *d_AXn,
+                  void *d_Pn, void *d_APn, void *d_Wn, double *h_rho)
 {
     if (!c || !dtype_ok(c, dt)) return LOBPCG_ERR_ARG;
     const int m = c->m;
@@ -2100,6 +2100,7 @@ int lobpcg_update(lobpcg_ctx *c, int dt, const void *d_X, const void *d_AX, cons
         !h_C || !h_theta || !h_J || nJ < 1 || nJ > m || !(norm_A > 0) || !d_Xn || !d_AXn || !d_Pn || !d_APn ||
         !d_Wn || !h_rho)
         return LOBPCG_ERR_ARG;
+    if (nP && (h_Pcols ? ldP < 1 || ldP > m : ldP != nP)) return LOBPCG_ERR_ARG;
     const void *ins[6] = {d_X, d_AX, d_W, d_AW, d_P, d_AP};
     const void *outs[5] = {d_Xn, d_AXn, d_Pn, d_APn, d_Wn};
     for (const void *o : outs)
@@ -2111,17 +2112,24 @@ int lobpcg_update(lobpcg_ctx *c, int dt, const void *d_X, const void *d_AX, cons
         if (j < 0 || j >= m || jpos[j] >= 0) return LOBPCG_ERR_ARG;
         jpos[j] = i;
     }
-    const int *djpos;
+    const int *djpos, *dpcols = nullptr;
     const double *dtheta;
     int s = upload_cols(c, jpos, &djpos);
     if (s) return s;
+    if (nP && h_Pcols) {
+        std::vector<int> pc(h_Pcols, h_Pcols + nP);
+        for (int x : pc)
+            if (x < 0 || x >= ldP) return LOBPCG_ERR_ARG;
+        s = upload_cols(c, pc, &dpcols);
+        if (s) return s;
+    }
     s = upload_doubles(c, std::vector<double>(h_theta, h_theta + m), &dtheta);
     if (s) return s;
     MV q;
     q.nside = 2;
     q.input(0, d_X, d_AX, m, m);
     q.input(1, d_W, d_AW, nW, nW);
-    if (nP) q.input(2, d_P, d_AP, nP, nP);
+    if (nP) q.input(2, d_P, d_AP, nP && h_Pcols ? ldP : nP, nP, dpcols);
     q.kout = m;
     q.out[0] = d_Pn;
     q.out[1] = d_APn;

@@ -83,7 +83,7 @@ def lib():
             "lobpcg_apply_T": (i, [p, i, p, p, i]),
             "lobpcg_gram": (i, [p, i, i, p, p, p, i, p, p]),
             "lobpcg_combine": (i, [p, i, i, p, p, p, p, p, i, p, p]),
-            "lobpcg_update": (i, [p, i, p, p, p, p, i, p, p, i, p, p, p, i, d, p, p, p, p, p, p]),
+            "lobpcg_update": (i, [p, i, p, p, p, p, i, p, p, i, p, i, p, p, p, i, d, p, p, p, p, p, p]),
             "lobpcg_residual": (i, [p, i, p, p, i, p, p, i, d, p, p]),
             "lobpcg_residual_noalloc": (i, [i, ctypes.c_longlong, p, p, i, p, p, i, d, p, p, p]),
             "lobpcg_dense_chol": (i, [i, p, p]),
@@ -368,10 +368,11 @@ def lobpcg_combine(ctx, ins, C, kout, cols=None, add=None):
     return out
 
 
-def lobpcg_update(ctx, X, AX, W, AW, P, AP, C, theta, J, norm_A):
+def lobpcg_update(ctx, X, AX, W, AW, P, AP, C, theta, J, norm_A, Pcols=None):
     """The fused update of steps 25-33 and 7: returns (X', AX', P'_J, AP'_J,
     W'_J, rho) for C = [C_X; C_W; C_P] of shape (m + nW + nP, m); P and AP
-    may be None (no P terms)."""
+    may be None (no P terms); Pcols: the columns of P, AP that form the
+    P block (nP = len(Pcols)), else all of them."""
     X = _blk(ctx, X, "X", ctx.m)
     AX = _blk(ctx, AX, "AX", ctx.m, X.dtype)
     W = _blk(ctx, W, "W", dtype=X.dtype)
@@ -380,7 +381,9 @@ def lobpcg_update(ctx, X, AX, W, AW, P, AP, C, theta, J, norm_A):
     if P is not None:
         P = _blk(ctx, P, "P", dtype=X.dtype)
         AP = _blk(ctx, AP, "AP", P.shape[1], X.dtype)
-    nP = int(P.shape[1]) if P is not None else 0
+    ldP = int(P.shape[1]) if P is not None else 0
+    pc = np.ascontiguousarray(np.asarray(Pcols, dtype=np.int32)) if (P is not None and Pcols is not None) else None
+    nP = len(pc) if pc is not None else ldP
     m = ctx.m
     Cn = np.ascontiguousarray(np.asarray(C, dtype=np.float64))
     if Cn.shape != (m + nW + nP, m):
@@ -395,7 +398,8 @@ def lobpcg_update(ctx, X, AX, W, AW, P, AP, C, theta, J, norm_A):
     Pn, APn, Wn = (torch.empty((N, max(nJ, 1)), dtype=X.dtype, device=X.device) for _ in range(3))
     rho = np.zeros(m)
     _check(lib().lobpcg_update(ctx.h, _dt(X), _ptr(X), _ptr(AX), _ptr(W), _ptr(AW), nW,
-                               _ptr(P) if P is not None else None, _ptr(AP) if P is not None else None, nP,
+                               _ptr(P) if P is not None else None, _ptr(AP) if P is not None else None, ldP,
+                               _np_ptr(pc) if pc is not None else None, nP,
                                _np_ptr(Cn), _np_ptr(th), _np_ptr(Jn) if nJ else None, nJ, float(norm_A),
                                _ptr(Xn), _ptr(AXn), _ptr(Pn), _ptr(APn), _ptr(Wn), _np_ptr(rho)), "lobpcg_update")
     return Xn, AXn, Pn[:, :nJ], APn[:, :nJ], Wn[:, :nJ], rho

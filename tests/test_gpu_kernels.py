@@ -356,32 +356,38 @@ def update_reference(X, AX, W, AW, P, AP, C, theta, J, norm_A):
 # without P, ragged last groups of 16 points, a grid of fewer points than one
 # workgroup pass), the fragment kernel (m = 30), the narrow kernel (m = 8) and
 # the wide kernel (m = 48)
-UPDATE_SHAPES = [(5003, 32, 32, 32, 32), (70001, 32, 20, 20, 20), (4099, 32, 23, 23, 21), (777, 32, 32, 0, 32),
-                 (3001, 12, 7, 5, 7), (37, 12, 5, 5, 4), (2049, 30, 17, 17, 15), (1000, 8, 5, 3, 5),
-                 (3000, 48, 40, 40, 33)]
+# (N, m, nW, nP, nJ, ldP): ldP > nP takes P as a column list of a wider
+# block (the solver's active directions)
+UPDATE_SHAPES = [(5003, 32, 32, 32, 32, 32), (70001, 32, 20, 20, 20, 20), (4099, 32, 23, 23, 21, 23),
+                 (777, 32, 32, 0, 32, 0), (3001, 12, 7, 5, 7, 5), (37, 12, 5, 5, 4, 5), (2049, 30, 17, 17, 15, 17),
+                 (1000, 8, 5, 3, 5, 3), (3000, 48, 40, 40, 33, 40), (9001, 32, 21, 21, 21, 24),
+                 (4097, 32, 26, 26, 20, 31), (4097, 32, 13, 13, 13, 16)]
 
 
-def update_inputs(N, m, nW, nP, nJ, npdt):
-    rng = np.random.default_rng(N + 7 * m + nW)
+def update_inputs(N, m, nW, nP, nJ, ldP, npdt):
+    rng = np.random.default_rng(N + 7 * m + nW + ldP)
     blk = lambda w, s: synth.random_block(N, w, seed=s).astype(npdt)
     X, AX, W, AW = blk(m, 1), blk(m, 2), blk(nW, 3), blk(nW, 4)
-    P, AP = (blk(nP, 5), blk(nP, 6)) if nP else (None, None)
+    P, AP = (blk(ldP, 5), blk(ldP, 6)) if nP else (None, None)
+    Pcols = np.sort(rng.choice(ldP, size=nP, replace=False)) if ldP > nP else None
     C = rng.standard_normal((m + nW + nP, m)) / np.sqrt(m)
     theta = np.sort(rng.uniform(0.01, 2.0, m))
     J = np.sort(rng.choice(m, size=nJ, replace=False))
-    return X, AX, W, AW, P, AP, C, theta, J
+    return X, AX, W, AW, P, AP, Pcols, C, theta, J
 
 
-@pytest.mark.parametrize("N,m,nW,nP,nJ", UPDATE_SHAPES)
+@pytest.mark.parametrize("N,m,nW,nP,nJ,ldP", UPDATE_SHAPES)
 @pytest.mark.parametrize("prec", [L.FP64, L.MIXED])
-def test_update(N, m, nW, nP, nJ, prec):
+def test_update(N, m, nW, nP, nJ, ldP, prec):
     ctx = ctx_for((N, 1, 1), m, None, L.MIXED)
     npdt = np.float64 if prec == L.FP64 else np.float32
     dtype = torch.float64 if prec == L.FP64 else torch.float32
-    X, AX, W, AW, P, AP, C, theta, J = update_inputs(N, m, nW, nP, nJ, npdt)
+    X, AX, W, AW, P, AP, Pcols, C, theta, J = update_inputs(N, m, nW, nP, nJ, ldP, npdt)
     d = lambda a: dev(a, dtype) if a is not None else None
-    got = L.lobpcg_update(ctx, d(X), d(AX), d(W), d(AW), d(P), d(AP), C, theta, J, 12.0)
+    got = L.lobpcg_update(ctx, d(X), d(AX), d(W), d(AW), d(P), d(AP), C, theta, J, 12.0, Pcols=Pcols)
     f64 = lambda a: a.astype(np.float64) if a is not None else None
+    if Pcols is not None:
+        P, AP = P[:, Pcols], AP[:, Pcols]
     # the FP32 kernels multiply by the coefficients rounded to FP32
     Cr = C.astype(np.float32).astype(np.float64) if prec == L.MIXED else C
     ref = update_reference(f64(X), f64(AX), f64(W), f64(AW), f64(P), f64(AP), Cr, theta, J, 12.0)
@@ -397,17 +403,17 @@ def test_update(N, m, nW, nP, nJ, prec):
     np.testing.assert_allclose(got[5], ref[5], rtol=1e-12 if prec == L.FP64 else 1e-4)
 
 
-@pytest.mark.parametrize("N,m,nW,nP,nJ", [s for s in UPDATE_SHAPES if s[1] % 4 == 0 and 8 < s[1] <= 32])
-def test_update_kernels_agree(N, m, nW, nP, nJ):
+@pytest.mark.parametrize("N,m,nW,nP,nJ,ldP", [s for s in UPDATE_SHAPES if s[1] % 4 == 0 and 8 < s[1] <= 32])
+def test_update_kernels_agree(N, m, nW, nP, nJ, ldP):
     """The LDS-pipelined FP32 update and the fragment kernel (kernel variant
     bit 0) take the same products in the same order: identical blocks."""
-    X, AX, W, AW, P, AP, C, theta, J = update_inputs(N, m, nW, nP, nJ, np.float32)
+    X, AX, W, AW, P, AP, Pcols, C, theta, J = update_inputs(N, m, nW, nP, nJ, ldP, np.float32)
     d = lambda a: dev(a, torch.float32) if a is not None else None
     res = []
     for v in (0, 1):
         ctx = L.lobpcg_setup(L.Op(N, 1, 1), L.Precond(None), m, L.MIXED)
         L.lobpcg_set_option(ctx, L.OPT_KERNELS, v)
-        res.append(L.lobpcg_update(ctx, d(X), d(AX), d(W), d(AW), d(P), d(AP), C, theta, J, 12.0))
+        res.append(L.lobpcg_update(ctx, d(X), d(AX), d(W), d(AW), d(P), d(AP), C, theta, J, 12.0, Pcols=Pcols))
     for a, b in zip(res[0][:5], res[1][:5]):
         assert torch.equal(a, b)
     np.testing.assert_allclose(res[0][5], res[1][5], rtol=1e-13)
