@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--m", type=int, default=32)
     ap.add_argument("--levels", type=int, default=6)
+    ap.add_argument("--nu", type=int, default=2, help="pre- and post-smoothing sweeps of the V-cycle")
+    ap.add_argument("--omega", type=float, default=2.0 / 3.0, help="weighted-Jacobi weight of the smoother")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=300)
     ap.add_argument("--spmm-reps", type=int, default=20)
@@ -156,7 +158,7 @@ def main():
     dims = (n, n, n)
     N = n ** 3
     X0 = torch.from_numpy(synth.x0_uniform(N, m, seed=2)).to(dev)
-    A, T = L.Op(*dims), L.Precond(levels)
+    A, T = L.Op(*dims), L.Precond(levels, args.nu, args.nu, 20, args.omega)
     from oracle import closed_form  # closed form of the spectrum, used only to report accuracy
     exact_next, _ = closed_form.smallest(*dims, m + 1)
     exact = exact_next[:m]
@@ -251,9 +253,9 @@ def main():
         "warmup": args.warmup, "ms_per_step": 1e3 * t_mixed, "higher_is_better": False, "scaling": "strong",
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "7-point Dirichlet Laplacian %d^3 (N=%d), m=%d smallest eigenpairs, "
-                               "GMG V(2,2) %d levels, tol %g after FP64 refinement, X0 uniform[-1,1] seed 2"
-                               % (n, N, m, levels, tol),
-                   "n": n, "N": N, "m": m, "levels": levels, "tol": tol},
+                               "GMG V(%d,%d) weighted Jacobi omega=%.4g, %d levels, tol %g after FP64 refinement, "
+                               "X0 uniform[-1,1] seed 2" % (n, N, m, args.nu, args.nu, args.omega, levels, tol),
+                   "n": n, "N": N, "m": m, "levels": levels, "nu": args.nu, "omega": args.omega, "tol": tol},
         "mixed": {"value": t_mixed, "unit": "s", **acc_mixed},
         "fp64": fp64,
         "speedup_mixed_vs_fp64": (fp64["value"] / t_mixed) if fp64 else None,
