@@ -481,7 +481,7 @@ def sweep_problem_size(args, L, synth, torch, dev):
         dims = (n, n, n)
         N = n ** 3
         levels = levels_for(n)
-        A, T = L.Op(*dims), L.Precond(levels)
+        A, T = L.Op(*dims), L.Precond(levels, args.nu, args.nu, 20, args.omega)
         for m in ((8, 32) if n <= 256 else (8,)):
             X0 = torch.from_numpy(synth.x0_uniform(N, m, seed=2)).to(dev)
             exact, _ = closed_form.smallest(*dims, m)
@@ -507,7 +507,7 @@ def seed_spread(args, L, synth, torch, dev):
     n, m, levels = args.n, args.m, args.levels
     dims = (n, n, n)
     N = n ** 3
-    A, T = L.Op(*dims), L.Precond(levels)
+    A, T = L.Op(*dims), L.Precond(levels, args.nu, args.nu, 20, args.omega)
     times = {"mixed": [], "fp64": []}
     iters = {"mixed": [], "fp64": []}
     for seed in [int(v) for v in args.seeds.split(",")]:
@@ -537,7 +537,7 @@ def sweep_block_size(args, L, synth, torch, dev):
     levels = 5 if args.levels == 6 else args.levels
     dims = (n, n, n)
     N = n ** 3
-    A, T = L.Op(*dims), L.Precond(levels)
+    A, T = L.Op(*dims), L.Precond(levels, args.nu, args.nu, 20, args.omega)
     for m in [int(v) for v in args.sweep_m.split(",")]:
         X0 = torch.from_numpy(synth.x0_uniform(N, m, seed=2)).to(dev)
         exact, _ = closed_form.smallest(*dims, m)

@@ -119,6 +119,33 @@ def test_block_edge_inside_a_cluster_n128_m64():
     release()
 
 
+@pytest.mark.parametrize("prec", [L.MIXED, L.FP64])
+def test_block_size_study_m80_converges(prec):
+    """The block-size study's m = 80 on 128^3, the hardest point: the block
+    holds two members of the triple lambda_79..81 with a six-fold group
+    7.5e-4 above.  With the smoother weight 6/7 (the V-cycle damps the upper
+    half of the spectrum best), cluster locking and the computed block
+    diagonal of gramB it converges within 1000 iterations in both precisions
+    (measured: 256 mixed, 536 FP64); eigenvalues within the a-posteriori
+    bound of the closed form."""
+    n, m, tol = 128, 80, 1e-8
+    N = n ** 3
+    ctx = L.lobpcg_setup(L.Op(n, n, n), L.Precond(5, 2, 2, 20, 6.0 / 7.0), m, prec)
+    L.lobpcg_set_option(ctx, L.OPT_LOCK_GAP, 3e-4)
+    L.lobpcg_set_option(ctx, L.OPT_FP64_EXPLICIT_GRAM, 1)
+    r = L.lobpcg_solve(ctx, dev(synth.x0_uniform(N, m, seed=2)), tol, 1000, hist=False)
+    exact, _ = closed_form.smallest(n, n, n, m + 6)
+    assert r.status == L.OK, r.iters
+    assert r.resid.max() <= tol
+    for j in range(m):
+        others = np.abs(exact - exact[j])
+        gap = others[others > 1e-12 * exact[j]].min()
+        assert abs(r.lam[j] - exact[j]) <= (12.0 * r.resid[j]) ** 2 / gap
+    check_orthonormal(r.X, 1e-9)
+    del ctx, r
+    release()
+
+
 @pytest.mark.parametrize("tol,rtol", [(1e-8, 1e-8), (1.5e-9, 1e-10)])
 def test_n128_m16_fp64_multigrid(tol, rtol):
     """FP64, n=128 (N=2,097,152), m=16, V(2,2) with 5 levels.  The block edge
