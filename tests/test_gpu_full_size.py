@@ -113,7 +113,9 @@ def test_block_edge_inside_a_cluster_n128_m64():
     for j in range(m):
         others = np.abs(exact - exact[j])
         gap = others[others > 1e-12 * exact[j]].min()
-        assert abs(r.lam[j] - exact[j]) <= (12.0 * r.resid[j]) ** 2 / gap
+        # plus FP64 rounding: a column locked far below tol has a bound
+        # under the rounding of its Ritz value
+        assert abs(r.lam[j] - exact[j]) <= (12.0 * r.resid[j]) ** 2 / gap + 1e-13 * exact[j]
     check_orthonormal(r.X, 1e-10)
     del ctx, r
     release()
@@ -140,7 +142,9 @@ def test_block_size_study_m80_converges(prec):
     for j in range(m):
         others = np.abs(exact - exact[j])
         gap = others[others > 1e-12 * exact[j]].min()
-        assert abs(r.lam[j] - exact[j]) <= (12.0 * r.resid[j]) ** 2 / gap
+        # plus FP64 rounding: a column locked far below tol has a bound
+        # under the rounding of its Ritz value
+        assert abs(r.lam[j] - exact[j]) <= (12.0 * r.resid[j]) ** 2 / gap + 1e-13 * exact[j]
     check_orthonormal(r.X, 1e-9)
     del ctx, r
     release()
