@@ -419,6 +419,42 @@ def test_update_kernels_agree(N, m, nW, nP, nJ, ldP):
     np.testing.assert_allclose(res[0][5], res[1][5], rtol=1e-13)
 
 
+def test_update_argument_errors():
+    """lobpcg_update rejects bad sizes, repeated or out-of-range active
+    columns, P column lists out of range and outputs that alias inputs,
+    before launching anything."""
+    N, m = 3001, 12
+    ctx = ctx_for((N, 1, 1), m, None, L.MIXED)
+    X, AX, W, AW, P, AP, Pcols, C, theta, J = update_inputs(N, m, 7, 5, 7, 8, np.float64)
+    d = lambda a: dev(a) if a is not None else None
+    dX, dAX, dW, dAW, dP, dAP = d(X), d(AX), d(W), d(AW), d(P), d(AP)
+    ok = L.lobpcg_update(ctx, dX, dAX, dW, dAW, dP, dAP, C, theta, J, 12.0, Pcols=Pcols)
+    assert ok[5].shape == (m,)
+    bad = [dict(J=[0, 0, 1]), dict(J=[m]), dict(Pcols=[0, 1, 2, 3, 8]), dict(Pcols=[-1, 1, 2, 3, 4]),
+           dict(norm_A=0.0)]
+    for b in bad:
+        kw = dict(J=J, Pcols=Pcols, norm_A=12.0)
+        kw.update(b)
+        with pytest.raises(L.LobpcgError):
+            L.lobpcg_update(ctx, dX, dAX, dW, dAW, dP, dAP, C, theta, kw["J"], kw["norm_A"], Pcols=kw["Pcols"])
+    # an output aliasing an input, through the C ABI directly
+    lib = L.lib()
+    Cn = np.ascontiguousarray(C)
+    th = np.ascontiguousarray(theta)
+    Jn = np.ascontiguousarray(J, dtype=np.int32)
+    pc = np.ascontiguousarray(Pcols, dtype=np.int32)
+    rho = np.zeros(m)
+    outs = [torch.empty_like(dX), torch.empty_like(dAX)] + [torch.empty((N, len(J)), dtype=dX.dtype, device=DEV)
+                                                            for _ in range(3)]
+    for k in range(5):
+        o = [t.data_ptr() for t in outs]
+        o[k] = dW.data_ptr()
+        s = lib.lobpcg_update(ctx.h, L.F64, dX.data_ptr(), dAX.data_ptr(), dW.data_ptr(), dAW.data_ptr(), 7,
+                              dP.data_ptr(), dAP.data_ptr(), 8, pc.ctypes.data, 5, Cn.ctypes.data, th.ctypes.data,
+                              Jn.ctypes.data, len(J), 12.0, *o, rho.ctypes.data)
+        assert s == L.ERR_ARG
+
+
 # ---------------------------------------------------------------- residual and norms (steps 7-8)
 
 @pytest.mark.parametrize("N,m,J", [(4096, 4, [0, 1, 2, 3]), (70001, 32, list(range(0, 32, 3))), (999, 7, [6]),
