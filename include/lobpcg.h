@@ -201,6 +201,14 @@ enum {
                                     /* stays active while an unconverged active column */
                                     /* has a Ritz value within this relative distance  */
                                     /* of its own (0 <= value < 1)                     */
+    LOBPCG_OPT_NWANT = 10,          /* a block wider than the wanted set (Section      */
+                                    /* 2.1.3's advice when the spectrum clusters at    */
+                                    /* the block edge): the solve ends as soon as the  */
+                                    /* first NWANT columns (the smallest Ritz pairs)   */
+                                    /* have rho_j <= tol, the rest being guard         */
+                                    /* columns; 0 (default) = m.  In the mixed solver  */
+                                    /* the FP32 phase's switch and stall tests also    */
+                                    /* look at the wanted columns only                 */
     LOBPCG_OPT_FP64_EXPLICIT_GRAM = 8 /* 1: FP64 iterations compute the block diagonal */
                                     /* of gramB and X^T AX too (the variant Section    */
                                     /* 2.2 reports testing in MATLAB: better           */

@@ -84,7 +84,7 @@ def b_orthonormalize(V, BV, *others):
 
 
 def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactivate=True, Y=None, apply_B=None,
-           explicit_gram=False, lock_gap=0.0):
+           explicit_gram=False, lock_gap=0.0, nwant=None):
     """Smallest eigenpairs of A x = lambda B x (Section 2.1.1).
 
     apply_A, apply_T, apply_B: functions on (N, k) blocks (apply_B None: B = I).
@@ -104,6 +104,12 @@ def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactiva
     residual is below tol stays in J while a column of J that is still above
     tol has a Ritz value within the relative distance lock_gap of its own, so
     that the members of a cluster leave J together.
+    nwant: a block wider than the wanted set (Section 2.1.3 advises a few
+    columns more than the eigenpairs sought when the spectrum clusters at
+    the block edge; a reading of how such a run ends): the iteration also
+    ends once the nwant smallest Ritz pairs (the first nwant columns) have
+    rho_j <= tol; the other columns are guard vectors, iterated like the rest
+    while unconverged.  None: nwant = m.
     """
     X0 = np.asfortranarray(np.asarray(X0, dtype=np.float64))
     N, m = X0.shape
@@ -141,11 +147,15 @@ def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactiva
     J = np.arange(m)
     P = AP = BP = None
     hist, status, k = [], NOT_CONVERGED, 0
+    nw = m if nwant is None else int(nwant)
     for k in range(maxit):                                     # step 6
         rho, Rr = rho_of(X, AX, BX, lam)                       # step 7 (all columns)
         hist.append(rho)
         if not np.all(np.isfinite(rho)):
             status = ERR_NONFINITE
+            break
+        if nw < m and np.all(rho[:nw] <= tol):                 # the wanted pairs have converged
+            status = OK
             break
         above = rho[J] > tol                                   # step 8
         if lock_gap > 0.0:
@@ -233,7 +243,7 @@ def lobpcg(apply_A, X0, tol, maxit, normA, apply_T=None, callback=None, reactiva
 
 def laplace7_solver(dims, m, X0, tol, maxit, levels=None, nu_pre=2, nu_post=2, coarse_sweeps=20,
                     omega=2.0 / 3.0, callback=None, Y=None, bdiag=None, explicit_gram=False, bmass=None,
-                    lock_gap=0.0):
+                    lock_gap=0.0, nwant=None):
     """LOBPCG on the 7-point Laplacian with optional V-cycle preconditioning,
     constraints Y and B = diag(bdiag) (a lumped mass) or B = the 7-point
     mass-type operator with coefficients bmass = (b0, b1)."""
@@ -250,7 +260,7 @@ def laplace7_solver(dims, m, X0, tol, maxit, levels=None, nu_pre=2, nu_post=2, c
         b0, b1 = bmass
         Bop = lambda V: grid.mass7(dims, b0, b1, V)
     return lobpcg(A, X0, tol, maxit, grid.gershgorin_laplace7(), apply_T=T, callback=callback, Y=Y, apply_B=Bop,
-                  explicit_gram=explicit_gram, lock_gap=lock_gap)
+                  explicit_gram=explicit_gram, lock_gap=lock_gap, nwant=nwant)
 
 
 def varcoef_solver(dims, kx, ky, kz, m, X0, tol, maxit, levels=None, callback=None):

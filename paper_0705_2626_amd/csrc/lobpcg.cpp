@@ -175,6 +175,7 @@ struct lobpcg_ctx {
     bool profile, reactivate;
     double lock_gap;              // soft locking keeps a converged column active while an unconverged
                                   // one has a Ritz value within this relative distance (0: off)
+    int nwant;                    // the run ends once the first nwant columns have converged (0: m)
     int mv_frag, mg_unpadded, gram_staged, gram_nt4, gram_nt32, gram_direct;  // kernel variants (see LOBPCG_OPT_KERNELS)
     bool fp32_explicit;           // FP32 phase: Gram diagonal blocks computed, not assumed
     bool fp64_explicit;           // the same for FP64 iterations
@@ -1275,6 +1276,7 @@ int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &
               int maxit, int &iters, double *h_hist, bool explicit_gram, bool allow_switch, int &outcome)
 {
     const int m = c->m;
+    const int nw = c->nwant > 0 ? c->nwant : m;   // wanted pairs; the others are guard columns
     std::vector<double> rr(m), xx(m), rho(m), SS, SAS, PP;
     std::vector<double> hist_max;
     outcome = PH_MAXIT;
@@ -1294,16 +1296,22 @@ int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &
             if (s) return s;
         }
         ps.have_res = false;
-        double rmax = 0.0;
+        double rmax = 0.0;   // over the wanted columns
         for (int j = 0; j < m; j++) {
             rho[j] = std::sqrt(rr[j]) / (normA * std::sqrt(xx[j]));
             if (!std::isfinite(rho[j])) return LOBPCG_ERR_NONFINITE;
-            rmax = std::max(rmax, rho[j]);
+            if (j < nw) rmax = std::max(rmax, rho[j]);
         }
         if (h_hist) std::copy(rho.begin(), rho.end(), h_hist + (size_t)iters * m);
         iters++;
         if (dt == DT_F32) c->stats.iters_fp32++;
         else c->stats.iters_fp64++;
+        // a block wider than the wanted set (Section 2.1.3): done once the
+        // first nw Ritz pairs have converged, whatever the guard columns do
+        if (nw < m && rmax <= tol) {
+            outcome = PH_CONVERGED;
+            return LOBPCG_OK;
+        }
         // step 8: drop converged columns; end only when every residual is small
         std::vector<int> Jn;
         for (int j : ps.J) {
@@ -1728,6 +1736,7 @@ int lobpcg_setup(lobpcg_ctx **out, const lobpcg_op *A, const lobpcg_op *B, const
     c->profile = false;
     c->reactivate = true;
     c->lock_gap = 0.0;
+    c->nwant = 0;
     c->mv_frag = 0;
     c->mg_unpadded = 0;
     c->gram_staged = 0;
@@ -1779,6 +1788,10 @@ int lobpcg_set_option(lobpcg_ctx *c, int key, double v)
         }
         return LOBPCG_OK;
     case LOBPCG_OPT_REACTIVATE: c->reactivate = v != 0; return LOBPCG_OK;
+    case LOBPCG_OPT_NWANT:
+        if (!(v >= 0.0 && v <= c->m) || v != std::floor(v)) return LOBPCG_ERR_ARG;
+        c->nwant = (int)v;
+        return LOBPCG_OK;
     case LOBPCG_OPT_LOCK_GAP:
         if (!(v >= 0.0 && v < 1.0)) return LOBPCG_ERR_ARG;
         c->lock_gap = v;

@@ -494,6 +494,37 @@ def test_explicit_gram_fp64_matches_oracle():
     np.testing.assert_allclose(r.hist[:k], ref.hist[:k], rtol=1e-6, atol=1e-14)
 
 
+@pytest.mark.parametrize("prec", [L.FP64, L.MIXED])
+def test_wanted_pairs_with_guard_columns_match_oracle(prec):
+    """A block of 7 columns for 4 wanted pairs (LOBPCG_OPT_NWANT): the solve
+    ends when the first 4 have converged, as the oracle's run with nwant = 4
+    does (same iteration count in FP64; eigenvalues and residuals of the
+    wanted pairs against the oracle and the closed form).  nwant out of
+    range is rejected."""
+    dims, m, nw, levels, tol = (12, 11, 10), 7, 4, 2, 1e-9
+    N = int(np.prod(dims))
+    X0 = synth.x0_uniform(N, m, seed=5)
+    ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(levels), m, prec)
+    L.lobpcg_set_option(ctx, L.OPT_NWANT, nw)
+    r = L.lobpcg_solve(ctx, dev(X0), tol, 500)
+    ref = olob.laplace7_solver(dims, m, X0, tol, 500, levels=levels, nwant=nw)
+    exact, _ = closed_form.smallest(*dims, m)
+    assert r.status == L.OK and ref.status == olob.OK
+    assert r.resid[:nw].max() <= tol
+    np.testing.assert_allclose(r.lam[:nw], exact[:nw], rtol=1e-10)
+    np.testing.assert_allclose(r.lam[:nw], ref.lam[:nw], rtol=1e-10)
+    if prec == L.FP64:
+        assert r.iters == ref.iters
+        assert active_sets(r.hist, tol) == active_sets(ref.hist, tol)
+        np.testing.assert_allclose(r.hist, ref.hist, rtol=1e-6, atol=1e-14)
+    ctx_all = L.lobpcg_setup(L.Op(*dims), L.Precond(levels), m, prec)
+    full = L.lobpcg_solve(ctx_all, dev(X0), tol, 500)
+    assert r.iters < full.iters
+    for v in (-1, m + 1, 2.5):
+        with pytest.raises(L.LobpcgError):
+            L.lobpcg_set_option(ctx, L.OPT_NWANT, v)
+
+
 def test_block_of_98_fp64():
     """The widest block of the paper's block-size study (m = 98) on a 16^3
     grid: a Rayleigh-Ritz basis of 294 vectors."""

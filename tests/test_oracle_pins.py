@@ -602,6 +602,28 @@ def test_mass7_B_matches_dense_generalized_eigenproblem():
     np.testing.assert_allclose(r.lam, mu[:m], rtol=1e-10)
 
 
+def test_wanted_pairs_with_guard_columns():
+    """A block of 7 columns for the 4 wanted pairs (three guard columns): the
+    run ends when the first 4 have converged, their Ritz values agree with the
+    closed form, and it takes no more iterations than converging all 7.  With
+    nwant = m it is the plain run, iteration for iteration."""
+    dims, m, nw, tol = (12, 11, 10), 7, 4, 1e-9
+    N = int(np.prod(dims))
+    X0 = synth.x0_uniform(N, m, seed=5)
+    exact, _ = closed_form.smallest(*dims, m)
+    r = lobpcg.laplace7_solver(dims, m, X0, tol, 500, levels=2, nwant=nw)
+    assert r.status == lobpcg.OK
+    assert r.hist[-1][:nw].max() <= tol and r.resid[:nw].max() <= 1.01 * tol
+    np.testing.assert_allclose(r.lam[:nw], exact[:nw], rtol=1e-12)
+    full = lobpcg.laplace7_solver(dims, m, X0, tol, 500, levels=2)
+    same = lobpcg.laplace7_solver(dims, m, X0, tol, 500, levels=2, nwant=m)
+    assert full.status == lobpcg.OK and same.iters == full.iters
+    assert np.array_equal(same.lam, full.lam) and np.array_equal(same.hist, full.hist)
+    assert r.iters <= full.iters
+    # the runs agree up to the wanted set's exit
+    np.testing.assert_array_equal(r.hist, full.hist[:r.iters])
+
+
 def test_cluster_locking_keeps_groups_together():
     """Soft locking by clusters (lock_gap): on 16^3 without preconditioner
     the triple lambda_2..4 leaves the active set in one iteration (with the
