@@ -36,18 +36,22 @@ bool chol_scaled(int n, const double *G, double *R)
             double g = 0.5 * (G[i * n + j] + G[j * n + i]);
             H[i * n + j] = g / (d[i] * d[j]);
         }
-    // upper Cholesky Rh (row-oriented): Rh[i][i] = sqrt(H_ii - sum_k<i Rh[k][i]^2)
+    // upper Cholesky Rh, one row at a time: row i of Rh from row i of H, then
+    // its outer product taken off the trailing rows of H (the subtractions
+    // of each entry in the same order as a dot product over k < i, with
+    // contiguous rows)
     std::fill(R, R + size_t(n) * n, 0.0);
     for (int i = 0; i < n; i++) {
-        double s = H[i * n + i];
-        for (int k = 0; k < i; k++) s -= R[k * n + i] * R[k * n + i];
+        const double s = H[i * n + i];
         if (!(s > 0.0) || !std::isfinite(s)) return false;
-        double rii = std::sqrt(s);
-        R[i * n + i] = rii;
+        const double rii = std::sqrt(s);
+        double *ri = R + size_t(i) * n;
+        ri[i] = rii;
+        for (int j = i + 1; j < n; j++) ri[j] = H[i * n + j] / rii;
         for (int j = i + 1; j < n; j++) {
-            double t = H[i * n + j];
-            for (int k = 0; k < i; k++) t -= R[k * n + i] * R[k * n + j];
-            R[i * n + j] = t / rii;
+            const double rj = ri[j];
+            double *hj = H.data() + size_t(j) * n;
+            for (int l = j; l < n; l++) hj[l] -= rj * ri[l];
         }
     }
     for (int i = 0; i < n; i++)
@@ -55,20 +59,23 @@ bool chol_scaled(int n, const double *G, double *R)
     return true;
 }
 
-// Inverse of an upper-triangular n x n matrix (row-major), by back substitution
-// column by column.
+// Inverse of an upper-triangular n x n matrix (row-major), by back
+// substitution, one row of the inverse at a time from the last:
+// Ri[i][:] = (e_i - sum_{k>i} R[i][k] Ri[k][:]) / R[i][i].
 bool triu_inverse(int n, const double *R, double *Ri)
 {
     std::fill(Ri, Ri + size_t(n) * n, 0.0);
-    for (int j = 0; j < n; j++) {
-        // solve R x = e_j; x is zero below j
-        for (int i = j; i >= 0; i--) {
-            double s = (i == j) ? 1.0 : 0.0;
-            for (int k = i + 1; k <= j; k++) s -= R[i * n + k] * Ri[k * n + j];
-            double rii = R[i * n + i];
-            if (rii == 0.0 || !std::isfinite(rii)) return false;
-            Ri[i * n + j] = s / rii;
+    for (int i = n - 1; i >= 0; i--) {
+        const double rii = R[i * n + i];
+        if (rii == 0.0 || !std::isfinite(rii)) return false;
+        double *out = Ri + size_t(i) * n;
+        out[i] = 1.0;
+        for (int k = i + 1; k < n; k++) {
+            const double r = R[i * n + k];
+            const double *rk = Ri + size_t(k) * n;
+            for (int j = k; j < n; j++) out[j] -= r * rk[j];
         }
+        for (int j = i; j < n; j++) out[j] /= rii;
     }
     return true;
 }
@@ -131,16 +138,35 @@ void tridiagonalize(int n, double *A, double *d, double *e, double *Qt)
         for (int i = k + 2; i < n; i++) A[i * n + k] = A[k * n + i] = 0.0;
         // Q <- Q H: column j of Q is row j of Qt; H = I - beta v v^T acts on
         // columns k+1..n-1, i.e. Qt rows: Qt[j][i] -= beta (sum_l Qt[l][i] v[l]) v[j]
-        for (int i = 0; i < n; i++) {
-            double s = 0.0;
-            for (int l = k + 1; l < n; l++) s += Qt[l * n + i] * v[l];
-            s *= beta;
-            for (int l = k + 1; l < n; l++) Qt[l * n + i] -= s * v[l];
+        for (int i = 0; i < n; i++) p[i] = 0.0;
+        for (int l = k + 1; l < n; l++) {
+            const double vl = v[l];
+            const double *ql = Qt + size_t(l) * n;
+            for (int i = 0; i < n; i++) p[i] += ql[i] * vl;
+        }
+        for (int i = 0; i < n; i++) p[i] *= beta;
+        for (int l = k + 1; l < n; l++) {
+            const double vl = v[l];
+            double *ql = Qt + size_t(l) * n;
+            for (int i = 0; i < n; i++) ql[i] -= p[i] * vl;
         }
     }
     for (int i = 0; i < n; i++) d[i] = A[i * n + i];
     for (int i = 0; i + 1 < n; i++) e[i] = A[i * n + i + 1];
     if (n > 0) e[n - 1] = 0.0;
+}
+
+// Rows (a, b) <- (c a - s b, s a + c b).  Most of the eigensolver's time is
+// spent here; the AVX2 clone (chosen at load time where the CPU has it)
+// does the same operations per element, four at a time.
+__attribute__((target_clones("avx2", "default"))) void rotate_rows(double *__restrict__ a, double *__restrict__ b,
+                                                                    int n, double c, double s)
+{
+    for (int i = 0; i < n; i++) {
+        const double u = a[i], t = b[i];
+        a[i] = c * u - s * t;
+        b[i] = s * u + c * t;
+    }
 }
 
 // Implicit symmetric QR with Wilkinson shift on the tridiagonal (d, e);
@@ -184,12 +210,7 @@ bool tridiagonal_qr(int n, double *d, double *e, double *Zt)
                 x = e[k];
                 z = bulge;
             }
-            double *zk = Zt + size_t(k) * n, *zk1 = Zt + size_t(k + 1) * n;
-            for (int i = 0; i < n; i++) {
-                double u = zk[i], t = zk1[i];
-                zk[i] = c * u - s * t;
-                zk1[i] = s * u + c * t;
-            }
+            rotate_rows(Zt + size_t(k) * n, Zt + size_t(k + 1) * n, n, c, s);
         }
     }
     return true;
@@ -231,28 +252,37 @@ bool rayleigh_ritz(int n, int m, const double *gramA, const double *gramB, doubl
         w(n), Y(size_t(n) * n);
     if (!chol_scaled(n, gramB, R.data())) return false;
     if (!triu_inverse(n, R.data(), Ri.data())) return false;
-    // T1 = gramA Ri (use the symmetric gramA)
-    for (int i = 0; i < n; i++)
-        for (int j = 0; j < n; j++) {
-            double s = 0.0;
-            for (int k = 0; k <= j; k++) s += 0.5 * (gramA[i * n + k] + gramA[k * n + i]) * Ri[k * n + j];
-            T1[i * n + j] = s;
+    // T1 = gramA Ri (the symmetric part of gramA); the products run over
+    // contiguous rows, each entry summed over k in increasing order
+    for (int i = 0; i < n; i++) {
+        double *t = T1.data() + size_t(i) * n;
+        for (int k = 0; k < n; k++) {
+            const double a = 0.5 * (gramA[i * n + k] + gramA[k * n + i]);
+            const double *rk = Ri.data() + size_t(k) * n;
+            for (int j = k; j < n; j++) t[j] += a * rk[j];
         }
+    }
     // M = Ri^T T1
-    for (int i = 0; i < n; i++)
-        for (int j = 0; j < n; j++) {
-            double s = 0.0;
-            for (int k = 0; k <= i; k++) s += Ri[k * n + i] * T1[k * n + j];
-            M[i * n + j] = s;
+    for (int i = 0; i < n; i++) {
+        double *mi = M.data() + size_t(i) * n;
+        for (int k = 0; k <= i; k++) {
+            const double r = Ri[k * n + i];
+            const double *tk = T1.data() + size_t(k) * n;
+            for (int j = 0; j < n; j++) mi[j] += r * tk[j];
         }
+    }
     if (!sym_eig(n, M.data(), w.data(), Y.data())) return false;
     for (int j = 0; j < m; j++) theta[j] = w[j];
-    for (int i = 0; i < n; i++)
-        for (int j = 0; j < m; j++) {
-            double s = 0.0;
-            for (int k = i; k < n; k++) s += Ri[i * n + k] * Y[k * n + j];
-            C[i * m + j] = s;
+    // C = Ri Y[:, :m]
+    for (int i = 0; i < n; i++) {
+        double *ci = C + size_t(i) * m;
+        for (int j = 0; j < m; j++) ci[j] = 0.0;
+        for (int k = i; k < n; k++) {
+            const double r = Ri[i * n + k];
+            const double *yk = Y.data() + size_t(k) * n;
+            for (int j = 0; j < m; j++) ci[j] += r * yk[j];
         }
+    }
     return true;
 }
 
