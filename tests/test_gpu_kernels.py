@@ -361,7 +361,10 @@ def update_reference(X, AX, W, AW, P, AP, C, theta, J, norm_A):
 UPDATE_SHAPES = [(5003, 32, 32, 32, 32, 32), (70001, 32, 20, 20, 20, 20), (4099, 32, 23, 23, 21, 23),
                  (777, 32, 32, 0, 32, 0), (3001, 12, 7, 5, 7, 5), (37, 12, 5, 5, 4, 5), (2049, 30, 17, 17, 15, 17),
                  (1000, 8, 5, 3, 5, 3), (3000, 48, 40, 40, 33, 40), (9001, 32, 21, 21, 21, 24),
-                 (4097, 32, 26, 26, 20, 31), (4097, 32, 13, 13, 13, 16)]
+                 (4097, 32, 26, 26, 20, 31), (4097, 32, 13, 13, 13, 16),
+                 # several 16-point groups per wave (the steady state of the
+                 # FP32 update's load pipeline), narrow and wide W and P
+                 (600011, 32, 13, 13, 11, 16), (600011, 32, 24, 24, 20, 28), (1200007, 16, 9, 9, 9, 12)]
 
 
 def update_inputs(N, m, nW, nP, nJ, ldP, npdt):
