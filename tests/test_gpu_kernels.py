@@ -194,7 +194,7 @@ def test_gram_fp64(N, widths, variant):
 @pytest.mark.parametrize("variant", [0, 4, 32, 48])
 @pytest.mark.parametrize("N,widths", [(4096, (8, 3, 3)), (70001, (32, 32, 32)), (5003, (5, 7, 2)),
                                       (99999, (32, 1, 1)), (77777, (2,)), (3001, (17, 9)), (129, (33,)),
-                                      (50021, (32, 31, 31))])
+                                      (50021, (32, 31, 31)), (1000003, (32, 16, 16))])
 def test_gram_fp32(N, widths, variant):
     ctx = ctx_for((N, 1, 1), 32, None, L.MIXED)
     L.lobpcg_set_option(ctx, L.OPT_KERNELS, variant)
