@@ -132,9 +132,9 @@ int lobpcg_solve(lobpcg_ctx *ctx, const lobpcg_op *A, const lobpcg_op *B, const 
                  double *h_hist, int *h_iters, double *h_final_resid);
 
 /* lobpcg_solve with constraints (hard locking, Section 2.3): the eigenpairs
- * are sought in the orthogonal complement of span(Y), imposed on X0 (step 2)
- * and on every preconditioned residual block (step 10) as
- * V - Y (Y^T Y)^-1 (Y^T V).
+ * are sought in the B-orthogonal complement of span(Y), imposed on X0 (step
+ * 2) and on every preconditioned residual block (step 10) as
+ * V - Y (Y^T B Y)^-1 (Y^T B V) (B = I without B).
  *   d_Y   N x ny FP64, point-major, full column rank, 1 <= ny <= 128,
  *         3m + ny <= N; caller-owned, read during the call only
  * As printed, step 7 does not project the residual: it goes to zero only when
@@ -142,10 +142,10 @@ int lobpcg_solve(lobpcg_ctx *ctx, const lobpcg_op *A, const lobpcg_op *B, const 
  * intended use: repeated calls with the converged X appended to Y give the
  * next eigenpairs).  In a MIXED context the FP32 iterations project their
  * residual blocks in FP64 (up-cast, project, down-cast) and the FP64 finish
- * applies step 2 again to the iterate it starts from.  Not with B (then
- * ERR_UNSUPPORTED); a rank-deficient Y (Cholesky of Y^T Y fails) gives
- * ERR_ARG.  Other arguments
- * and outputs as lobpcg_solve. */
+ * applies step 2 again to the iterate it starts from.  With B, B Y is formed
+ * once per call (in pieces of at most m columns) for Y^T B Y, and B V for
+ * every projected block.  A rank-deficient Y (Cholesky of Y^T B Y fails)
+ * gives ERR_ARG.  Other arguments and outputs as lobpcg_solve. */
 int lobpcg_solve_constrained(lobpcg_ctx *ctx, const lobpcg_op *A, const lobpcg_op *B, const lobpcg_precond *T,
                              const double *d_Y, int ny, const double *d_X0, int m, double tol, int maxit,
                              double *h_lambda, double *d_X, double *h_hist, int *h_iters,

@@ -938,10 +938,12 @@ std::vector<int> positions(const std::vector<int> &sub, const std::vector<int> &
     return pos;
 }
 
-// Steps 2 and 10 with B = I: dst = V - Y (Y^T Y)^-1 (Y^T V) for the N x k
-// block V (FP64).  Y^T V comes from the Gram kernel (Lm = Y, Rm = V), the
-// small solve runs on the host with the Cholesky factor of Y^T Y, and the
-// update is one multivector product [V Y] [I; -C].
+// Steps 2 and 10: dst = V - Y (Y^T B Y)^-1 (Y^T B V) for the N x k block V
+// (FP64; B = I unless the context has B).  Y^T (B V) comes from the Gram
+// kernel (Lm = Y, Rm = V or B V, the latter formed in the spare B-block BPJ,
+// which holds nothing between two updates), the small solve runs on the
+// host with the Cholesky factor of Y^T B Y, and the update is one
+// multivector product [V Y] [I; -C].
 int constrain64(lobpcg_ctx *c, const void *V, int k, void *dst, int step);
 
 // Steps 2 and 10 on a block of precision dt.  An FP32 block (the FP32 phase
@@ -967,11 +969,12 @@ int constrain(lobpcg_ctx *c, int dt, const void *V, int k, void *dst, int step)
     return e == hipSuccess ? LOBPCG_OK : LOBPCG_ERR_HIP;
 }
 
-int constrain64(lobpcg_ctx *c, const void *V, int k, void *dst, int step)
+// Y^T V (ny x k, row-major) for the N x k FP64 block V, in launches of at
+// most GX_MAX_L rows of Y
+int gram_Yt(lobpcg_ctx *c, const void *V, int k, std::vector<double> &G, int step)
 {
     const int ny = c->ny;
-    // Y^T V (ny x k) in launches of at most GX_MAX_L rows
-    std::vector<double> G((size_t)ny * k);
+    G.assign((size_t)ny * k, 0.0);
     for (int i0 = 0; i0 < ny; i0 += GX_MAX_L) {
         const int nr = std::min(GX_MAX_L, ny - i0);
         GramXArgs a;
@@ -1008,8 +1011,23 @@ int constrain64(lobpcg_ctx *c, const void *V, int k, void *dst, int step)
                 if (i < nr && j < k) G[(size_t)(i0 + i) * k + j] = h[(size_t)t * 256 + e];
             }
     }
-    if (!all_finite(G)) return LOBPCG_ERR_NONFINITE;
-    // C = (RY^T RY)^-1 G: forward then back substitution, column by column
+    return all_finite(G) ? LOBPCG_OK : LOBPCG_ERR_NONFINITE;
+}
+
+int constrain64(lobpcg_ctx *c, const void *V, int k, void *dst, int step)
+{
+    const int ny = c->ny;
+    const void *BV = V;
+    if (c->hasB) {
+        int s = apply_B(c, DT_F64, V, c->b64.BPJ, k, step);
+        if (s) return s;
+        BV = c->b64.BPJ;
+    }
+    std::vector<double> G;
+    int s = gram_Yt(c, BV, k, G, step);
+    if (s) return s;
+    // C = (RY^T RY)^-1 G (RY^T RY = Y^T B Y): forward then back substitution,
+    // column by column
     std::vector<double> C(G);
     for (int j = 0; j < k; j++) {
         for (int i = 0; i < ny; i++) {
@@ -1845,8 +1863,8 @@ static int solve_impl(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, con
         c->Bop = *B;
     }
     if (ny < 0 || ny > LOBPCG_MAX_M || (ny > 0 && !d_Y) || 3LL * m + ny > c->N) return LOBPCG_ERR_ARG;
-    // B != I: the folded form only, without constraints
-    if (B && (ny > 0 || !c->fold)) return LOBPCG_ERR_UNSUPPORTED;
+    // B != I: the folded form only
+    if (B && !c->fold) return LOBPCG_ERR_UNSUPPORTED;
     auto t0 = std::chrono::steady_clock::now();
     memset(&c->stats, 0, sizeof(c->stats));
     c->ev_used = 0;
@@ -1855,13 +1873,38 @@ static int solve_impl(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, con
     c->Y = ny ? d_Y : nullptr;
     c->ny = ny;
     if (ny) {
-        // the Cholesky factor of Y^T Y (Y must have full column rank)
+        // the Cholesky factor of Y^T B Y (Y must have full column rank)
         std::vector<double> G;
-        const void *Sb[1] = {d_Y};
-        int w1[1] = {ny};
-        int s0 = gram(c, DT_F64, 1, Sb, nullptr, w1, G, nullptr, LOBPCG_STEP_OTHER);
-        if (s0) return s0;
-        if (!all_finite(G)) return LOBPCG_ERR_NONFINITE;
+        if (c->hasB) {
+            // B Y in pieces of at most m columns: the piece of Y copied into
+            // the FP64 block W (free before the iterations), B applied into
+            // T0, then Y^T (B Y_piece)
+            G.assign((size_t)ny * ny, 0.0);
+            for (int j0 = 0; j0 < ny; j0 += m) {
+                const int kc = std::min(m, ny - j0);
+                std::vector<double> E((size_t)ny * kc, 0.0);
+                for (int j = 0; j < kc; j++) E[(size_t)(j0 + j) * kc + j] = 1.0;
+                MV q;
+                q.input(0, d_Y, nullptr, ny, ny);
+                q.kout = kc;
+                q.out[0] = c->b64.W;
+                int s0 = mv(c, DT_F64, q, E.data(), LOBPCG_STEP_OTHER);
+                if (s0) return s0;
+                s0 = apply_B(c, DT_F64, c->b64.W, c->b64.T0, kc, LOBPCG_STEP_OTHER);
+                if (s0) return s0;
+                std::vector<double> Gp;
+                s0 = gram_Yt(c, c->b64.T0, kc, Gp, LOBPCG_STEP_OTHER);
+                if (s0) return s0;
+                for (int i = 0; i < ny; i++)
+                    for (int j = 0; j < kc; j++) G[(size_t)i * ny + j0 + j] = Gp[(size_t)i * kc + j];
+            }
+        } else {
+            const void *Sb[1] = {d_Y};
+            int w1[1] = {ny};
+            int s0 = gram(c, DT_F64, 1, Sb, nullptr, w1, G, nullptr, LOBPCG_STEP_OTHER);
+            if (s0) return s0;
+            if (!all_finite(G)) return LOBPCG_ERR_NONFINITE;
+        }
         c->RY.assign((size_t)ny * ny, 0.0);
         if (!chol_scaled(ny, G.data(), c->RY.data())) return LOBPCG_ERR_ARG;
     }

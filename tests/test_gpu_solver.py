@@ -699,17 +699,73 @@ def test_scalar_B_scales_the_closed_form():
 
 
 def test_B_unsupported_combinations():
-    """B with constraints, or with the Cholesky-QR factors applied instead of
-    folded, is not provided."""
+    """B with the Cholesky-QR factors applied instead of folded is not
+    provided."""
     dims, m = (12, 10, 8), 3
     N = int(np.prod(dims))
     for Bd in (L.Diag(*dims, dev(lumped_mass(N, 1))), L.Mass7(*dims, 0.6, 1.0 / 12.0)):
         ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(None), m, L.FP64, B=Bd)
         X0 = dev(synth.x0_uniform(N, m))
-        r = L.lobpcg_solve(ctx, X0, 1e-8, 10, Y=dev(synth.random_block(N, 2, seed=3)), raise_on_error=False)
-        assert r.status == L.ERR_UNSUPPORTED
         L.lobpcg_set_option(ctx, L.OPT_FOLD_CHOLQR, 0)
         assert L.lobpcg_solve(ctx, X0, 1e-8, 10, raise_on_error=False).status == L.ERR_UNSUPPORTED
+        r = L.lobpcg_solve(ctx, X0, 1e-8, 10, Y=dev(synth.random_block(N, 2, seed=3)), raise_on_error=False)
+        assert r.status == L.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("prec", [L.FP64, L.MIXED])
+def test_diagonal_B_with_constraints_matches_dense_pencil(prec):
+    """Constraints with B = diag(d) (steps 2 and 10 B-orthogonal): Y spans the
+    B-eigenvectors 0 and 2 of the pencil (A, B) (randomly mixed; a dense
+    generalized eigensolve on 8 x 7 x 6 points); the solve finds eigenpairs 1,
+    3 and 4, as the oracle does, with X B-orthogonal to Y and B-orthonormal."""
+    dims, m, tol = (8, 7, 6), 3, 1e-9
+    N = int(np.prod(dims))
+    d = lumped_mass(N, 13)
+    A = grid.laplace7(dims, np.eye(N))
+    s = 1.0 / np.sqrt(d)
+    mu, Z = np.linalg.eigh(s[:, None] * A * s[None, :])
+    V = s[:, None] * Z                                  # B-orthonormal eigenvectors
+    assert np.all(np.diff(mu[:6]) > 1e-6)
+    Y = V[:, [0, 2]] @ np.random.default_rng(14).standard_normal((2, 2))
+    X0 = synth.x0_uniform(N, m, seed=6)
+    ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(None), m, prec, B=L.Diag(*dims, dev(d)))
+    r = L.lobpcg_solve(ctx, dev(X0), tol, 500, Y=dev(Y))
+    ref = olob.laplace7_solver(dims, m, X0, tol, 500, bdiag=d, Y=Y)
+    assert r.status == L.OK and ref.status == olob.OK
+    rt = 1e-9 if prec == L.FP64 else 1e-6
+    np.testing.assert_allclose(r.lam, mu[[1, 3, 4]], rtol=rt)
+    np.testing.assert_allclose(r.lam, ref.lam, rtol=rt)
+    assert r.resid.max() <= tol
+    X = r.X.cpu().numpy()
+    assert np.abs(Y.T @ (d[:, None] * X)).max() < 1e-9
+    np.testing.assert_allclose(X.T @ (d[:, None] * X), np.eye(m), atol=1e-10)
+    if prec == L.FP64:
+        assert abs(r.iters - ref.iters) <= 2, (r.iters, ref.iters)
+
+
+@pytest.mark.parametrize("prec", [L.FP64, L.MIXED])
+@pytest.mark.parametrize("ny", [3, 7])
+def test_mass7_B_with_constraints_gives_the_next_closed_form_pairs(prec, ny):
+    """Constraints with the 7-point mass-type B: the sine modes are the
+    B-eigenvectors too, so with Y spanning the ny smallest modes (randomly
+    mixed; 7 > m takes B Y in two pieces) the solve gives the next m
+    eigenvalues mu / (b0 + b1 (6 - mu)); X is B-orthogonal to Y and
+    B-orthonormal, every explicit residual <= tol."""
+    dims, m, levels, tol = (20, 18, 16), 5, 3, 1e-9 if prec == L.FP64 else 1e-8
+    b0, b1 = 1.0, -0.1
+    N = int(np.prod(dims))
+    mu, ijk = closed_form.smallest(*dims, ny + m)
+    Y = sine_block(dims, ijk[:ny]) @ np.random.default_rng(ny).standard_normal((ny, ny))
+    ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(levels), m, prec, B=L.Mass7(*dims, b0, b1))
+    r = L.lobpcg_solve(ctx, dev(synth.x0_uniform(N, m, seed=9)), tol, 300, Y=dev(Y))
+    assert r.status == L.OK
+    lam = mu[ny:] / (b0 + b1 * (6.0 - mu[ny:]))
+    np.testing.assert_allclose(r.lam, lam, rtol=1e-9 if prec == L.FP64 else 1e-6)
+    assert r.resid.max() <= tol
+    X = r.X.cpu().numpy()
+    BX = grid.mass7(dims, b0, b1, X)
+    assert np.abs(Y.T @ BX).max() < 1e-9 * np.abs(Y).max() * np.sqrt(N)
+    np.testing.assert_allclose(X.T @ BX, np.eye(m), atol=1e-10)
 
 
 @pytest.mark.parametrize("b0,b1", [(0.6, 1.0 / 12.0), (1.0, -0.1)])
