@@ -209,6 +209,13 @@ enum {
                                     /* columns; 0 (default) = m.  In the mixed solver  */
                                     /* the FP32 phase's switch and stall tests also    */
                                     /* look at the wanted columns only                 */
+    LOBPCG_OPT_FP32_EXPLICIT_ABOVE = 11,/* MIXED, with FP32_EXPLICIT_GRAM: an FP32       */
+                                    /* iteration takes the explicit form only while    */
+                                    /* more than this many columns are active, the     */
+                                    /* paper's form after (X then changes little per   */
+                                    /* iteration; the Gram step reads neither AX nor   */
+                                    /* the X-X tiles); default m/4 rounded down, 0:    */
+                                    /* always the explicit form                        */
     LOBPCG_OPT_FP64_EXPLICIT_GRAM = 8 /* 1: FP64 iterations compute the block diagonal */
                                     /* of gramB and X^T AX too (the variant Section    */
                                     /* 2.2 reports testing in MATLAB: better           */

@@ -177,7 +177,8 @@ struct lobpcg_ctx {
                                   // one has a Ritz value within this relative distance (0: off)
     int nwant;                    // the run ends once the first nwant columns have converged (0: m)
     int mv_frag, mg_unpadded, gram_staged, gram_nt4, gram_nt32, gram_direct;  // kernel variants (see LOBPCG_OPT_KERNELS)
-    bool fp32_explicit;           // FP32 phase: Gram diagonal blocks computed, not assumed
+    bool fp32_explicit;           // FP32 phase: Gram diagonal blocks computed, not assumed ...
+    int fp32_explicit_above;      // ... while more columns than this are active (-1: m / 4)
     bool fp64_explicit;           // the same for FP64 iterations
     bool fold;                    // Cholesky-QR factors of W_J, P_J folded into Gram and coefficients
     bool hasB;                    // A x = lambda B x with B = diag (FP64 only)
@@ -1290,6 +1291,15 @@ int folded_step(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState
     return LOBPCG_OK;
 }
 
+// An FP32 iteration with few active columns takes the paper's form of the
+// Gram matrices even where the explicit one is chosen: X then changes little
+// per iteration, and the Gram step reads neither AX nor the X-X tiles.
+bool narrow_fp32(const lobpcg_ctx *c, int dt, int nJ)
+{
+    const int above = c->fp32_explicit_above >= 0 ? c->fp32_explicit_above : c->m / 4;
+    return dt == DT_F32 && nJ <= above;
+}
+
 int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &ps, double tol, double normA,
               int maxit, int &iters, double *h_hist, bool explicit_gram, bool allow_switch, int &outcome)
 {
@@ -1394,7 +1404,8 @@ int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &
         }
         if (c->fold) {
             bool switched;
-            s = folded_step(c, A, dt, B, ps, Wt, nJ, explicit_gram, allow_switch, switched);
+            s = folded_step(c, A, dt, B, ps, Wt, nJ, explicit_gram && !narrow_fp32(c, dt, nJ), allow_switch,
+                            switched);
             if (s) return s;
             if (switched) {
                 outcome = PH_SWITCH;
@@ -1473,12 +1484,13 @@ int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &
         const void *Sb[3] = {B.X[ps.cur], B.W, B.PJ};
         const void *ASb[3] = {B.AX[ps.cur], B.AW, B.APJ};
         int wb[3] = {m, nJ, nP};
-        s = gram(c, dt, nb, Sb, ASb, wb, SS, &SAS, LOBPCG_STEP_GRAM, !explicit_gram);
+        const bool eg = explicit_gram && !narrow_fp32(c, dt, nJ);
+        s = gram(c, dt, nb, Sb, ASb, wb, SS, &SAS, LOBPCG_STEP_GRAM, !eg);
         if (s) return s;
         if (!all_finite(SS) || !all_finite(SAS)) return LOBPCG_ERR_NONFINITE;
         const int K = m + nJ + nP;
         std::vector<double> gA(SAS), gB(SS);
-        if (!explicit_gram) {
+        if (!eg) {
             // the paper's form: Lambda and identities on the block diagonal
             auto blk = [&](int i0, int n0, std::vector<double> &M, bool lam) {
                 for (int i = 0; i < n0; i++)
@@ -1762,6 +1774,7 @@ int lobpcg_setup(lobpcg_ctx **out, const lobpcg_op *A, const lobpcg_op *B, const
     c->gram_nt32 = 2;
     c->gram_direct = 0;
     c->fp32_explicit = true;
+    c->fp32_explicit_above = -1;
     c->fp64_explicit = false;
     c->fold = true;
     c->Y = nullptr;
@@ -1815,6 +1828,10 @@ int lobpcg_set_option(lobpcg_ctx *c, int key, double v)
         c->lock_gap = v;
         return LOBPCG_OK;
     case LOBPCG_OPT_FP32_EXPLICIT_GRAM: c->fp32_explicit = v != 0; return LOBPCG_OK;
+    case LOBPCG_OPT_FP32_EXPLICIT_ABOVE:
+        if (!(v >= 0.0 && v <= c->m) || v != std::floor(v)) return LOBPCG_ERR_ARG;
+        c->fp32_explicit_above = (int)v;
+        return LOBPCG_OK;
     case LOBPCG_OPT_FOLD_CHOLQR: c->fold = v != 0; return LOBPCG_OK;
     case LOBPCG_OPT_FP64_EXPLICIT_GRAM: c->fp64_explicit = v != 0; return LOBPCG_OK;
     case LOBPCG_OPT_KERNELS:

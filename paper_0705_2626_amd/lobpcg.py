@@ -27,6 +27,7 @@ OPT_FOLD_CHOLQR = 7
 OPT_FP64_EXPLICIT_GRAM = 8
 OPT_LOCK_GAP = 9
 OPT_NWANT = 10
+OPT_FP32_EXPLICIT_ABOVE = 11
 STEP_NAMES = ["residual", "precond", "ortho", "apply_A", "gram", "rr_host", "update", "other"]
 
 

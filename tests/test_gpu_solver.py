@@ -184,6 +184,28 @@ def test_mixed_precision_reaches_fp64_accuracy():
     assert r.resid.max() <= tol
 
 
+@pytest.mark.parametrize("above", [0, 2, 8, 16])
+def test_mixed_explicit_gram_threshold(above):
+    """The FP32 iterations' Gram form by active count (explicit while more
+    than `above` columns are active, the paper's form after; 0: always
+    explicit, 16 = m: never): every setting reaches the FP64 eigenpairs of
+    the closed form and every explicit residual <= tol.  Out-of-range values
+    are rejected."""
+    dims, m, levels, tol = (32, 30, 28), 16, 3, 1e-8
+    N = int(np.prod(dims))
+    ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(levels), m, L.MIXED)
+    L.lobpcg_set_option(ctx, L.OPT_FP32_EXPLICIT_ABOVE, above)
+    r = L.lobpcg_solve(ctx, dev(synth.x0_uniform(N, m, seed=3)), tol, 300)
+    st = L.lobpcg_get_stats(ctx)
+    exact, _ = closed_form.smallest(*dims, m)
+    assert r.status == L.OK and st["iters_fp32"] > 0
+    np.testing.assert_allclose(r.lam, exact, rtol=1e-9)
+    assert r.resid.max() <= tol
+    for v in (-1, m + 1, 2.5):
+        with pytest.raises(L.LobpcgError):
+            L.lobpcg_set_option(ctx, L.OPT_FP32_EXPLICIT_ABOVE, v)
+
+
 def test_mixed_precision_non_cubic_degenerate_edge():
     """m=10 on a cube cuts a degenerate eigenvalue group: values still right."""
     dims, m, levels, tol = (16, 16, 16), 10, 3, 1e-8
