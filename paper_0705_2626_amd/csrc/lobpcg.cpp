@@ -1413,12 +1413,20 @@ int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &
             }
             continue;
         }
-        // step 11: W_J = W_J R^-1 with R = chol(W_J^T W_J); the result goes to
-        // whichever of W / T0 does not hold the input
+        // step 11: W_J = W_J R^-1 with R = chol(W_J^T B W_J); the result goes
+        // to whichever of W / T0 does not hold the input (with B, B W_J is
+        // formed for the Gram matrix and again for the orthonormal W_J)
+        const bool hb = c->hasB;
         {
             const void *Sb[1] = {Wt};
+            const void *BSb[1] = {B.BW};
             int w1[1] = {nJ};
-            s = gram(c, dt, 1, Sb, nullptr, w1, SS, nullptr, LOBPCG_STEP_ORTHO);
+            if (hb) {
+                s = apply_B(c, dt, Wt, B.BW, nJ, LOBPCG_STEP_ORTHO);
+                if (s) return s;
+            }
+            s = gram(c, dt, 1, Sb, nullptr, w1, SS, nullptr, LOBPCG_STEP_ORTHO, false, nullptr, nullptr, false,
+                     hb ? BSb : nullptr);
             if (s) return s;
             std::vector<double> Ri;
             if (!all_finite(SS)) return LOBPCG_ERR_NONFINITE;
@@ -1438,9 +1446,13 @@ int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &
             if (s) return s;
             if (dst == B.T0) std::swap(B.W, B.T0);
         }
-        // step 12: AW_J = A W_J
+        // step 12: AW_J = A W_J (and B W_J)
         s = apply_A(c, A, dt, B.W, B.AW, nJ);
         if (s) return s;
+        if (hb) {
+            s = apply_B(c, dt, B.W, B.BW, nJ, LOBPCG_STEP_ORTHO);
+            if (s) return s;
+        }
         // steps 13-16: orthonormalise the directions of the active columns
         // that have one (P holds the columns ps.Pcols)
         std::vector<int> Jp, ppos;
@@ -1455,8 +1467,10 @@ int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &
         if (!Jp.empty()) {
             const int np = (int)ps.Pcols.size();
             const void *Sb[1] = {B.P};
+            const void *BSb[1] = {B.BP};
             int w1[1] = {np};
-            s = gram(c, dt, 1, Sb, nullptr, w1, PP, nullptr, LOBPCG_STEP_ORTHO);
+            s = gram(c, dt, 1, Sb, nullptr, w1, PP, nullptr, LOBPCG_STEP_ORTHO, false, nullptr, nullptr, false,
+                     hb ? BSb : nullptr);
             if (s) return s;
             const int k = (int)Jp.size();
             std::vector<double> G((size_t)k * k), Ri;
@@ -1474,6 +1488,14 @@ int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &
                 q.out[1] = B.APJ;
                 s = mv(c, dt, q, Ri.data(), LOBPCG_STEP_ORTHO);
                 if (s) return s;
+                if (hb) {
+                    MV qb;
+                    qb.input(0, B.BP, nullptr, np, k, dcols);
+                    qb.kout = k;
+                    qb.out[0] = B.BPJ;
+                    s = mv(c, dt, qb, Ri.data(), LOBPCG_STEP_ORTHO);
+                    if (s) return s;
+                }
                 nP = k;
             } else {
                 c->stats.restarts++;
@@ -1485,7 +1507,9 @@ int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &
         const void *ASb[3] = {B.AX[ps.cur], B.AW, B.APJ};
         int wb[3] = {m, nJ, nP};
         const bool eg = explicit_gram && !narrow_fp32(c, dt, nJ);
-        s = gram(c, dt, nb, Sb, ASb, wb, SS, &SAS, LOBPCG_STEP_GRAM, !eg);
+        const void *BSb[3] = {B.BX[ps.cur], B.BW, B.BPJ};
+        s = gram(c, dt, nb, Sb, ASb, wb, SS, &SAS, LOBPCG_STEP_GRAM, !eg, nullptr, nullptr, false,
+                 hb ? BSb : nullptr);
         if (s) return s;
         if (!all_finite(SS) || !all_finite(SAS)) return LOBPCG_ERR_NONFINITE;
         const int K = m + nJ + nP;
@@ -1546,15 +1570,36 @@ int run_phase(lobpcg_ctx *c, const lobpcg_op *A, int dt, Blocks &B, PhaseState &
         if (s) return s;
         MV q;
         q.nside = 2;
-        q.input(0, B.X[ps.cur], B.AX[ps.cur], m, m);
-        q.input(1, B.W, B.AW, nJ, nJ);
-        if (nP) q.input(2, B.PJ, B.APJ, nP, nP);
+        if (hb) {
+            // three sides, as in the folded step: X alone, then B X and A X
+            // with the residual W = AX' - BX' Theta
+            MV qx;
+            qx.input(0, B.X[ps.cur], nullptr, m, m);
+            qx.input(1, B.W, nullptr, nJ, nJ);
+            if (nP) qx.input(2, B.PJ, nullptr, nP, nP);
+            qx.kout = m;
+            qx.out[0] = B.P;
+            qx.opos = djpos;
+            qx.nout = nJ;
+            qx.out2[0] = B.X[1 - ps.cur];
+            s = mv(c, dt, qx, C.data(), LOBPCG_STEP_UPDATE);
+            if (s) return s;
+            q.input(0, B.BX[ps.cur], B.AX[ps.cur], m, m);
+            q.input(1, B.BW, B.AW, nJ, nJ);
+            if (nP) q.input(2, B.BPJ, B.APJ, nP, nP);
+            q.out[0] = B.BP;
+            q.out2[0] = B.BX[1 - ps.cur];
+        } else {
+            q.input(0, B.X[ps.cur], B.AX[ps.cur], m, m);
+            q.input(1, B.W, B.AW, nJ, nJ);
+            if (nP) q.input(2, B.PJ, B.APJ, nP, nP);
+            q.out[0] = B.P;
+            q.out2[0] = B.X[1 - ps.cur];
+        }
         q.kout = m;
-        q.out[0] = B.P;
         q.out[1] = B.AP;
         q.opos = djpos;
         q.nout = nJ;
-        q.out2[0] = B.X[1 - ps.cur];
         q.out2[1] = B.AX[1 - ps.cur];
         q.resid = true;
         q.theta = dtheta;
@@ -1880,8 +1925,6 @@ static int solve_impl(lobpcg_ctx *c, const lobpcg_op *A, const lobpcg_op *B, con
         c->Bop = *B;
     }
     if (ny < 0 || ny > LOBPCG_MAX_M || (ny > 0 && !d_Y) || 3LL * m + ny > c->N) return LOBPCG_ERR_ARG;
-    // B != I: the folded form only
-    if (B && !c->fold) return LOBPCG_ERR_UNSUPPORTED;
     auto t0 = std::chrono::steady_clock::now();
     memset(&c->stats, 0, sizeof(c->stats));
     c->ev_used = 0;

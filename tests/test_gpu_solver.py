@@ -720,18 +720,60 @@ def test_scalar_B_scales_the_closed_form():
     np.testing.assert_allclose(r.lam, exact / c, rtol=1e-9)
 
 
-def test_B_unsupported_combinations():
-    """B with the Cholesky-QR factors applied instead of folded is not
-    provided."""
+def test_B_adjoint_unsupported():
+    """The eigenvalue adjoint is defined for B = I only."""
     dims, m = (12, 10, 8), 3
     N = int(np.prod(dims))
-    for Bd in (L.Diag(*dims, dev(lumped_mass(N, 1))), L.Mass7(*dims, 0.6, 1.0 / 12.0)):
-        ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(None), m, L.FP64, B=Bd)
-        X0 = dev(synth.x0_uniform(N, m))
+    kx, ky, kz = synth.gaussian_field_faces(*dims, sigma=0.5, corr=4.0, seed=2)
+    ctx = L.lobpcg_setup(L.Op(*dims, dev(kx), dev(ky), dev(kz)), L.Precond(None), m, L.FP64,
+                         B=L.Diag(*dims, dev(lumped_mass(N, 1))))
+    with pytest.raises(L.LobpcgError) as e:
+        L.lobpcg_eig_grad_k(ctx, dev(synth.x0_uniform(N, m)), np.ones(m))
+    assert e.value.status == L.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("prec", [L.FP64, L.MIXED])
+@pytest.mark.parametrize("kind", ["diag", "mass7"])
+def test_B_applied_and_folded_cholqr_agree(kind, prec):
+    """With B, steps 11 and 14-15 as printed (R^-1 of W_J^T B W_J and
+    P_J^T B P_J applied to W_J, B W_J, P_J, A P_J and B P_J) and folded (the
+    default) give the oracle's eigenpairs, with X B-orthonormal and every
+    explicit residual <= tol; with the mass-type B also under constraints
+    (Y = the 3 smallest sine modes, B-eigenvectors: the next closed-form
+    pairs)."""
+    dims, m, levels, tol = (20, 18, 16), 6, 3, 1e-9 if prec == L.FP64 else 1e-8
+    N = int(np.prod(dims))
+    X0 = synth.x0_uniform(N, m, seed=8)
+    if kind == "diag":
+        d = lumped_mass(N, 21)
+        Bd, kw, Bapply = L.Diag(*dims, dev(d)), {"bdiag": d}, (lambda V: d[:, None] * V)
+    else:
+        b0, b1 = 0.6, 1.0 / 12.0
+        Bd, kw, Bapply = L.Mass7(*dims, b0, b1), {"bmass": (b0, b1)}, (lambda V: grid.mass7(dims, b0, b1, V))
+    ref = olob.laplace7_solver(dims, m, X0, tol, 300, levels=levels, **kw)
+    assert ref.status == olob.OK
+    rt = 5e-9 if prec == L.FP64 else 1e-6
+    iters = []
+    for fold in (0, 1):
+        ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(levels), m, prec, B=Bd)
+        L.lobpcg_set_option(ctx, L.OPT_FOLD_CHOLQR, fold)
+        r = L.lobpcg_solve(ctx, dev(X0), tol, 300)
+        assert r.status == L.OK and r.resid.max() <= tol
+        np.testing.assert_allclose(r.lam, ref.lam, rtol=rt)
+        X = r.X.cpu().numpy()
+        np.testing.assert_allclose(X.T @ Bapply(X), np.eye(m), atol=1e-10)
+        iters.append(r.iters)
+    if prec == L.FP64:
+        assert abs(iters[0] - iters[1]) <= 2, iters
+    if kind == "mass7":
+        mu, ijk = closed_form.smallest(*dims, m + 3)
+        Y = sine_block(dims, ijk[:3])
+        ctx = L.lobpcg_setup(L.Op(*dims), L.Precond(levels), m, prec, B=Bd)
         L.lobpcg_set_option(ctx, L.OPT_FOLD_CHOLQR, 0)
-        assert L.lobpcg_solve(ctx, X0, 1e-8, 10, raise_on_error=False).status == L.ERR_UNSUPPORTED
-        r = L.lobpcg_solve(ctx, X0, 1e-8, 10, Y=dev(synth.random_block(N, 2, seed=3)), raise_on_error=False)
-        assert r.status == L.ERR_UNSUPPORTED
+        r = L.lobpcg_solve(ctx, dev(synth.x0_uniform(N, m, seed=9)), tol, 300, Y=dev(Y))
+        assert r.status == L.OK and r.resid.max() <= tol
+        np.testing.assert_allclose(r.lam, mu[3:] / (b0 + b1 * (6.0 - mu[3:])), rtol=rt)
+        assert np.abs(Y.T @ Bapply(r.X.cpu().numpy())).max() < 1e-9 * np.sqrt(N)
 
 
 @pytest.mark.parametrize("prec", [L.FP64, L.MIXED])
