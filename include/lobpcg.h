@@ -152,8 +152,9 @@ int lobpcg_solve_constrained(lobpcg_ctx *ctx, const lobpcg_op *A, const lobpcg_o
                              double *h_final_resid);
 
 /* Hellmann-Feynman eigenvalue adjoint for VARCOEF7: for
- * lambda_i = (x_i, A x_i) / (x_i, x_i) and A = sum_f k_f (e_p - e_q)(e_p - e_q)^T,
- * d lambda_i / d k_f = (x_i[p] - x_i[q])^2 / (x_i, x_i).  Writes the
+ * lambda_i = (x_i, A x_i) / (x_i, B x_i) and A = sum_f k_f (e_p - e_q)(e_p - e_q)^T
+ * (B = I, or the context's B, which does not depend on k),
+ * d lambda_i / d k_f = (x_i[p] - x_i[q])^2 / (x_i, B x_i).  Writes the
  * vector-Jacobian product g_f = sum_i h_gbar[i] d lambda_i / d k_f into the
  * three device FP64 face arrays (shapes as in lobpcg_op).  d_X: N x m FP64. */
 int lobpcg_eig_grad_k(lobpcg_ctx *ctx, const double *d_X, const double *h_gbar, int m,

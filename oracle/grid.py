@@ -130,6 +130,18 @@ def eig_grad_faces(dims, X, gbar):
     return gkx, gky, gkz
 
 
+def eig_grad_faces_B(dims, X, gbar, BX):
+    """The face gradients for A x = lambda B x with B independent of k:
+    d lambda_i / d k_f = (x_i[p]-x_i[q])^2 / (x_i, B x_i), i.e. the sums of
+    eig_grad_faces with each weight gbar_i rescaled from (x_i, x_i) to
+    (x_i, B x_i).  BX: B applied to the columns of X."""
+    X = np.asarray(X, dtype=np.float64)
+    BX = np.asarray(BX, dtype=np.float64)
+    xx = np.einsum("pi,pi->i", X, X)
+    xbx = np.einsum("pi,pi->i", X, BX)
+    return eig_grad_faces(dims, X, np.asarray(gbar, dtype=np.float64) * xx / xbx)
+
+
 def coarsen(dims):
     """Grid of the next coarser level: each axis halves, rounding down."""
     return tuple(n // 2 for n in dims)

@@ -3,7 +3,8 @@
 EigSmallest maps the face coefficients k of -div(k grad u) to the m smallest
 eigenvalues, solving with LOBPCG (FP64) in the forward pass; the backward pass
 is one launch of the library's Hellmann-Feynman adjoint kernel,
-d lambda_i / d k_f = (x_i[p] - x_i[q])^2 / (x_i, x_i), contracted with the
+d lambda_i / d k_f = (x_i[p] - x_i[q])^2 / (x_i, B x_i) (B = I unless the
+solver context has a B, which does not depend on k), contracted with the
 incoming gradient.  The derivative is undefined where lambda_i is a multiple
 eigenvalue; a warning is raised when two returned eigenvalues are closer than
 1e-8 ||A||.

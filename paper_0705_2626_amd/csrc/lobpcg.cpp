@@ -2092,9 +2092,9 @@ int lobpcg_eig_grad_k(lobpcg_ctx *c, const double *d_X, const double *h_gbar, in
                       double *gkz)
 {
     if (!c || !d_X || !h_gbar || !gkx || !gky || !gkz || m < 1 || m > c->m) return LOBPCG_ERR_ARG;
-    if (c->hasB) return LOBPCG_ERR_UNSUPPORTED;
     // column norms (x_i, x_i) through the residual kernel with AX = X and
-    // lambda = 0; it works on blocks of the context's width, so a narrower X
+    // lambda = 0, or (x_i, B x_i) from the Gram kernel with B X in the spare
+    // B-block; both work on blocks of the context's width, so a narrower X
     // is first copied into zero-padded scratch
     std::vector<double> zero(c->m, 0.0), rr, xx;
     std::vector<int> none;
@@ -2106,8 +2106,21 @@ int lobpcg_eig_grad_k(lobpcg_ctx *c, const double *d_X, const double *h_gbar, in
                                 hipMemcpyDeviceToDevice, c->st));
         Xs = t;
     }
-    int s = residual(c, DT_F64, Xs, Xs, zero, none, nullptr, rr, xx);
-    if (s) return s;
+    int s;
+    if (c->hasB) {
+        s = apply_B(c, DT_F64, Xs, c->b64.BPJ, c->m, LOBPCG_STEP_OTHER);
+        if (s) return s;
+        std::vector<double> G;
+        const void *Sb[1] = {Xs}, *BSb[1] = {c->b64.BPJ};
+        int w1[1] = {c->m};
+        s = gram(c, DT_F64, 1, Sb, nullptr, w1, G, nullptr, LOBPCG_STEP_OTHER, false, nullptr, nullptr, false, BSb);
+        if (s) return s;
+        xx.assign(c->m, 0.0);
+        for (int i = 0; i < c->m; i++) xx[i] = G[(size_t)i * c->m + i];
+    } else {
+        s = residual(c, DT_F64, Xs, Xs, zero, none, nullptr, rr, xx);
+        if (s) return s;
+    }
     std::vector<double> w(c->m, 0.0);
     for (int i = 0; i < m; i++) {
         if (!(xx[i] > 0)) return LOBPCG_ERR_ARG;

@@ -439,6 +439,42 @@ def test_adjoint_matches_dense_finite_differences():
     np.testing.assert_allclose(gk, fd, rtol=1e-6, atol=1e-8)
 
 
+def test_adjoint_with_B_matches_dense_finite_differences():
+    """A(k) x = lambda B x with a fixed diagonal B (seeded, in [0.5, 2]): the
+    gradient (x_p - x_q)^2 / (x, B x) of eig_grad_faces_B against central
+    differences of the pencil's eigenvalues (dense, through the congruent
+    standard problem) in every face coefficient."""
+    dims = (3, 4, 3)
+    N = int(np.prod(dims))
+    kx, ky, kz = lognormal_faces(dims, 17)
+    d = np.random.default_rng(18).uniform(0.5, 2.0, N)
+    s = 1.0 / np.sqrt(d)
+    shapes = synth.face_shapes(*dims)
+    sizes = [int(np.prod(t)) for t in shapes]
+    kflat = np.concatenate([kx.ravel(), ky.ravel(), kz.ravel()])
+
+    def eigs(kf):
+        a, b, c = np.split(kf, np.cumsum(sizes)[:2])
+        A = dense_varcoef_by_faces(*dims, a.reshape(shapes[0]), b.reshape(shapes[1]), c.reshape(shapes[2]))
+        w, Z = np.linalg.eigh(s[:, None] * A * s[None, :])
+        return w, s[:, None] * Z
+
+    w, V = eigs(kflat)
+    X = V[:, :3] * np.array([1.0, -2.5, 0.3])        # not B-normalised: the formula divides by (x, B x)
+    gbar = np.array([0.7, -1.3, 0.4])
+    gk = np.concatenate([a.ravel() for a in grid.eig_grad_faces_B(dims, X, gbar, d[:, None] * X)])
+    h = 1e-6
+    fd = np.empty_like(kflat)
+    for f in range(kflat.size):
+        kp, km = kflat.copy(), kflat.copy()
+        kp[f] += h; km[f] -= h
+        fd[f] = gbar @ (eigs(kp)[0][:3] - eigs(km)[0][:3]) / (2 * h)
+    np.testing.assert_allclose(gk, fd, rtol=1e-6, atol=1e-8)
+    # with B = I it is eig_grad_faces
+    for a, b in zip(grid.eig_grad_faces_B(dims, X, gbar, X), grid.eig_grad_faces(dims, X, gbar)):
+        np.testing.assert_allclose(a, b, rtol=1e-14, atol=0)
+
+
 def test_adjoint_scale_invariance():
     """lambda(c k) = c lambda(k), so the gradient does not change under k -> c k."""
     dims = (5, 5, 6)
