@@ -181,7 +181,7 @@ struct lobpcg_ctx {
     int fp32_explicit_above;      // ... while more columns than this are active (-1: m / 4)
     bool fp64_explicit;           // the same for FP64 iterations
     bool fold;                    // Cholesky-QR factors of W_J, P_J folded into Gram and coefficients
-    bool hasB;                    // A x = lambda B x with B = diag (FP64 only)
+    bool hasB;                    // A x = lambda B x (B: Bop, a positive diagonal or the mass-type stencil)
     lobpcg_op Bop;
     const double *Y;              // constraints of the current solve (FP64, N x ny) or null
     int ny;
