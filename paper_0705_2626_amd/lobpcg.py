@@ -223,7 +223,7 @@ class Context:
 
 
 def lobpcg_setup(A, T, m, precision=FP64, device="cuda", stream=None, B=None):
-    """Context for A x = lambda x, or A x = lambda B x with B a Diag (FP64)."""
+    """Context for A x = lambda x, or A x = lambda B x with B a Diag or a Mass7 (FP64 or mixed)."""
     return Context(A, T, m, precision, device, stream, B)
 
 
