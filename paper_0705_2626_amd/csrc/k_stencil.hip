@@ -335,7 +335,8 @@ static hipError_t run_stencil(const Grid3 &g, int k, const void *u, void *out, c
         if (product && k < 16) launch(std::integral_constant<int, 2>(), 8192);
         else launch(std::integral_constant<int, 4>(), product ? 4096 : 8192);
     } else {
-        if (product) launch(std::integral_constant<int, 2>(), 8192);
+        // the two sweeps from zero read one block, as a product does
+        if (product || EPI == EPI_JACOBI2) launch(std::integral_constant<int, 2>(), 8192);
         else launch(std::integral_constant<int, 1>(), 2048);
     }
     return hipGetLastError();
@@ -405,16 +406,17 @@ hipError_t launch_resid7(int dtype, const Grid3 &g, int k, const void *x, const 
 // (precision T, k = L V columns per point): the right-hand side u is read
 // as stored (type TU, kc <= k columns) and its copy in the cycle's layout
 // written to ucopy; the result is written as stored (type TO, kc columns).
-// Shapes of the sweeps above: one row per thread for FP32, four for FP64.
+// Shapes of the sweeps above: one row per thread for FP32 (two for the
+// sweeps from zero, which read one block), four for FP64.
 template <typename T, int V, int EPI, typename TU, typename TO, bool CIN, bool COUT>
 static hipError_t run_edge_sweep(const Grid3 &g, int kc, int k, const void *u, void *out, const void *b, T *ucopy,
                                  double s, double c1, hipStream_t st)
 {
     const int L = k / V;
-    constexpr int R = sizeof(T) == 4 ? 1 : 4;
+    constexpr int R = sizeof(T) == 4 ? (EPI == EPI_JACOBI2 ? 2 : 1) : 4;
     dim3 grid;
     int zchunk;
-    geometry(g.nx, (g.ny + R - 1) / R, g.nz, L, grid, zchunk, sizeof(T) == 4 ? 2048 : 8192);
+    geometry(g.nx, (g.ny + R - 1) / R, g.nz, L, grid, zchunk, sizeof(T) == 4 && R == 1 ? 2048 : 8192);
     hipLaunchKernelGGL((stencil7_kernel<T, V, EPI, R, TU, TO, CIN, COUT>), grid, dim3(256), 0, st, g.nx, g.ny, g.nz,
                        L, zchunk, (const TU *)u, (TO *)out, (const T *)b, (T)s, (T)c1, ucopy, kc);
     return hipGetLastError();
