@@ -54,8 +54,8 @@ HBM_PEAK_GBPS = 8000.0
 # two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB copy;
 # valid only while the kernel source is the one the counters were taken with.
 TRAFFIC = {
-    "update": {"bytes_per_launch": 16.764e9, "source": "paper_0705_2626_amd/csrc/k_update.hip",
-               "sha1": "fd885da565cd8167f25f10e94dc0a99e10cd68b3", "profile": "profiles/lobpcg_mixed_n256_m32_hbm_traffic.md"},
+    "update": {"bytes_per_launch": 16.763e9, "source": "paper_0705_2626_amd/csrc/k_update.hip",
+               "sha1": "69c451f26724be4d2374ccf4b5c094a6fd724539", "profile": "profiles/lobpcg_mixed_n256_m32_hbm_traffic.md"},
 }
 
 

@@ -189,7 +189,10 @@ enum {
                                     /* loaded per tile group rather than staged once   */
                                     /* per row chunk through LDS (bits 3-4 apply to    */
                                     /* that kernel and to products with more operand   */
-                                    /* blocks than the LDS-staged kernel holds)        */
+                                    /* blocks than the LDS-staged kernel holds); bit   */
+                                    /* 6: the LDS-pipelined update stores P, AP and W  */
+                                    /* per MFMA fragment also when they have at most   */
+                                    /* 16 columns (default: as compact rows)           */
     LOBPCG_OPT_FP32_EXPLICIT_GRAM = 6,/* MIXED: 1 (default) FP32 iterations compute   */
                                     /* X^T X, X^T AX, W^T W, P^T P rather than taking  */
                                     /* I and Lambda for them as the paper's form does  */

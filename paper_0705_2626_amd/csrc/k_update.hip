@@ -453,13 +453,20 @@ __device__ __forceinline__ void mvl_wait_vm()
 __device__ __forceinline__ void mvl_wait_lds() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
 static const int MVL_SLOT = 16 * 32;   // floats of one input's 16 rows (at most 32 columns)
-static const int MVL_ST0 = 10;         // store instructions per side: P (8) and X' (2)
 static const int MVL_CMAP = 128;       // column-list entries (3 inputs of at most 32 columns, 16-byte multiple)
-static const int MVL_ST1 = 18;         // AP (8), W (8) and AX' (2)
 
-template <int NIN>
+// SW = 0: P, AP and W leave the MFMA accumulators directly, one 4-byte store
+// per 4-row x 16-column fragment (8 per output).  SW = 1, 2 or 4: they have at
+// most 4 SW stored columns and leave through the wave's LDS tile as compact
+// rows, SW 4-byte stores per output (16 rows x 4 SW columns = 64 SW values):
+// with few active columns the fragment stores are mostly dropped lanes, and
+// their instructions, not their bytes, cost the time.
+template <int NIN, int SW>
 __global__ void __launch_bounds__(256) mvl_kernel(MVDev<float> a)
 {
+    // store instructions per side: P and X' (2), then AP, W and AX' (2)
+    constexpr int SO = SW > 0 ? SW : 8;
+    constexpr int MVL_ST0 = SO + 2, MVL_ST1 = 2 * SO + 2;
     typedef float T;
     typedef floatx4 accT;
     const int NT = 2, NC = 32;
@@ -502,6 +509,29 @@ __global__ void __launch_bounds__(256) mvl_kernel(MVDev<float> a)
         if (a.cols[b])
             for (int r = tid; r < a.k[b]; r += blockDim.x) cmap[roffs[b] + r] = a.cols[b][r];
     __syncthreads();
+
+    // SW > 0: value e = 64 i + lane of a compact P / AP (W) row block of a
+    // 16-point group, row e / nout and stored column q = e mod nout, comes
+    // from the tile column c with opos[c] = q (wpos[c] = q); -1 where no
+    // column is stored there (then nothing is written, as with SW = 0)
+    int ptile[SW > 0 ? SW : 1], wtile[SW > 0 ? SW : 1];
+    if constexpr (SW > 0) {
+#pragma unroll
+        for (int i = 0; i < SW; i++) {
+            const int e = 64 * i + lane;
+            ptile[i] = wtile[i] = -1;
+            if (e < 16 * a.nout) {
+                const int row = e / a.nout, q = e - row * a.nout;
+                for (int c = 0; c < NC; c++)
+                    if (opos[c] == q) ptile[i] = row * (NC + 4) + c;
+            }
+            if (e < 16 * a.nW) {
+                const int row = e / a.nW, q = e - row * a.nW;
+                for (int c = 0; c < NC; c++)
+                    if (wpos[c] == q) wtile[i] = row * (NC + 4) + c;
+            }
+        }
+    }
 
     // per input: the byte offset each lane fetches for DMA instruction j (two
     // per input, 64 lanes x 16 bytes each).  Rows of a multiple of 4 columns
@@ -597,6 +627,25 @@ __global__ void __launch_bounds__(256) mvl_kernel(MVDev<float> a)
     for (int nt = 0; nt < NT; nt++) sr[nt] = sx[nt] = 0.0;
     accT keepX[NT];
     T *st = stage + wave * 16 * (NC + 4);
+    // an MFMA result into this wave's tile (row-major, NC + 4 floats a row)
+    auto to_tile = [&](const accT(&v)[NT]) {
+#pragma unroll
+        for (int rr = 0; rr < 4; rr++)
+#pragma unroll
+            for (int nt = 0; nt < NT; nt++) st[Mfma<T>::row(lane, rr) * (NC + 4) + 16 * nt + lr] = v[nt][rr];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    };
+    // the compact rows from the tile: value 64 i + lane of the group's block
+    // (rows past N fall outside the buffer's range and are dropped); the tile
+    // is private to this wave and LDS operations of one wave complete in order
+    auto compact_store = [&](mvl_v4i r, const int(&tl)[SW > 0 ? SW : 1]) {
+#pragma unroll
+        for (int i = 0; i < SW; i++) {
+            const T v = st[tl[i] >= 0 ? tl[i] : 0];
+            mvl_st1(r, tl[i] >= 0 ? (unsigned)((64 * i + lane) * 4) : MVL_OOB, v);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    };
     if (Tn > 0) issue(0);
     if (Tn > 1) issue(1);
     for (int t = 0; t < Tn; t++) {
@@ -625,20 +674,26 @@ __global__ void __launch_bounds__(256) mvl_kernel(MVDev<float> a)
         // P (side 0) or AP (side 1) in the active columns
         {
             const mvl_v4i r = mvl_rsrc(a.out[s] + p0 * a.nout, (unsigned)(nrows * a.nout * 4));
+            if constexpr (SW > 0) {
+                to_tile(acc);
+                compact_store(r, ptile);
+            } else {
 #pragma unroll
-            for (int rr = 0; rr < 4; rr++)
+                for (int rr = 0; rr < 4; rr++)
 #pragma unroll
-                for (int nt = 0; nt < NT; nt++) {
-                    const int q = opos[16 * nt + lr];
-                    const int row = Mfma<T>::row(lane, rr);
-                    mvl_st1(r, q >= 0 ? (unsigned)((row * a.nout + q) * 4) : MVL_OOB, acc[nt][rr]);
-                }
+                    for (int nt = 0; nt < NT; nt++) {
+                        const int q = opos[16 * nt + lr];
+                        const int row = Mfma<T>::row(lane, rr);
+                        mvl_st1(r, q >= 0 ? (unsigned)((row * a.nout + q) * 4) : MVL_OOB, acc[nt][rr]);
+                    }
+            }
         }
         mma_in(acc, av[0], 0);
         // side 1: the residual W = AX' - X' Theta in the active columns and
         // the column sums of squares of step 8
         if (s == 1) {
             const mvl_v4i r = mvl_rsrc(a.Wout + p0 * a.nW, (unsigned)(nrows * a.nW * 4));
+            accT wv[NT];
 #pragma unroll
             for (int rr = 0; rr < 4; rr++)
 #pragma unroll
@@ -650,9 +705,17 @@ __global__ void __launch_bounds__(256) mvl_kernel(MVDev<float> a)
                         sr[nt] += rv * rv;
                         sx[nt] += x * x;
                     }
-                    const int w = wpos[c];
-                    mvl_st1(r, w >= 0 ? (unsigned)((row * a.nW + w) * 4) : MVL_OOB, (T)rv);
+                    if constexpr (SW > 0) {
+                        wv[nt][rr] = (T)rv;
+                    } else {
+                        const int w = wpos[c];
+                        mvl_st1(r, w >= 0 ? (unsigned)((row * a.nW + w) * 4) : MVL_OOB, (T)rv);
+                    }
                 }
+            if constexpr (SW > 0) {
+                to_tile(wv);
+                compact_store(r, wtile);
+            }
         } else {
 #pragma unroll
             for (int nt = 0; nt < NT; nt++) keepX[nt] = acc[nt];
@@ -1028,10 +1091,22 @@ static hipError_t run_mvl(const MVArgs &h, hipStream_t st)
     int nsteps = 0;
     for (int b = 0; b < h.nin; b++) nsteps += mvf_k4(h.k[b], h.ld[b], h.cols[b] != nullptr, 4);
     const size_t shm = mvl_lds_bytes(h.nin, nsteps);
-    if (h.nin == 3)
-        hipLaunchKernelGGL((mvl_kernel<3>), dim3(nb), dim3(256), shm, st, a);
-    else
-        hipLaunchKernelGGL((mvl_kernel<2>), dim3(nb), dim3(256), shm, st, a);
+    // P / AP and W with at most 16 stored columns: compact stores (SW of them)
+    const int nst = h.nout > h.nW ? h.nout : h.nW;
+    const int sw = h.mvl_fragment_stores ? 0 : nst <= 4 ? 1 : nst <= 8 ? 2 : nst <= 16 ? 4 : 0;
+#define MVL_LAUNCH(NIN, SW) hipLaunchKernelGGL((mvl_kernel<NIN, SW>), dim3(nb), dim3(256), shm, st, a)
+    if (h.nin == 3) {
+        if (sw == 1) MVL_LAUNCH(3, 1);
+        else if (sw == 2) MVL_LAUNCH(3, 2);
+        else if (sw == 4) MVL_LAUNCH(3, 4);
+        else MVL_LAUNCH(3, 0);
+    } else {
+        if (sw == 1) MVL_LAUNCH(2, 1);
+        else if (sw == 2) MVL_LAUNCH(2, 2);
+        else if (sw == 4) MVL_LAUNCH(2, 4);
+        else MVL_LAUNCH(2, 0);
+    }
+#undef MVL_LAUNCH
     return mv_reduce(h, nb, st);
 }
 

@@ -100,6 +100,7 @@ struct MVArgs {
     double *sums;           // [2 kout]
     long long N;
     int frag_only = 0;      // 1: the FP32 update on mvf_kernel even where the LDS-pipelined kernel applies
+    int mvl_fragment_stores = 0;  // 1: that kernel stores P, AP and W per MFMA fragment also for few columns
 };
 int mv_blocks(long long N);
 hipError_t launch_mv(int dtype, const MVArgs &a, hipStream_t st);

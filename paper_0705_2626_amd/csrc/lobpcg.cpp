@@ -176,7 +176,7 @@ struct lobpcg_ctx {
     double lock_gap;              // soft locking keeps a converged column active while an unconverged
                                   // one has a Ritz value within this relative distance (0: off)
     int nwant;                    // the run ends once the first nwant columns have converged (0: m)
-    int mv_frag, mg_unpadded, gram_staged, gram_nt4, gram_nt32, gram_direct;  // kernel variants (see LOBPCG_OPT_KERNELS)
+    int mv_frag, mg_unpadded, gram_staged, gram_nt4, gram_nt32, gram_direct, mv_fragst;  // kernel variants (see LOBPCG_OPT_KERNELS)
     bool fp32_explicit;           // FP32 phase: Gram diagonal blocks computed, not assumed ...
     int fp32_explicit_above;      // ... while more columns than this are active (-1: m / 4)
     bool fp64_explicit;           // the same for FP64 iterations
@@ -565,6 +565,7 @@ int mv(lobpcg_ctx *c, int dt, const MV &q, const double *C, int step)
     };
     MVArgs a;
     a.frag_only = c->mv_frag;
+    a.mvl_fragment_stores = c->mv_fragst;
     a.nside = q.nside;
     a.N = c->N;
     a.partials = q.resid ? c->d_mv_part : nullptr;
@@ -1818,6 +1819,7 @@ int lobpcg_setup(lobpcg_ctx **out, const lobpcg_op *A, const lobpcg_op *B, const
     c->gram_nt4 = 0;
     c->gram_nt32 = 2;
     c->gram_direct = 0;
+    c->mv_fragst = 0;
     c->fp32_explicit = true;
     c->fp32_explicit_above = -1;
     c->fp64_explicit = false;
@@ -1880,13 +1882,14 @@ int lobpcg_set_option(lobpcg_ctx *c, int key, double v)
     case LOBPCG_OPT_FOLD_CHOLQR: c->fold = v != 0; return LOBPCG_OK;
     case LOBPCG_OPT_FP64_EXPLICIT_GRAM: c->fp64_explicit = v != 0; return LOBPCG_OK;
     case LOBPCG_OPT_KERNELS:
-        if (v < 0 || v > 63) return LOBPCG_ERR_ARG;
+        if (v < 0 || v > 127) return LOBPCG_ERR_ARG;
         c->mv_frag = ((int)v & 1) != 0;
         c->mg_unpadded = ((int)v & 2) != 0;
         c->gram_staged = ((int)v & 4) != 0;
         c->gram_nt4 = ((int)v & 8) != 0;
         c->gram_nt32 = ((int)v & 16) ? 4 : 2;
         c->gram_direct = ((int)v & 32) != 0;
+        c->mv_fragst = ((int)v & 64) != 0;
         return LOBPCG_OK;
     default: return LOBPCG_ERR_ARG;
     }

@@ -364,7 +364,10 @@ UPDATE_SHAPES = [(5003, 32, 32, 32, 32, 32), (70001, 32, 20, 20, 20, 20), (4099,
                  (4097, 32, 26, 26, 20, 31), (4097, 32, 13, 13, 13, 16),
                  # several 16-point groups per wave (the steady state of the
                  # FP32 update's load pipeline), narrow and wide W and P
-                 (600011, 32, 13, 13, 11, 16), (600011, 32, 24, 24, 20, 28), (1200007, 16, 9, 9, 9, 12)]
+                 (600011, 32, 13, 13, 11, 16), (600011, 32, 24, 24, 20, 28), (1200007, 16, 9, 9, 9, 12),
+                 # few active columns (P, AP and W leave as compact rows)
+                 (600011, 32, 1, 1, 1, 1), (70001, 32, 3, 3, 3, 8), (600011, 32, 6, 6, 6, 6),
+                 (4099, 16, 2, 0, 2, 0), (1003, 20, 4, 2, 3, 4)]
 
 
 def update_inputs(N, m, nW, nP, nJ, ldP, npdt):
@@ -408,18 +411,20 @@ def test_update(N, m, nW, nP, nJ, ldP, prec):
 
 @pytest.mark.parametrize("N,m,nW,nP,nJ,ldP", [s for s in UPDATE_SHAPES if s[1] % 4 == 0 and 8 < s[1] <= 32])
 def test_update_kernels_agree(N, m, nW, nP, nJ, ldP):
-    """The LDS-pipelined FP32 update and the fragment kernel (kernel variant
-    bit 0) take the same products in the same order: identical blocks."""
+    """The LDS-pipelined FP32 update, the same with P, AP and W stored per
+    MFMA fragment (kernel variant bit 6) and the fragment kernel (bit 0) take
+    the same products in the same order: identical blocks."""
     X, AX, W, AW, P, AP, Pcols, C, theta, J = update_inputs(N, m, nW, nP, nJ, ldP, np.float32)
     d = lambda a: dev(a, torch.float32) if a is not None else None
     res = []
-    for v in (0, 1):
+    for v in (0, 1, 64):
         ctx = L.lobpcg_setup(L.Op(N, 1, 1), L.Precond(None), m, L.MIXED)
         L.lobpcg_set_option(ctx, L.OPT_KERNELS, v)
         res.append(L.lobpcg_update(ctx, d(X), d(AX), d(W), d(AW), d(P), d(AP), C, theta, J, 12.0, Pcols=Pcols))
-    for a, b in zip(res[0][:5], res[1][:5]):
-        assert torch.equal(a, b)
-    np.testing.assert_allclose(res[0][5], res[1][5], rtol=1e-13)
+    for r in res[1:]:
+        for a, b in zip(res[0][:5], r[:5]):
+            assert torch.equal(a, b)
+        np.testing.assert_allclose(res[0][5], r[5], rtol=1e-13)
 
 
 def test_update_argument_errors():

@@ -372,12 +372,12 @@ def test_error_paths():
     assert r.status == L.NOT_CONVERGED and r.iters == 2
     with pytest.raises(L.LobpcgError):
         L.lobpcg_solve(ctx, dev(synth.x0_uniform(N, m)), -1.0, 10)
-    for v in (64, -4, 1000):        # out of range
+    for v in (128, -4, 1000):       # out of range
         with pytest.raises(L.LobpcgError):
             L.lobpcg_set_option(ctx, L.OPT_KERNELS, v)
 
 
-@pytest.mark.parametrize("variant,prec", [(4, L.FP64), (8, L.FP64), (32, L.FP64), (1, L.MIXED)])
+@pytest.mark.parametrize("variant,prec", [(4, L.FP64), (8, L.FP64), (32, L.FP64), (1, L.MIXED), (64, L.MIXED)])
 @pytest.mark.parametrize("m", [6, 12])
 def test_kernel_variants_give_the_same_solution(variant, prec, m):
     """The default Gram and update kernels and the other variants agree."""
